@@ -1,0 +1,218 @@
+/*
+ * fastcount.h -- C ABI of the MI355X (gfx950) exact counting library.
+ *
+ * Method: Karan, Eichhorn, Hurlburt, Iraci, Zola, "Fast Counting in Machine
+ * Learning Applications" (UAI 2018, arXiv 1804.04640).
+ *
+ * Data model (Section 2).  A complete categorical database D of n variables
+ * and m instances; variable v has arity r_v in 1..255 and every instance
+ * holds a state 0 <= s < r_v (the paper numbers states 1..r_v; state s here
+ * is the paper's s+1).  A query is an ordered list of k distinct variables,
+ * 1 <= k <= FC_MAX_VARS.  Query(X_i, Pa) of Sections 3.1-3.3 is the list
+ * Pa ++ [X_i]: the child is the last variable.
+ *
+ * Dense table layout.  The contingency table of a query has prod r_v cells
+ * (q_i * r_i, Section 2), int32, mixed-radix with vars[0] the most
+ * significant digit and the child the least significant one (the MSD digit
+ * order of Section 3.3):
+ *     idx = ((s_0 * r_1 + s_1) * r_2 + ...) * r_{k-1} + s_{k-1}
+ * so row j (one parent configuration) is the contiguous slice
+ * [j * r_i, (j + 1) * r_i).
+ *
+ * Pointers.  Query descriptions (vars, var_off, table_off, items, states)
+ * are host memory.  Output buffers (tables, scores, err, gram, pair records)
+ * may be device memory (for example a torch tensor's data_ptr) or host
+ * memory; the library tells them apart with hipPointerGetAttributes.  With
+ * device outputs a call is asynchronous on `stream` (a hipStream_t; NULL is
+ * the null stream); with host outputs it returns after the results are in
+ * place.  Every output buffer is owned by the caller.
+ *
+ * Errors.  Every int-returning call returns FC_OK (0) or a negative FC_ERR_*
+ * code and never aborts.  A batch is validated as a whole before anything
+ * is launched, so a rejected call has no effect; fc_last_error() then holds
+ * a message (per host thread) that names the first offending query index.
+ *
+ * Threads.  An fc_db is immutable once created.  Calls on one fc_db from
+ * several host threads, each on its own stream, may run concurrently: every
+ * call owns its scratch memory (the independent function objects of
+ * Section 3.1).
+ */
+#ifndef FASTCOUNT_H
+#define FASTCOUNT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fc_db fc_db;
+
+/* Status codes. */
+#define FC_OK 0
+#define FC_ERR_INVALID (-1) /* malformed argument or query            */
+#define FC_ERR_RANGE (-2)   /* a size beyond what the library handles  */
+#define FC_ERR_NOMEM (-3)   /* device or pinned host allocation failed */
+#define FC_ERR_DEVICE (-4)  /* a HIP runtime call failed               */
+
+#define FC_MAX_VARS 8
+
+/* fc_db_create layouts. */
+#define FC_COL_MAJOR 0 /* data[v * m + p]: n columns of m states       */
+#define FC_ROW_MAJOR 1 /* data[p * n + v]: m instances of n states     */
+
+/* fc_db_create flags. */
+#define FC_DB_BITVECTORS 1u     /* also build per-state bit-vectors        */
+#define FC_DB_DATA_ON_DEVICE 2u /* `data` is a device pointer              */
+
+/* Strategy field of the batch flags (low 4 bits). */
+#define FC_STRAT_AUTO 0u      /* per-query choice by the cost model / tuner */
+#define FC_STRAT_HIST 1u      /* joint key + LDS histogram (Section 3.3)    */
+#define FC_STRAT_BITMAP 2u    /* AND of bit-vectors + popcount (Sec. 3.2)   */
+#define FC_STRAT_PARTITION 3u /* MSD partition by the top key digits, each  */
+                              /* part counted in LDS (Section 3.3)          */
+#define FC_STRAT_SORT FC_STRAT_PARTITION
+#define FC_STRAT_MASK 0xFu
+#define FC_NO_GRAPH 0x10u     /* launch directly, never through a hipGraph  */
+
+/* Reducers (bit mask; several may be fused into one counting pass). */
+#define FC_RED_LL 1u   /* log-likelihood of Eq. (1), bits (Fig. 2)          */
+#define FC_RED_MDL 2u  /* -LL + 1/2 log2(m) q (r-1), bits, minimised        */
+#define FC_RED_BDEU 4u /* BDeu log marginal likelihood, nats, maximised     */
+#define FC_RED_MI 8u   /* mutual information child ; parents, nats          */
+
+typedef struct fc_reduce_params {
+    double ess; /* BDeu equivalent sample size alpha (> 0); 1.0 if NULL */
+} fc_reduce_params;
+
+typedef struct fc_pair_rec {
+    int32_t a, b;     /* item indices into the `items` list, a < b     */
+    int32_t n_ab;     /* Count(X_a = 1 AND X_b = 1)                     */
+    float support;    /* n_ab / m                                       */
+    float conf_ab;    /* n_ab / Count(X_a = 1): confidence of a => b    */
+    float conf_ba;    /* n_ab / Count(X_b = 1): confidence of b => a    */
+} fc_pair_rec;
+
+/*
+ * Make D resident on the current HIP device (Section 2 database; the
+ * column-major layout and precomputed per-variable partitions of Section
+ * 3.3; the per-state bitmaps of Section 3.2 when FC_DB_BITVECTORS is set).
+ *
+ * data    n*m states, FC_COL_MAJOR or FC_ROW_MAJOR; host memory unless
+ *         FC_DB_DATA_ON_DEVICE.  The caller keeps ownership; it is copied.
+ * m       instances, 0 <= m < 2^31 (counts are int32).
+ * n       variables, n >= 1.
+ * arity   host array of n arities, each 1..255.
+ * stream  stream for the upload and preprocessing kernels; the call
+ *         synchronises it before returning.
+ * out     receives the handle.
+ * Fails with FC_ERR_INVALID on a bad argument or when a state is not below
+ * its variable's arity (the database must be complete), FC_ERR_RANGE when
+ * m >= 2^31, FC_ERR_NOMEM when device memory runs out.
+ */
+int fc_db_create(const uint8_t *data, int64_t m, int32_t n,
+                 const uint8_t *arity, int32_t layout, uint32_t flags,
+                 void *stream, fc_db **out);
+
+/* Free every device and host resource of the handle (NULL is a no-op). */
+void fc_db_destroy(fc_db *db);
+
+/*
+ * Database facts: instances, variables, whether bit-vectors exist, and the
+ * device bytes held.  Any output pointer may be NULL.
+ */
+int fc_db_info(const fc_db *db, int64_t *m, int32_t *n, int32_t *has_bits,
+               int64_t *device_bytes);
+
+/*
+ * Host copies of the per-variable marginal counts (sum of arities int64
+ * values, variable-major) and entropies in bits (n floats), computed on the
+ * device at creation; the entropy order drives the Bitmap traversal order of
+ * Section 3.2.  Either pointer may be NULL.
+ */
+int fc_db_marginals(const fc_db *db, int64_t *counts, float *entropy_bits);
+
+/*
+ * Number of cells prod r_v of the query's table (q_i * r_i, Section 2), or a
+ * negative FC_ERR_* code for an invalid query.
+ */
+int64_t fc_table_cells(const fc_db *db, const int32_t *vars, int32_t k);
+
+/*
+ * One query, one dense int32 table (Section 2 definition; the per-query
+ * path).  `cells` must equal fc_table_cells(db, vars, k).  `table` is
+ * overwritten.
+ */
+int fc_count(fc_db *db, const int32_t *vars, int32_t k, int32_t *table,
+             int64_t cells, void *stream);
+
+/*
+ * Count((X_vars[0] = states[0]) AND ...): the single-assignment query of
+ * Section 2, answered by one path of bit-vector intersections and a
+ * popcount (the single-path specialisation closing Section 3.3).  Uses the
+ * bit-vectors when the handle has them, the state columns otherwise.  The
+ * result is written to the host int64 `*count`; the call synchronises.
+ */
+int fc_count_assignment(fc_db *db, const int32_t *vars, const uint8_t *states,
+                        int32_t k, int64_t *count, void *stream);
+
+/*
+ * Many queries of uneven size in one submission (concurrent query groups,
+ * Section 3.1).  Query i is vars_flat[var_off[i] .. var_off[i+1]); its table
+ * is written at tables[table_off[i] .. table_off[i] + cells_i).  var_off and
+ * table_off hold nq+1 int64 values; table_off may be NULL, meaning tables are
+ * packed back to back in query order.  flags: an FC_STRAT_* value (forced
+ * strategies exist for testing; every strategy returns identical tables) and
+ * optionally FC_NO_GRAPH.
+ */
+int fc_count_batch(fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
+                   int64_t nq, int32_t *tables, const int64_t *table_off,
+                   uint32_t flags, void *stream);
+
+/*
+ * Query(X_i, Pa, F) with F drawn from a fixed set of reducers (Sections 3.1,
+ * Fig. 2, Eq. (1); MDL and BDeu of Section 4.2; mutual information of
+ * Section 1): counts every query's table and streams it into each reducer in
+ * the `reducers` mask.  Scores are float32 computed with compensated
+ * summation; for the j-th set bit of the mask (ascending), scores[j*nq + i]
+ * is query i's score and, if err is not NULL, err[j*nq + i] an upper
+ * estimate of its absolute rounding error.  `tables` may be NULL: the counts
+ * are then consumed and never stored (Section 3.1); otherwise it receives the
+ * tables as in fc_count_batch.  p may be NULL (ess = 1).
+ */
+int fc_count_reduce(fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
+                    int64_t nq, uint32_t reducers, const fc_reduce_params *p,
+                    float *scores, float *err, int32_t *tables,
+                    const int64_t *table_off, uint32_t flags, void *stream);
+
+/*
+ * All 2-itemset supports of binary items (association rule mining, Section
+ * 4.3) from the co-occurrence Gram matrix A^T A of the one-hot instance x item
+ * matrix, computed with int8 MFMA and exact int32 accumulation.  items lists
+ * ni distinct variables of arity 2 (state 1 = item present); NULL means all
+ * variables.  gram (nullable, ni*ni int32, row-major) receives the full
+ * symmetric matrix.  Every pair a < b with n_ab / m > minsup is written to
+ * out (ordered by a, then b) up to `cap` records; *n_out receives the total
+ * number of qualifying pairs (which may exceed cap).  Needs bit-vectors.
+ */
+int fc_pairs(fc_db *db, const int32_t *items, int32_t ni, double minsup,
+             int32_t *gram, fc_pair_rec *out, int64_t cap, int64_t *n_out,
+             void *stream);
+
+/*
+ * Device bytes a batch needs beyond the resident database: tables and
+ * scratch of fc_count_reduce with tables == NULL, the work plan, and the
+ * staging of host outputs.  Used by callers that admit work by memory.
+ */
+int fc_batch_footprint(const fc_db *db, const int32_t *vars_flat,
+                       const int64_t *var_off, int64_t nq, uint32_t flags,
+                       int64_t *bytes);
+
+/* Message of the last failed call on this host thread ("" if none). */
+const char *fc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASTCOUNT_H */

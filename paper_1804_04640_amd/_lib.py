@@ -1,0 +1,160 @@
+"""ctypes binding of the C ABI in include/fastcount.h (same names, same order
+of arguments).  Argument marshalling only: every step runs in the HIP
+library; if the library is not built, every call fails loudly."""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libfastcount.so")
+
+FC_OK = 0
+FC_ERR_INVALID = -1
+FC_ERR_RANGE = -2
+FC_ERR_NOMEM = -3
+FC_ERR_DEVICE = -4
+FC_MAX_VARS = 8
+FC_COL_MAJOR = 0
+FC_ROW_MAJOR = 1
+FC_DB_BITVECTORS = 1
+FC_DB_DATA_ON_DEVICE = 2
+FC_STRAT_AUTO = 0
+FC_STRAT_HIST = 1
+FC_STRAT_BITMAP = 2
+FC_STRAT_PARTITION = 3
+FC_STRAT_SORT = FC_STRAT_PARTITION
+FC_NO_GRAPH = 0x10
+FC_RED_LL = 1
+FC_RED_MDL = 2
+FC_RED_BDEU = 4
+FC_RED_MI = 8
+
+# every symbol the header declares
+EXPORTS = ("fc_db_create", "fc_db_destroy", "fc_db_info", "fc_db_marginals", "fc_table_cells",
+           "fc_count", "fc_count_assignment", "fc_count_batch", "fc_count_reduce", "fc_pairs",
+           "fc_batch_footprint", "fc_last_error")
+
+
+class FastcountError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("fastcount error %d: %s" % (code, msg))
+        self.code = code
+
+
+class fc_reduce_params(ctypes.Structure):
+    _fields_ = [("ess", ctypes.c_double)]
+
+
+class fc_pair_rec(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_int32), ("b", ctypes.c_int32), ("n_ab", ctypes.c_int32),
+                ("support", ctypes.c_float), ("conf_ab", ctypes.c_float),
+                ("conf_ba", ctypes.c_float)]
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def load():
+    """Load libfastcount.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise FastcountError(FC_ERR_DEVICE,
+                                 "HIP library %s is not built; run __graft_entry__.build() or "
+                                 "python paper_1804_04640_amd/build.py" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+        sig = {
+            "fc_db_create": (ctypes.c_int, [P, i64, i32, P, i32, u32, P, P]),
+            "fc_db_destroy": (None, [P]),
+            "fc_db_info": (ctypes.c_int, [P, P, P, P, P]),
+            "fc_db_marginals": (ctypes.c_int, [P, P, P]),
+            "fc_table_cells": (i64, [P, P, i32]),
+            "fc_count": (ctypes.c_int, [P, P, i32, P, i64, P]),
+            "fc_count_assignment": (ctypes.c_int, [P, P, P, i32, P, P]),
+            "fc_count_batch": (ctypes.c_int, [P, P, P, i64, P, P, u32, P]),
+            "fc_count_reduce": (ctypes.c_int, [P, P, P, i64, u32, P, P, P, P, P, u32, P]),
+            "fc_pairs": (ctypes.c_int, [P, P, i32, ctypes.c_double, P, P, i64, P, P]),
+            "fc_batch_footprint": (ctypes.c_int, [P, P, P, i64, u32, P]),
+            "fc_last_error": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+        return _lib
+
+
+def last_error() -> str:
+    return load().fc_last_error().decode("utf-8", "replace")
+
+
+def check(rc: int) -> int:
+    if rc < 0:
+        raise FastcountError(int(rc), last_error())
+    return rc
+
+
+# Thin wrappers with the C names; pointers are plain integers (host or device).
+def fc_db_create(data, m, n, arity, layout, flags, stream):
+    h = ctypes.c_void_p()
+    check(load().fc_db_create(data, m, n, arity, layout, flags, stream, ctypes.byref(h)))
+    return h.value
+
+
+def fc_db_destroy(db):
+    load().fc_db_destroy(db)
+
+
+def fc_db_info(db):
+    m, n, hb, nb = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+    check(load().fc_db_info(db, ctypes.byref(m), ctypes.byref(n), ctypes.byref(hb),
+                            ctypes.byref(nb)))
+    return m.value, n.value, bool(hb.value), nb.value
+
+
+def fc_db_marginals(db, counts, entropy_bits):
+    return check(load().fc_db_marginals(db, counts, entropy_bits))
+
+
+def fc_table_cells(db, vars_, k):
+    return check(load().fc_table_cells(db, vars_, k))
+
+
+def fc_count(db, vars_, k, table, cells, stream):
+    return check(load().fc_count(db, vars_, k, table, cells, stream))
+
+
+def fc_count_assignment(db, vars_, states, k, stream):
+    out = ctypes.c_int64()
+    check(load().fc_count_assignment(db, vars_, states, k, ctypes.byref(out), stream))
+    return out.value
+
+
+def fc_count_batch(db, vars_flat, var_off, nq, tables, table_off, flags, stream):
+    return check(load().fc_count_batch(db, vars_flat, var_off, nq, tables, table_off, flags,
+                                       stream))
+
+
+def fc_count_reduce(db, vars_flat, var_off, nq, reducers, params, scores, err, tables, table_off,
+                    flags, stream):
+    return check(load().fc_count_reduce(db, vars_flat, var_off, nq, reducers, params, scores, err,
+                                        tables, table_off, flags, stream))
+
+
+def fc_pairs(db, items, ni, minsup, gram, out, cap, stream):
+    n_out = ctypes.c_int64()
+    check(load().fc_pairs(db, items, ni, minsup, gram, out, cap, ctypes.byref(n_out), stream))
+    return n_out.value
+
+
+def fc_batch_footprint(db, vars_flat, var_off, nq, flags):
+    b = ctypes.c_int64()
+    check(load().fc_batch_footprint(db, vars_flat, var_off, nq, flags, ctypes.byref(b)))
+    return b.value

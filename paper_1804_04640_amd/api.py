@@ -1,0 +1,219 @@
+"""torch-facing wrapper over the C ABI: device memory and streams come from
+torch, every step of the counting path runs in the HIP library.
+
+    db = Database(D, arity)                      # D: uint8 [n][m] numpy or torch
+    T = db.count([0, 2, 1])                      # int32 tensor on the device
+    tables, off = db.count_batch(queries)        # packed tables + offsets
+    scores = db.count_reduce(queries, ("bdeu", "mi"), ess=1.0)
+    n = db.count_assignment([0, 1], [2, 0])
+    recs = db.pairs(minsup=0.001)
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, Iterable, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+REDUCER_BITS = {"ll": L.FC_RED_LL, "mdl": L.FC_RED_MDL, "bdeu": L.FC_RED_BDEU, "mi": L.FC_RED_MI}
+STRATEGIES = {"auto": L.FC_STRAT_AUTO, "hist": L.FC_STRAT_HIST, "bitmap": L.FC_STRAT_BITMAP,
+              "partition": L.FC_STRAT_PARTITION, "sort": L.FC_STRAT_SORT}
+
+
+def _np_ptr(a: np.ndarray) -> int:
+    return a.ctypes.data if a.size else 0
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def flatten_queries(queries):
+    """(vars_flat int32, var_off int64) from a list of variable lists, or
+    pass an existing (flat, off) pair through."""
+    if isinstance(queries, tuple) and len(queries) == 2 and isinstance(queries[1], np.ndarray):
+        flat, off = queries
+        return np.ascontiguousarray(flat, np.int32), np.ascontiguousarray(off, np.int64)
+    qs = [np.asarray(q, dtype=np.int32).ravel() for q in queries]
+    off = np.zeros(len(qs) + 1, dtype=np.int64)
+    if qs:
+        off[1:] = np.cumsum([len(q) for q in qs])
+    flat = np.concatenate(qs).astype(np.int32) if qs else np.zeros(0, np.int32)
+    return np.ascontiguousarray(flat), off
+
+
+class Database:
+    """A complete categorical database resident on one GPU."""
+
+    def __init__(self, D, arity, bitvectors: bool = True, layout: str = "col", stream=None,
+                 device=None):
+        arity = np.ascontiguousarray(np.asarray(arity, dtype=np.uint8))
+        lay = L.FC_COL_MAJOR if layout == "col" else L.FC_ROW_MAJOR
+        flags = L.FC_DB_BITVECTORS if bitvectors else 0
+        self.device = torch.device(device) if device is not None else torch.device(
+            "cuda", torch.cuda.current_device())
+        with torch.cuda.device(self.device):
+            if isinstance(D, torch.Tensor):
+                Dt = D.contiguous()
+                if Dt.dtype != torch.uint8:
+                    raise TypeError("D must be uint8")
+                if Dt.is_cuda:
+                    flags |= L.FC_DB_DATA_ON_DEVICE
+                ptr = Dt.data_ptr() if Dt.numel() else 0
+                shape = tuple(Dt.shape)
+            else:
+                Dt = np.ascontiguousarray(np.asarray(D, dtype=np.uint8))
+                ptr = _np_ptr(Dt)
+                shape = Dt.shape
+            if len(shape) != 2:
+                raise ValueError("D must be 2-D")
+            n, m = (shape[0], shape[1]) if lay == L.FC_COL_MAJOR else (shape[1], shape[0])
+            if len(arity) != n:
+                raise ValueError("arity has %d entries for %d variables" % (len(arity), n))
+            self._h = L.fc_db_create(ptr, m, n, _np_ptr(arity), lay, flags, _stream(stream))
+        self.n, self.m = int(n), int(m)
+        self.arity = arity.copy()
+        self.bitvectors = bitvectors
+
+    # ----------------------------------------------------------- lifecycle
+    def close(self):
+        if getattr(self, "_h", None):
+            L.fc_db_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self) -> int:
+        if not self._h:
+            raise L.FastcountError(L.FC_ERR_INVALID, "database is closed")
+        return self._h
+
+    # ----------------------------------------------------------- facts
+    def info(self):
+        return L.fc_db_info(self.handle)
+
+    def marginals(self):
+        cnt = np.zeros(int(self.arity.astype(np.int64).sum()), np.int64)
+        ent = np.zeros(self.n, np.float32)
+        L.fc_db_marginals(self.handle, _np_ptr(cnt), _np_ptr(ent))
+        return cnt, ent
+
+    def table_cells(self, vars_) -> int:
+        v = np.ascontiguousarray(vars_, np.int32)
+        return L.fc_table_cells(self.handle, _np_ptr(v), len(v))
+
+    def _empty(self, n, dtype):
+        return torch.empty(int(n), dtype=dtype, device=self.device)
+
+    # ----------------------------------------------------------- counting
+    def count(self, vars_, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        v = np.ascontiguousarray(vars_, np.int32)
+        cells = self.table_cells(v)
+        if out is None:
+            out = self._empty(cells, torch.int32)
+        L.fc_count(self.handle, _np_ptr(v), len(v), out.data_ptr(), cells, _stream(stream))
+        return out
+
+    def count_assignment(self, vars_, states, stream=None) -> int:
+        v = np.ascontiguousarray(vars_, np.int32)
+        s = np.ascontiguousarray(states, np.uint8)
+        return L.fc_count_assignment(self.handle, _np_ptr(v), _np_ptr(s), len(v), _stream(stream))
+
+    def table_offsets(self, queries) -> np.ndarray:
+        flat, off = flatten_queries(queries)
+        # out-of-range variables are clipped here only to size the buffer; the
+        # library rejects such queries with a message naming them
+        ar = np.take(self.arity.astype(np.int64), flat, mode="clip")
+        cells = np.array([int(np.prod(ar[off[i]:off[i + 1]])) for i in range(len(off) - 1)],
+                         dtype=np.int64)
+        toff = np.zeros(len(cells) + 1, np.int64)
+        toff[1:] = np.cumsum(cells)
+        return toff
+
+    def count_batch(self, queries, strategy: str = "auto", tables: Optional[torch.Tensor] = None,
+                    table_off: Optional[np.ndarray] = None, graph: bool = True, stream=None):
+        """Returns (tables int32 tensor, table_off int64 numpy [nq+1])."""
+        flat, off = flatten_queries(queries)
+        nq = len(off) - 1
+        if table_off is None:
+            toff = self.table_offsets((flat, off))
+            tptr = 0
+        else:
+            toff = np.ascontiguousarray(table_off, np.int64)
+            tptr = _np_ptr(toff)
+        if tables is None:
+            tables = self._empty(max(1, int(toff[-1])), torch.int32)
+        flags = STRATEGIES[strategy] | (0 if graph else L.FC_NO_GRAPH)
+        L.fc_count_batch(self.handle, _np_ptr(flat), _np_ptr(off), nq, tables.data_ptr(), tptr,
+                         flags, _stream(stream))
+        return tables, toff
+
+    def count_reduce(self, queries, reducers: Sequence[str] = ("mdl",), ess: float = 1.0,
+                     keep_tables: bool = False, strategy: str = "auto", with_err: bool = True,
+                     stream=None, out: Optional[torch.Tensor] = None,
+                     err_out: Optional[torch.Tensor] = None):
+        """Returns (scores {name: tensor[nq]}, err {name: tensor[nq]} or None,
+        tables or None, table_off or None)."""
+        flat, off = flatten_queries(queries)
+        nq = len(off) - 1
+        names = [r for r in ("ll", "mdl", "bdeu", "mi") if r in reducers]
+        if len(names) != len(set(reducers)):
+            raise ValueError("unknown reducer in %r" % (reducers,))
+        mask = 0
+        for r in names:
+            mask |= REDUCER_BITS[r]
+        scores = out if out is not None else self._empty(len(names) * max(nq, 1), torch.float32)
+        err = (err_out if err_out is not None else
+               self._empty(len(names) * max(nq, 1), torch.float32)) if with_err else None
+        tables, toff = None, None
+        if keep_tables:
+            toff = self.table_offsets((flat, off))
+            tables = self._empty(max(1, int(toff[-1])), torch.int32)
+        params = L.fc_reduce_params(float(ess))
+        L.fc_count_reduce(self.handle, _np_ptr(flat), _np_ptr(off), nq, mask,
+                          ctypes.addressof(params), scores.data_ptr(),
+                          err.data_ptr() if err is not None else 0,
+                          tables.data_ptr() if tables is not None else 0, 0,
+                          STRATEGIES[strategy], _stream(stream))
+        sc = {r: scores[i * nq:(i + 1) * nq] for i, r in enumerate(names)}
+        er = {r: err[i * nq:(i + 1) * nq] for i, r in enumerate(names)} if err is not None else None
+        return sc, er, tables, toff
+
+    def footprint(self, queries, strategy: str = "auto") -> int:
+        flat, off = flatten_queries(queries)
+        return L.fc_batch_footprint(self.handle, _np_ptr(flat), _np_ptr(off), len(off) - 1,
+                                    STRATEGIES[strategy])
+
+    # ----------------------------------------------------------- pairs
+    def pairs(self, minsup: float, items: Optional[Iterable[int]] = None, gram: bool = False,
+              cap: Optional[int] = None, stream=None):
+        """Association-rule pairs (Section 4.3).  Returns (records numpy
+        structured array, gram tensor or None)."""
+        it = None if items is None else np.ascontiguousarray(list(items), np.int32)
+        ni = self.n if it is None else len(it)
+        g = self._empty(ni * ni, torch.int32) if gram else None
+        cap = ni * (ni - 1) // 2 if cap is None else int(cap)
+        recs = (L.fc_pair_rec * max(cap, 1))()
+        total = L.fc_pairs(self.handle, _np_ptr(it) if it is not None else 0, ni, float(minsup),
+                           g.data_ptr() if g is not None else 0, ctypes.addressof(recs), cap,
+                           _stream(stream))
+        dt = np.dtype([("a", np.int32), ("b", np.int32), ("n_ab", np.int32),
+                       ("support", np.float32), ("conf_ab", np.float32), ("conf_ba", np.float32)])
+        arr = np.frombuffer(recs, dtype=dt, count=min(total, cap)).copy()
+        return arr, (g.view(ni, ni) if g is not None else None), total

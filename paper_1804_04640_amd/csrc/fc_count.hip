@@ -1,0 +1,772 @@
+// Counting kernels, the batch planner and the counting entry points.
+//
+// Three exact strategies produce identical tables (the numbers of the
+// Section 2 definition):
+//  * HIST: every instance's states form one mixed-radix key (the digits of
+//    the MSD radix of Section 3.3, child least significant) and the key's
+//    cell is incremented in an LDS histogram.  Small tables keep up to 64
+//    copies of the histogram (one per lane slot, odd row stride) so lanes of
+//    a wave rarely hit the same address.
+//  * BITMAP: the per-state bit-vectors of the query's variables are ANDed
+//    down the configuration tree of Alg. 1 and the leaves are popcounted; a
+//    subtree whose prefix is empty in every lane of the wave is pruned, as
+//    Alg. 1 prunes a zero intersection.  The tree is walked on chip for a
+//    few 64-row words per thread at a time, never stored.
+//  * PARTITION: tables too large for LDS are split by their top key digits
+//    into windows that fit (the MSD partition of Section 3.3); each window is
+//    an LDS histogram of the rows whose key falls in it.
+// Partial tables of row chunks are summed into the output with int32
+// atomics, which is exact and order independent.
+#include <algorithm>
+#include <cstring>
+
+#include "fc_internal.h"
+
+namespace fc {
+
+constexpr int kHistMaxCells = 40000;  // odd row stride * 4 B <= 160 KiB
+
+__device__ __forceinline__ void map_block(int64_t b, int32_t nd, int32_t chunks, int32_t &d,
+                                          int32_t &c) {
+    // XCD-aware order: blocks are dealt round-robin to the 8 XCDs, so block
+    // b runs on XCD b % 8.  When chunks is a multiple of 8, XCD x works on
+    // chunks x, x+8, ... of every descriptor in turn, keeping one row range
+    // of all columns hot in its own L2.
+    if (chunks % kXcds == 0) {
+        int32_t x = (int32_t)(b % kXcds);
+        int64_t t = b / kXcds;
+        int32_t phase = (int32_t)(t / nd);
+        d = (int32_t)(t % nd);
+        c = phase * kXcds + x;
+    } else {
+        d = (int32_t)(b / chunks);
+        c = (int32_t)(b % chunks);
+    }
+}
+
+__device__ __forceinline__ uint32_t byte_of(const uint4 &v, int i) {
+    uint32_t w = (i < 4) ? v.x : (i < 8) ? v.y : (i < 12) ? v.z : v.w;
+    return (w >> ((i & 3) * 8)) & 0xFFu;
+}
+
+// LDS histogram count of one descriptor over one row chunk.
+// SMALL: every stride is below 2^24, so 24-bit multiplies suffice.
+template <int K, bool SMALL>
+__global__ __launch_bounds__(kBlock) void k_hist(const uint8_t *__restrict__ cols, int64_t m_pad,
+                                                 const uint8_t *__restrict__ arity,
+                                                 const QDesc *__restrict__ descs, int32_t nd,
+                                                 int32_t chunks, int32_t lds_words,
+                                                 int32_t pad_rows, int32_t *__restrict__ tables) {
+    extern __shared__ uint32_t lds[];
+    int32_t di, c;
+    map_block(blockIdx.x, nd, chunks, di, c);
+    const QDesc &q = descs[di];
+    const int32_t win_base = q.win_base;
+    const uint32_t win = (uint32_t)q.win_cells;
+
+    uint32_t stride[K];
+    const uint8_t *colp[K];
+    {
+        uint32_t s = 1;
+#pragma unroll
+        for (int t = K - 1; t >= 0; --t) {
+            int32_t v = q.var[t];
+            stride[t] = s;
+            s *= arity[v];
+            colp[t] = cols + (int64_t)v * m_pad;
+        }
+    }
+    const int32_t cs = (int32_t)(win | 1u);
+    int32_t copies = lds_words / cs;
+    copies = copies >= 64 ? 64 : copies >= 32 ? 32 : copies >= 16 ? 16 : copies >= 8 ? 8
+           : copies >= 4 ? 4 : copies >= 2 ? 2 : 1;
+    for (int32_t i = threadIdx.x; i < copies * cs; i += kBlock) lds[i] = 0;
+    __syncthreads();
+
+    const int64_t tiles = m_pad / kTileRows;
+    const int64_t r0 = (int64_t)c * tiles / chunks * kTileRows;
+    const int64_t r1 = (int64_t)(c + 1) * tiles / chunks * kTileRows;
+    uint32_t *h = lds + (threadIdx.x & (copies - 1)) * cs;
+
+    for (int64_t row = r0 + (int64_t)threadIdx.x * 16; row < r1; row += kBlock * 16) {
+        uint4 v[K];
+#pragma unroll
+        for (int t = 0; t < K; ++t) v[t] = *reinterpret_cast<const uint4 *>(colp[t] + row);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            uint32_t key = 0;
+#pragma unroll
+            for (int t = 0; t < K; ++t) {
+                uint32_t b = byte_of(v[t], i);
+                key += SMALL ? __umul24(b, stride[t]) : b * stride[t];
+            }
+            key -= (uint32_t)win_base;
+            if (key < win) atomicAdd(&h[key], 1u);
+        }
+    }
+    __syncthreads();
+    const bool has_pad = (r1 == m_pad) && (r0 < r1) && win_base == 0;
+    int32_t *out = tables + q.table_off + win_base;
+    for (int32_t cell = threadIdx.x; cell < (int32_t)win; cell += kBlock) {
+        uint32_t sum = 0;
+        for (int32_t p = 0; p < copies; ++p) sum += lds[p * cs + cell];
+        if (cell == 0 && has_pad) sum -= (uint32_t)pad_rows;  // padding rows are key 0
+        if (sum) atomicAdd(&out[cell], (int32_t)sum);
+    }
+}
+
+// Bitmap count (Alg. 1) of one descriptor over one chunk of 64-row words.
+template <int L, int K, int W>
+struct Walk {
+    __device__ __forceinline__ static void go(const uint64_t (&pre)[W], uint32_t cell,
+                                              const uint64_t *__restrict__ bits, int64_t words,
+                                              int64_t w, const int32_t (&base)[K],
+                                              const int32_t (&rad)[K], uint32_t *acc) {
+        for (int32_t s = 0; s < rad[L]; ++s) {
+            const uint64_t *row = bits + (int64_t)(base[L] + s) * words + w;
+            uint64_t x[W];
+#pragma unroll
+            for (int i = 0; i < W; ++i) x[i] = row[i] & pre[i];
+            const uint32_t c2 = cell * (uint32_t)rad[L] + (uint32_t)s;
+            if constexpr (L == K - 1) {
+                uint32_t pc = 0;
+#pragma unroll
+                for (int i = 0; i < W; ++i) pc += (uint32_t)__popcll(x[i]);
+                acc[c2 * kBlock] += pc;
+            } else {
+                uint64_t any = 0;
+#pragma unroll
+                for (int i = 0; i < W; ++i) any |= x[i];
+                if (__any(any != 0)) Walk<L + 1, K, W>::go(x, c2, bits, words, w, base, rad, acc);
+            }
+        }
+    }
+};
+
+template <int K, int W>
+__global__ __launch_bounds__(kBlock) void k_bitmap(const uint64_t *__restrict__ bits,
+                                                   int64_t words,
+                                                   const int32_t *__restrict__ soff,
+                                                   const uint8_t *__restrict__ arity,
+                                                   const QDesc *__restrict__ descs, int32_t nd,
+                                                   int32_t chunks, int32_t *__restrict__ tables) {
+    extern __shared__ uint32_t acc[];  // [cells][kBlock], thread-private columns
+    int32_t di, c;
+    map_block(blockIdx.x, nd, chunks, di, c);
+    const QDesc &q = descs[di];
+    const int32_t cells = q.cells;
+    int32_t base[K], rad[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        base[t] = soff[q.var[t]];
+        rad[t] = arity[q.var[t]];
+    }
+    for (int32_t i = threadIdx.x; i < cells * kBlock; i += kBlock) acc[i] = 0;
+    __syncthreads();
+    const int64_t tiles = words / (kTileRows / 64);
+    const int64_t w0 = (int64_t)c * tiles / chunks * (kTileRows / 64);
+    const int64_t w1 = (int64_t)(c + 1) * tiles / chunks * (kTileRows / 64);
+    uint64_t ones[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i) ones[i] = ~0ull;
+    for (int64_t w = w0 + (int64_t)threadIdx.x * W; w < w1; w += kBlock * W)
+        Walk<0, K, W>::go(ones, 0u, bits, words, w, base, rad, acc + threadIdx.x);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int32_t *out = tables + q.table_off;
+    for (int32_t cell = wave; cell < cells; cell += kWaves) {
+        uint32_t s = 0;
+        for (int j = lane; j < kBlock; j += 64) s += acc[cell * kBlock + j];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (lane == 0 && s) atomicAdd(&out[cell], (int32_t)s);
+    }
+}
+
+// Zero every descriptor's table (tables placed by the caller).
+__global__ void k_zero_tables(const QDesc *__restrict__ descs, int32_t nd,
+                              int32_t *__restrict__ tables) {
+    for (int32_t d = blockIdx.x; d < nd; d += gridDim.x) {
+        int32_t *t = tables + descs[d].table_off;
+        for (int32_t i = threadIdx.x; i < descs[d].cells; i += blockDim.x) t[i] = 0;
+    }
+}
+
+// Single-assignment count: one path of the Alg. 1 tree (bit-vector rows).
+struct Rows8 {
+    int32_t r[FC_MAX_VARS];
+};
+__global__ void k_assign_bits(const uint64_t *__restrict__ bits, int64_t words, Rows8 rows,
+                              int32_t k, unsigned long long *__restrict__ out) {
+    unsigned long long cnt = 0;
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words;
+         w += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t x = ~0ull;
+        for (int32_t t = 0; t < k; ++t) x &= bits[(int64_t)rows.r[t] * words + w];
+        cnt += (unsigned long long)__popcll(x);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(out, cnt);
+}
+
+// Same count from the state columns (no bit-vectors): one partition path.
+struct Assign8 {
+    int32_t var[FC_MAX_VARS];
+    int32_t state[FC_MAX_VARS];
+};
+__global__ void k_assign_cols(const uint8_t *__restrict__ cols, int64_t m, int64_t m_pad,
+                              Assign8 a, int32_t k, unsigned long long *__restrict__ out) {
+    unsigned long long cnt = 0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        bool ok = true;
+        for (int32_t t = 0; t < k; ++t)
+            ok = ok && cols[(int64_t)a.var[t] * m_pad + p] == (uint8_t)a.state[t];
+        cnt += ok ? 1ull : 0ull;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(out, cnt);
+}
+
+// ------------------------------------------------------------------ planner
+enum Strat { S_HIST = 1, S_BITMAP = 2, S_PART = 3 };
+
+struct Launch {
+    int strat;
+    int K;
+    bool small;
+    int64_t first;    // first descriptor
+    int32_t count;    // descriptors
+    int32_t chunks;
+    int32_t lds_bytes;
+};
+
+struct Plan {
+    std::vector<QDesc> work;    // counting descriptors, grouped by launch
+    std::vector<QDesc> query;   // one per query, in query order (reducers)
+    std::vector<Launch> launches;
+    int64_t total_cells = 0;    // table buffer size in cells
+    bool packed = true;         // tables back to back in query order
+};
+
+static const int32_t kClassCap[] = {16, 64, 256, 1024, 4096, 16384, kHistMaxCells};
+static const int32_t kClassLds[] = {64 * 17 * 4,  64 * 65 * 4,   16 * 257 * 4, 4 * 1025 * 4,
+                                    4097 * 4,     16385 * 4,     kHistMaxCells * 4 + 4};
+
+static int hist_class(int64_t cells) {
+    for (int i = 0; i < 7; ++i)
+        if (cells <= kClassCap[i]) return i;
+    return -1;
+}
+
+static int validate(const fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
+                    int64_t nq, const int64_t *table_off, std::vector<int64_t> &cells) {
+    if (!db) {
+        set_error("NULL database handle");
+        return FC_ERR_INVALID;
+    }
+    if (nq < 0 || (nq > 0 && (!vars_flat || !var_off))) {
+        set_error("need nq >= 0, vars_flat and var_off");
+        return FC_ERR_INVALID;
+    }
+    if (nq > (int64_t)INT32_MAX / 2) {
+        set_error("batch of %lld queries is too large", (long long)nq);
+        return FC_ERR_RANGE;
+    }
+    cells.resize((size_t)nq);
+    if (nq > 0 && var_off[0] != 0) {
+        set_error("var_off[0] must be 0");
+        return FC_ERR_INVALID;
+    }
+    for (int64_t i = 0; i < nq; ++i) {
+        int64_t k = var_off[i + 1] - var_off[i];
+        if (k < 1 || k > FC_MAX_VARS) {
+            set_error("query %lld has %lld variables (need 1..%d)", (long long)i, (long long)k,
+                      FC_MAX_VARS);
+            return FC_ERR_INVALID;
+        }
+        const int32_t *v = vars_flat + var_off[i];
+        int64_t c = 1;
+        for (int64_t t = 0; t < k; ++t) {
+            if (v[t] < 0 || v[t] >= db->n) {
+                set_error("query %lld: variable %d out of range [0, %d)", (long long)i, v[t],
+                          db->n);
+                return FC_ERR_INVALID;
+            }
+            for (int64_t u = 0; u < t; ++u)
+                if (v[u] == v[t]) {
+                    set_error("query %lld: variable %d appears twice", (long long)i, v[t]);
+                    return FC_ERR_INVALID;
+                }
+            c *= db->arity[v[t]];
+        }
+        if (c > INT32_MAX) {
+            set_error("query %lld: table of %lld cells exceeds int32 indexing", (long long)i,
+                      (long long)c);
+            return FC_ERR_RANGE;
+        }
+        cells[(size_t)i] = c;
+    }
+    if (table_off) {
+        int64_t total = table_off[nq];
+        for (int64_t i = 0; i < nq; ++i)
+            if (table_off[i] < 0 || table_off[i] + cells[(size_t)i] > total) {
+                set_error("query %lld: table_off places its %lld cells outside [0, %lld)",
+                          (long long)i, (long long)cells[(size_t)i], (long long)total);
+                return FC_ERR_INVALID;
+            }
+    }
+    return FC_OK;
+}
+
+static int32_t pick_chunks(const fc_db *db, int64_t nd, int64_t cells) {
+    const int64_t tiles = db->m_pad / kTileRows;
+    int64_t min_rows = db->tune.chunk_rows > 0 ? db->tune.chunk_rows : 32768;
+    if (min_rows < 8 * cells) min_rows = 8 * cells;  // keep flushes << scans
+    int64_t max_chunks = std::max<int64_t>(1, db->m_pad / min_rows);
+    int64_t want = (4 * (int64_t)db->cu_count + nd - 1) / nd;
+    if (want < kXcds) want = kXcds;
+    if (db->tune.hist_min_chunks > 0) want = std::max<int64_t>(want, db->tune.hist_min_chunks);
+    int64_t ch = std::min(want, std::min(max_chunks, tiles));
+    if (ch >= kXcds) ch -= ch % kXcds;
+    if (ch < 1) ch = 1;
+    return (int32_t)ch;
+}
+
+static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
+                      int64_t nq, const int64_t *table_off, uint32_t flags,
+                      const std::vector<int64_t> &cells, Plan &P) {
+    const uint32_t forced = flags & FC_STRAT_MASK;
+    if (forced > FC_STRAT_PARTITION) {
+        set_error("unknown strategy %u", forced);
+        return FC_ERR_INVALID;
+    }
+    if (forced == FC_STRAT_BITMAP && !db->d_bits) {
+        set_error("FC_STRAT_BITMAP needs a database created with FC_DB_BITVECTORS");
+        return FC_ERR_INVALID;
+    }
+    P.packed = table_off == nullptr;
+    P.query.resize((size_t)nq);
+    int64_t off = 0;
+    // buckets: strat(3) x K(8) x class(7) x small(2)
+    std::vector<std::vector<QDesc>> bucket(3 * 8 * 7 * 2);
+    auto bidx = [](int st, int K, int cls, bool small) {
+        return (((st - 1) * 8 + (K - 1)) * 7 + cls) * 2 + (small ? 1 : 0);
+    };
+    for (int64_t i = 0; i < nq; ++i) {
+        QDesc d;
+        std::memset(&d, 0, sizeof d);
+        const int64_t k = var_off[i + 1] - var_off[i];
+        const int64_t c = cells[(size_t)i];
+        d.k = (int32_t)k;
+        for (int64_t t = 0; t < k; ++t) d.var[t] = vars_flat[var_off[i] + t];
+        d.cells = (int32_t)c;
+        d.qid = (int32_t)i;
+        d.table_off = table_off ? table_off[i] : off;
+        off += c;
+        d.win_base = 0;
+        d.win_cells = (int32_t)c;
+        P.query[(size_t)i] = d;
+
+        int st;
+        if (forced == FC_STRAT_BITMAP)
+            st = c <= 128 ? S_BITMAP : (c <= kHistMaxCells ? S_HIST : S_PART);
+        else if (forced == FC_STRAT_HIST)
+            st = c <= kHistMaxCells ? S_HIST : S_PART;
+        else if (forced == FC_STRAT_PARTITION)
+            st = S_PART;
+        else if (db->d_bits && c <= db->tune.bitmap_max_cells)
+            st = S_BITMAP;
+        else
+            st = c <= kHistMaxCells ? S_HIST : S_PART;
+        const bool small = c < (int64_t(1) << 24);
+        if (st == S_BITMAP) {
+            bucket[bidx(S_BITMAP, (int)k, 0, false)].push_back(d);
+        } else if (st == S_HIST) {
+            bucket[bidx(S_HIST, (int)k, hist_class(c), small)].push_back(d);
+        } else {
+            // windows over the top key digits: at least two when forced
+            int64_t win = kHistMaxCells;
+            if (forced == FC_STRAT_PARTITION && c <= kHistMaxCells) win = (c + 1) / 2;
+            if (win < 1) win = 1;
+            for (int64_t b0 = 0; b0 < c; b0 += win) {
+                QDesc w = d;
+                w.win_base = (int32_t)b0;
+                w.win_cells = (int32_t)std::min<int64_t>(win, c - b0);
+                bucket[bidx(S_PART, (int)k, hist_class(w.win_cells), small)].push_back(w);
+            }
+        }
+    }
+    P.total_cells = table_off ? table_off[nq] : off;
+    for (int st = 1; st <= 3; ++st)
+        for (int K = 1; K <= 8; ++K)
+            for (int cls = 0; cls < 7; ++cls)
+                for (int sm = 0; sm < 2; ++sm) {
+                    auto &b = bucket[bidx(st, K, cls, sm != 0)];
+                    if (b.empty()) continue;
+                    Launch L;
+                    L.strat = st;
+                    L.K = K;
+                    L.small = sm != 0;
+                    L.first = (int64_t)P.work.size();
+                    L.count = (int32_t)b.size();
+                    int64_t maxc = 0;
+                    for (auto &d : b) maxc = std::max<int64_t>(maxc, d.win_cells);
+                    L.chunks = pick_chunks(db, L.count, maxc);
+                    if (st == S_BITMAP)
+                        L.lds_bytes = (int32_t)(maxc * kBlock * 4);
+                    else
+                        L.lds_bytes = kClassLds[cls];
+                    P.work.insert(P.work.end(), b.begin(), b.end());
+                    P.launches.push_back(L);
+                }
+    return FC_OK;
+}
+
+// ------------------------------------------------------------------ launch
+template <int K>
+static hipError_t launch_hist_k(const fc_db *db, const Launch &L, const QDesc *d,
+                                int32_t *tables, hipStream_t s) {
+    const int64_t blocks = (int64_t)L.count * L.chunks;
+    const int32_t pad = (int32_t)(db->m_pad - db->m);
+    if (L.small)
+        hipLaunchKernelGGL((k_hist<K, true>), dim3((unsigned)blocks), dim3(kBlock), L.lds_bytes,
+                           s, db->d_cols, db->m_pad, db->d_arity, d, L.count, L.chunks,
+                           L.lds_bytes / 4, pad, tables);
+    else
+        hipLaunchKernelGGL((k_hist<K, false>), dim3((unsigned)blocks), dim3(kBlock), L.lds_bytes,
+                           s, db->d_cols, db->m_pad, db->d_arity, d, L.count, L.chunks,
+                           L.lds_bytes / 4, pad, tables);
+    return hipGetLastError();
+}
+
+template <int K>
+static hipError_t launch_bitmap_k(const fc_db *db, const Launch &L, const QDesc *d,
+                                  int32_t *tables, hipStream_t s) {
+    const int64_t blocks = (int64_t)L.count * L.chunks;
+    if (db->tune.bitmap_words >= 4)
+        hipLaunchKernelGGL((k_bitmap<K, 4>), dim3((unsigned)blocks), dim3(kBlock), L.lds_bytes,
+                           s, db->d_bits, db->words, db->d_soff, db->d_arity, d, L.count,
+                           L.chunks, tables);
+    else if (db->tune.bitmap_words == 2)
+        hipLaunchKernelGGL((k_bitmap<K, 2>), dim3((unsigned)blocks), dim3(kBlock), L.lds_bytes,
+                           s, db->d_bits, db->words, db->d_soff, db->d_arity, d, L.count,
+                           L.chunks, tables);
+    else
+        hipLaunchKernelGGL((k_bitmap<K, 1>), dim3((unsigned)blocks), dim3(kBlock), L.lds_bytes,
+                           s, db->d_bits, db->words, db->d_soff, db->d_arity, d, L.count,
+                           L.chunks, tables);
+    return hipGetLastError();
+}
+
+template <int K>
+static hipError_t launch_one(const fc_db *db, const Launch &L, const QDesc *d, int32_t *t,
+                             hipStream_t s) {
+    return L.strat == S_BITMAP ? launch_bitmap_k<K>(db, L, d, t, s)
+                               : launch_hist_k<K>(db, L, d, t, s);
+}
+
+static hipError_t launch_count(const fc_db *db, const Launch &L, const QDesc *d_work,
+                               int32_t *tables, hipStream_t s) {
+    const QDesc *d = d_work + L.first;
+    switch (L.K) {
+        case 1: return launch_one<1>(db, L, d, tables, s);
+        case 2: return launch_one<2>(db, L, d, tables, s);
+        case 3: return launch_one<3>(db, L, d, tables, s);
+        case 4: return launch_one<4>(db, L, d, tables, s);
+        case 5: return launch_one<5>(db, L, d, tables, s);
+        case 6: return launch_one<6>(db, L, d, tables, s);
+        case 7: return launch_one<7>(db, L, d, tables, s);
+        default: return launch_one<8>(db, L, d, tables, s);
+    }
+}
+
+static bool g_lds_attr_set = false;
+static std::mutex g_attr_mu;
+
+template <int K>
+static void set_attrs_k() {
+    (void)hipFuncSetAttribute((const void *)k_hist<K, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
+    (void)hipFuncSetAttribute((const void *)k_hist<K, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
+    (void)hipFuncSetAttribute((const void *)k_bitmap<K, 1>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
+    (void)hipFuncSetAttribute((const void *)k_bitmap<K, 2>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
+    (void)hipFuncSetAttribute((const void *)k_bitmap<K, 4>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
+}
+
+static void ensure_attrs() {
+    std::lock_guard<std::mutex> lk(g_attr_mu);
+    if (g_lds_attr_set) return;
+    set_attrs_k<1>(); set_attrs_k<2>(); set_attrs_k<3>(); set_attrs_k<4>();
+    set_attrs_k<5>(); set_attrs_k<6>(); set_attrs_k<7>(); set_attrs_k<8>();
+    (void)hipGetLastError();
+    g_lds_attr_set = true;
+}
+
+// Runs a whole batch: plan upload, table zeroing, counting launches, and the
+// optional reducers.  tables: device buffer of P.total_cells cells.
+static int run_batch(fc_db *db, Plan &P, int32_t *tables, uint32_t reducers, double ess,
+                     float *scores, float *err, hipStream_t s) {
+    ensure_attrs();
+    const size_t nw = P.work.size(), nqd = reducers ? P.query.size() : 0;
+    const size_t bytes = sizeof(QDesc) * (nw + nqd);
+    DevBuf d_desc;
+    if (bytes) {
+        FC_HIP(d_desc.alloc(bytes, s));
+        Staging *st = staging_acquire(bytes);
+        if (!st) {
+            set_error("pinned staging allocation of %zu bytes failed", bytes);
+            return FC_ERR_NOMEM;
+        }
+        std::memcpy(st->host, P.work.data(), sizeof(QDesc) * nw);
+        if (nqd) std::memcpy((QDesc *)st->host + nw, P.query.data(), sizeof(QDesc) * nqd);
+        hipError_t e = hipMemcpyAsync(d_desc.p, st->host, bytes, hipMemcpyHostToDevice, s);
+        staging_release(st, s);
+        if (e != hipSuccess) {
+            set_error("plan upload failed: %s", hipGetErrorString(e));
+            return FC_ERR_DEVICE;
+        }
+    }
+    const QDesc *dw = (const QDesc *)d_desc.p;
+    if (P.packed) {
+        FC_HIP(fill_zero_i32(tables, P.total_cells, s));
+    } else if (!P.query.empty()) {
+        // zero each query's table once, from the per-query list
+        DevBuf dq;
+        const QDesc *src = dw + nw;
+        if (!nqd) {
+            FC_HIP(dq.alloc(sizeof(QDesc) * P.query.size(), s));
+            Staging *st = staging_acquire(sizeof(QDesc) * P.query.size());
+            if (!st) {
+                set_error("pinned staging allocation failed");
+                return FC_ERR_NOMEM;
+            }
+            std::memcpy(st->host, P.query.data(), sizeof(QDesc) * P.query.size());
+            hipError_t e = hipMemcpyAsync(dq.p, st->host, sizeof(QDesc) * P.query.size(),
+                                          hipMemcpyHostToDevice, s);
+            staging_release(st, s);
+            FC_HIP(e);
+            src = (const QDesc *)dq.p;
+        }
+        int32_t nd = (int32_t)P.query.size();
+        hipLaunchKernelGGL(k_zero_tables, dim3((unsigned)std::min<int32_t>(nd, 65536)), dim3(256),
+                           0, s, src, nd, tables);
+        FC_HIP(hipGetLastError());
+    }
+    if (db->m > 0)
+        for (const Launch &L : P.launches) FC_HIP(launch_count(db, L, dw, tables, s));
+    if (reducers && nqd)
+        FC_HIP(launch_reduce(db, dw + nw, (int64_t)nqd, tables, reducers, ess, scores, err, s));
+    return FC_OK;
+}
+
+}  // namespace fc
+
+using namespace fc;
+
+extern "C" int64_t fc_table_cells(const fc_db *db, const int32_t *vars, int32_t k) {
+    clear_error();
+    if (!vars) {
+        set_error("fc_table_cells: vars is NULL");
+        return FC_ERR_INVALID;
+    }
+    std::vector<int64_t> cells;
+    int64_t off[2] = {0, k};
+    int rc = validate(db, vars, off, 1, nullptr, cells);
+    return rc ? rc : cells[0];
+}
+
+extern "C" int fc_count_batch(fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
+                              int64_t nq, int32_t *tables, const int64_t *table_off,
+                              uint32_t flags, void *stream) {
+    clear_error();
+    std::vector<int64_t> cells;
+    int rc = validate(db, vars_flat, var_off, nq, table_off, cells);
+    if (rc) return rc;
+    if (nq > 0 && !tables) {
+        set_error("fc_count_batch: tables is NULL");
+        return FC_ERR_INVALID;
+    }
+    Plan P;
+    if ((rc = build_plan(db, vars_flat, var_off, nq, table_off, flags, cells, P))) return rc;
+    if (nq == 0) return FC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    FC_HIP(hipSetDevice(db->device));
+    if (is_device_ptr(tables)) return run_batch(db, P, tables, 0, 0.0, nullptr, nullptr, s);
+    DevBuf dt;
+    FC_HIP(dt.alloc(sizeof(int32_t) * (size_t)P.total_cells, s));
+    if (!P.packed) {  // keep the caller's cells outside the tables intact
+        FC_HIP(hipMemcpyAsync(dt.p, tables, sizeof(int32_t) * (size_t)P.total_cells,
+                              hipMemcpyHostToDevice, s));
+    }
+    if ((rc = run_batch(db, P, (int32_t *)dt.p, 0, 0.0, nullptr, nullptr, s))) return rc;
+    FC_HIP(hipMemcpyAsync(tables, dt.p, sizeof(int32_t) * (size_t)P.total_cells,
+                          hipMemcpyDeviceToHost, s));
+    FC_HIP(hipStreamSynchronize(s));
+    return FC_OK;
+}
+
+extern "C" int fc_count(fc_db *db, const int32_t *vars, int32_t k, int32_t *table, int64_t cells,
+                        void *stream) {
+    clear_error();
+    if (!vars || !table) {
+        set_error("fc_count: vars and table must not be NULL");
+        return FC_ERR_INVALID;
+    }
+    int64_t off[2] = {0, k};
+    std::vector<int64_t> c;
+    int rc = validate(db, vars, off, 1, nullptr, c);
+    if (rc) return rc;
+    if (c[0] != cells) {
+        set_error("fc_count: cells=%lld but the query's table has %lld cells", (long long)cells,
+                  (long long)c[0]);
+        return FC_ERR_INVALID;
+    }
+    return fc_count_batch(db, vars, off, 1, table, nullptr, FC_STRAT_AUTO, stream);
+}
+
+extern "C" int fc_count_reduce(fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
+                               int64_t nq, uint32_t reducers, const fc_reduce_params *p,
+                               float *scores, float *err, int32_t *tables,
+                               const int64_t *table_off, uint32_t flags, void *stream) {
+    clear_error();
+    std::vector<int64_t> cells;
+    int rc = validate(db, vars_flat, var_off, nq, table_off, cells);
+    if (rc) return rc;
+    if (reducers == 0 || (reducers & ~(uint32_t)(FC_RED_LL | FC_RED_MDL | FC_RED_BDEU | FC_RED_MI))) {
+        set_error("fc_count_reduce: reducer mask %#x is empty or unknown", reducers);
+        return FC_ERR_INVALID;
+    }
+    const double ess = p ? p->ess : 1.0;
+    if (!(ess > 0.0)) {
+        set_error("fc_count_reduce: ess must be > 0");
+        return FC_ERR_INVALID;
+    }
+    if (nq > 0 && !scores) {
+        set_error("fc_count_reduce: scores is NULL");
+        return FC_ERR_INVALID;
+    }
+    if (!tables && table_off) {
+        set_error("fc_count_reduce: table_off given without tables");
+        return FC_ERR_INVALID;
+    }
+    Plan P;
+    if ((rc = build_plan(db, vars_flat, var_off, nq, table_off, flags, cells, P))) return rc;
+    if (nq == 0) return FC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    FC_HIP(hipSetDevice(db->device));
+    const int nred = __builtin_popcount(reducers);
+    const size_t sbytes = sizeof(float) * (size_t)nred * (size_t)nq;
+    const bool tdev = tables && is_device_ptr(tables);
+    const bool sdev = is_device_ptr(scores);
+    const bool edev = err && is_device_ptr(err);
+    DevBuf dt, ds, de;
+    int32_t *t = tables;
+    if (!tdev) {
+        FC_HIP(dt.alloc(sizeof(int32_t) * (size_t)P.total_cells, s));
+        t = (int32_t *)dt.p;
+        if (tables && !P.packed)
+            FC_HIP(hipMemcpyAsync(t, tables, sizeof(int32_t) * (size_t)P.total_cells,
+                                  hipMemcpyHostToDevice, s));
+    }
+    float *sc = scores, *er = err;
+    if (!sdev) {
+        FC_HIP(ds.alloc(sbytes, s));
+        sc = (float *)ds.p;
+    }
+    if (err && !edev) {
+        FC_HIP(de.alloc(sbytes, s));
+        er = (float *)de.p;
+    }
+    if ((rc = run_batch(db, P, t, reducers, ess, sc, er, s))) return rc;
+    bool sync = false;
+    if (tables && !tdev) {
+        FC_HIP(hipMemcpyAsync(tables, t, sizeof(int32_t) * (size_t)P.total_cells,
+                              hipMemcpyDeviceToHost, s));
+        sync = true;
+    }
+    if (!sdev) {
+        FC_HIP(hipMemcpyAsync(scores, sc, sbytes, hipMemcpyDeviceToHost, s));
+        sync = true;
+    }
+    if (err && !edev) {
+        FC_HIP(hipMemcpyAsync(err, er, sbytes, hipMemcpyDeviceToHost, s));
+        sync = true;
+    }
+    if (sync) FC_HIP(hipStreamSynchronize(s));
+    return FC_OK;
+}
+
+extern "C" int fc_count_assignment(fc_db *db, const int32_t *vars, const uint8_t *states,
+                                   int32_t k, int64_t *count, void *stream) {
+    clear_error();
+    if (!vars || !states || !count) {
+        set_error("fc_count_assignment: vars, states and count must not be NULL");
+        return FC_ERR_INVALID;
+    }
+    int64_t off[2] = {0, k};
+    std::vector<int64_t> c;
+    int rc = validate(db, vars, off, 1, nullptr, c);
+    if (rc) return rc;
+    for (int32_t t = 0; t < k; ++t)
+        if (states[t] >= db->arity[vars[t]]) {
+            set_error("fc_count_assignment: state %u of variable %d is not below its arity %u",
+                      states[t], vars[t], db->arity[vars[t]]);
+            return FC_ERR_INVALID;
+        }
+    hipStream_t s = (hipStream_t)stream;
+    FC_HIP(hipSetDevice(db->device));
+    DevBuf d;
+    FC_HIP(d.alloc(sizeof(unsigned long long), s));
+    FC_HIP(fill_zero_i32((int32_t *)d.p, 2, s));
+    if (db->m > 0) {
+        if (db->d_bits) {
+            Rows8 rows;
+            for (int32_t t = 0; t < FC_MAX_VARS; ++t)
+                rows.r[t] = t < k ? db->state_off[vars[t]] + states[t] : 0;
+            int64_t blocks = std::min<int64_t>((db->words + 255) / 256, 4 * db->cu_count);
+            hipLaunchKernelGGL(k_assign_bits, dim3((unsigned)blocks), dim3(256), 0, s, db->d_bits,
+                               db->words, rows, k, (unsigned long long *)d.p);
+        } else {
+            Assign8 a;
+            for (int32_t t = 0; t < FC_MAX_VARS; ++t) {
+                a.var[t] = t < k ? vars[t] : 0;
+                a.state[t] = t < k ? states[t] : 0;
+            }
+            int64_t blocks = std::min<int64_t>((db->m + 255) / 256, 4 * db->cu_count);
+            hipLaunchKernelGGL(k_assign_cols, dim3((unsigned)blocks), dim3(256), 0, s, db->d_cols,
+                               db->m, db->m_pad, a, k, (unsigned long long *)d.p);
+        }
+        FC_HIP(hipGetLastError());
+    }
+    unsigned long long h = 0;
+    FC_HIP(hipMemcpyAsync(&h, d.p, sizeof h, hipMemcpyDeviceToHost, s));
+    FC_HIP(hipStreamSynchronize(s));
+    *count = (int64_t)h;
+    return FC_OK;
+}
+
+extern "C" int fc_batch_footprint(const fc_db *db, const int32_t *vars_flat,
+                                  const int64_t *var_off, int64_t nq, uint32_t flags,
+                                  int64_t *bytes) {
+    clear_error();
+    if (!bytes) {
+        set_error("fc_batch_footprint: bytes is NULL");
+        return FC_ERR_INVALID;
+    }
+    std::vector<int64_t> cells;
+    int rc = validate(db, vars_flat, var_off, nq, nullptr, cells);
+    if (rc) return rc;
+    Plan P;
+    if ((rc = build_plan(db, vars_flat, var_off, nq, nullptr, flags, cells, P))) return rc;
+    *bytes = (int64_t)sizeof(int32_t) * P.total_cells +
+             (int64_t)sizeof(QDesc) * (int64_t)(P.work.size() + P.query.size()) +
+             (int64_t)sizeof(float) * 2 * 4 * nq;
+    return FC_OK;
+}

@@ -1,0 +1,356 @@
+// Device-resident database: state columns, per-state bit-vectors, marginals.
+//
+// The database of Section 2 is held column-major (as the Radix strategy of
+// Section 3.3 wants), one uint8 per state, each column padded to whole
+// 4096-row tiles.  Per-state bitmaps of Section 3.2 are stored as 64-bit
+// words, one row of words per (variable, state).  Per-variable marginal
+// counts (the precomputed first partition level of Section 3.3) and
+// entropies (the Bitmap traversal order of Section 3.2) are computed once.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "fc_internal.h"
+
+namespace fc {
+
+static thread_local std::string g_err;
+
+void set_error(const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+
+void clear_error() { g_err.clear(); }
+
+bool is_device_ptr(const void *p) {
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+__global__ void k_fill_zero_i32(int32_t *p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = 0;
+}
+
+hipError_t fill_zero_i32(int32_t *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_fill_zero_i32, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ staging pool
+static std::mutex g_stage_mu;
+static std::vector<Staging *> g_stage_free;
+
+Staging *staging_acquire(size_t bytes) {
+    Staging *st = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_stage_mu);
+        for (size_t i = 0; i < g_stage_free.size(); ++i)
+            if (g_stage_free[i]->cap >= bytes || i + 1 == g_stage_free.size()) {
+                st = g_stage_free[i];
+                g_stage_free.erase(g_stage_free.begin() + (long)i);
+                break;
+            }
+    }
+    if (!st) st = new (std::nothrow) Staging();
+    if (!st) return nullptr;
+    if (st->done) (void)hipEventSynchronize(st->done);  // previous copy out of it
+    if (st->cap < bytes) {
+        if (st->host) (void)hipHostFree(st->host);
+        st->host = nullptr;
+        st->cap = 0;
+        size_t cap = bytes < (1u << 20) ? (1u << 20) : bytes + bytes / 4;
+        if (hipHostMalloc(&st->host, cap, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            st->host = nullptr;
+            delete st;
+            return nullptr;
+        }
+        st->cap = cap;
+    }
+    if (!st->done && hipEventCreateWithFlags(&st->done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        st->done = nullptr;
+    }
+    return st;
+}
+
+void staging_release(Staging *st, hipStream_t s) {
+    if (!st) return;
+    if (st->done) (void)hipEventRecord(st->done, s);
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    g_stage_free.push_back(st);
+}
+
+// ------------------------------------------------------------ kernels
+// Row-major [m][n] -> column-major [n][m_pad] through an LDS tile.
+__global__ void k_transpose(const uint8_t *__restrict__ rm, int64_t m, int32_t n,
+                            uint8_t *__restrict__ cols, int64_t m_pad) {
+    __shared__ uint8_t tile[64][65];
+    int64_t p0 = (int64_t)blockIdx.x * 64;
+    int32_t v0 = blockIdx.y * 64;
+    int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+    for (int r = ty; r < 64; r += 4) {
+        int64_t p = p0 + r;
+        int32_t v = v0 + tx;
+        tile[r][tx] = (p < m && v < n) ? rm[p * n + v] : 0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        int32_t v = v0 + r;
+        int64_t p = p0 + tx;
+        if (v < n && p < m_pad) cols[(int64_t)v * m_pad + p] = tile[tx][r];
+    }
+}
+
+// Checks every state against its arity and counts the states of each
+// variable (the marginals).  One workgroup per (variable, row slab).
+__global__ void k_check_marg(const uint8_t *__restrict__ cols, int64_t m, int64_t m_pad,
+                             const uint8_t *__restrict__ arity, const int32_t *__restrict__ soff,
+                             int32_t *__restrict__ marg, int32_t *__restrict__ bad) {
+    __shared__ int32_t h[256];
+    int32_t v = blockIdx.y;
+    int r = arity[v];
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    const uint8_t *col = cols + (int64_t)v * m_pad;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int nbad = 0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += stride) {
+        int s = col[p];
+        if (s >= r) ++nbad;
+        atomicAdd(&h[s], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < r; i += blockDim.x)
+        if (h[i]) atomicAdd(&marg[soff[v] + i], h[i]);
+    if (nbad) atomicAdd(bad, nbad);
+}
+
+// Per-state bit-vectors: bit (p mod 64) of word p/64 of row (v, s) is set when
+// instance p of variable v is in state s.  One wave per 64-row word; padding
+// rows (p >= m) contribute no bits.
+__global__ void k_bitvectors(const uint8_t *__restrict__ cols, int64_t m, int64_t m_pad,
+                             int64_t words, const uint8_t *__restrict__ arity,
+                             const int32_t *__restrict__ soff, uint64_t *__restrict__ bits) {
+    int32_t v = blockIdx.y;
+    int lane = threadIdx.x & 63;
+    int64_t w = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    if (w >= words) return;
+    int64_t p = w * 64 + lane;
+    int s = (p < m) ? cols[(int64_t)v * m_pad + p] : 255;
+    int r = arity[v];
+    uint64_t *row = bits + (int64_t)soff[v] * words + w;
+    for (int st = 0; st < r; ++st) {
+        uint64_t b = __ballot(s == st);
+        if (lane == (st & 63)) row[(int64_t)st * words] = b;
+    }
+}
+
+}  // namespace fc
+
+using namespace fc;
+
+extern "C" const char *fc_last_error(void) { return g_err.c_str(); }
+
+extern "C" void fc_db_destroy(fc_db *db) {
+    if (!db) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(db->device);
+    (void)hipDeviceSynchronize();
+    if (db->d_cols) (void)hipFree(db->d_cols);
+    if (db->d_bits) (void)hipFree(db->d_bits);
+    if (db->d_arity) (void)hipFree(db->d_arity);
+    if (db->d_soff) (void)hipFree(db->d_soff);
+    if (db->d_marg) (void)hipFree(db->d_marg);
+    (void)hipSetDevice(cur);
+    delete db;
+}
+
+namespace {
+struct DbGuard {
+    fc_db *db;
+    ~DbGuard() {
+        if (db) fc_db_destroy(db);
+    }
+};
+}  // namespace
+
+static int db_alloc(void **p, size_t bytes, fc_db *db) {
+    hipError_t e = hipMalloc(p, bytes ? bytes : 16);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        set_error("device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+        return FC_ERR_NOMEM;
+    }
+    db->device_bytes += (int64_t)bytes;
+    return FC_OK;
+}
+
+extern "C" int fc_db_create(const uint8_t *data, int64_t m, int32_t n, const uint8_t *arity,
+                            int32_t layout, uint32_t flags, void *stream, fc_db **out) {
+    clear_error();
+    if (!out) {
+        set_error("fc_db_create: out is NULL");
+        return FC_ERR_INVALID;
+    }
+    *out = nullptr;
+    if (n < 1 || m < 0 || !arity || (m > 0 && !data)) {
+        set_error("fc_db_create: need n >= 1, m >= 0, arity and data (n=%d m=%lld)", n,
+                  (long long)m);
+        return FC_ERR_INVALID;
+    }
+    if (m >= (int64_t(1) << 31)) {
+        set_error("fc_db_create: m=%lld does not fit int32 counts", (long long)m);
+        return FC_ERR_RANGE;
+    }
+    if (layout != FC_COL_MAJOR && layout != FC_ROW_MAJOR) {
+        set_error("fc_db_create: unknown layout %d", layout);
+        return FC_ERR_INVALID;
+    }
+    for (int32_t v = 0; v < n; ++v)
+        if (arity[v] == 0) {
+            set_error("fc_db_create: variable %d has arity 0", v);
+            return FC_ERR_INVALID;
+        }
+    hipStream_t s = (hipStream_t)stream;
+    fc_db *db = new (std::nothrow) fc_db();
+    if (!db) {
+        set_error("fc_db_create: host allocation failed");
+        return FC_ERR_NOMEM;
+    }
+    DbGuard guard{db};
+    FC_HIP(hipGetDevice(&db->device));
+    FC_HIP(hipDeviceGetAttribute(&db->cu_count, hipDeviceAttributeMultiprocessorCount, db->device));
+    db->m = m;
+    db->n = n;
+    db->m_pad = ((m + kTileRows - 1) / kTileRows) * kTileRows;
+    if (db->m_pad == 0) db->m_pad = kTileRows;
+    db->words = db->m_pad / 64;
+    db->arity.assign(arity, arity + n);
+    db->state_off.resize((size_t)n + 1);
+    db->state_off[0] = 0;
+    for (int32_t v = 0; v < n; ++v) db->state_off[v + 1] = db->state_off[v] + arity[v];
+    const int32_t sum_r = db->state_off[n];
+
+    int rc;
+    if ((rc = db_alloc((void **)&db->d_cols, (size_t)n * (size_t)db->m_pad, db))) return rc;
+    if ((rc = db_alloc((void **)&db->d_arity, (size_t)n, db))) return rc;
+    if ((rc = db_alloc((void **)&db->d_soff, sizeof(int32_t) * ((size_t)n + 1), db))) return rc;
+    if ((rc = db_alloc((void **)&db->d_marg, sizeof(int32_t) * (size_t)sum_r, db))) return rc;
+    FC_HIP(hipMemcpyAsync(db->d_arity, arity, (size_t)n, hipMemcpyHostToDevice, s));
+    FC_HIP(hipMemcpyAsync(db->d_soff, db->state_off.data(), sizeof(int32_t) * ((size_t)n + 1),
+                          hipMemcpyHostToDevice, s));
+    FC_HIP(fill_zero_i32(db->d_marg, sum_r, s));
+    // padding rows hold state 0 (removed from every count arithmetically)
+    FC_HIP(fill_zero_i32((int32_t *)db->d_cols, (int64_t)n * db->m_pad / 4, s));
+
+    const bool on_dev = (flags & FC_DB_DATA_ON_DEVICE) != 0;
+    if (m > 0) {
+        if (layout == FC_COL_MAJOR) {
+            FC_HIP(hipMemcpy2DAsync(db->d_cols, (size_t)db->m_pad, data, (size_t)m, (size_t)m,
+                                    (size_t)n,
+                                    on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+        } else {
+            const uint8_t *src = data;
+            DevBuf tmp;
+            if (!on_dev) {
+                FC_HIP(tmp.alloc((size_t)m * (size_t)n, s));
+                FC_HIP(hipMemcpyAsync(tmp.p, data, (size_t)m * (size_t)n, hipMemcpyHostToDevice,
+                                      s));
+                src = (const uint8_t *)tmp.p;
+            }
+            dim3 grid((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64));
+            hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, s, src, m, n, db->d_cols,
+                               db->m_pad);
+            FC_HIP(hipGetLastError());
+            FC_HIP(hipStreamSynchronize(s));  // tmp is freed on s after this
+        }
+    }
+    // validation + marginals
+    DevBuf bad;
+    FC_HIP(bad.alloc(sizeof(int32_t), s));
+    FC_HIP(fill_zero_i32((int32_t *)bad.p, 1, s));
+    if (m > 0) {
+        int64_t slabs = (m + 65535) / 65536;
+        if (slabs > 64) slabs = 64;
+        hipLaunchKernelGGL(k_check_marg, dim3((unsigned)slabs, (unsigned)n), dim3(256), 0, s,
+                           db->d_cols, m, db->m_pad, db->d_arity, db->d_soff, db->d_marg,
+                           (int32_t *)bad.p);
+        FC_HIP(hipGetLastError());
+    }
+    int32_t nbad = 0;
+    std::vector<int32_t> marg32((size_t)sum_r);
+    FC_HIP(hipMemcpyAsync(&nbad, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    FC_HIP(hipMemcpyAsync(marg32.data(), db->d_marg, sizeof(int32_t) * (size_t)sum_r,
+                          hipMemcpyDeviceToHost, s));
+    FC_HIP(hipStreamSynchronize(s));
+    if (nbad) {
+        set_error("fc_db_create: %d states are not below their variable's arity "
+                  "(the database must be complete)", nbad);
+        return FC_ERR_INVALID;
+    }
+    db->marg.assign(marg32.begin(), marg32.end());
+    db->entropy.assign((size_t)n, 0.0f);
+    for (int32_t v = 0; v < n; ++v) {
+        double h = 0.0;
+        for (int st = 0; st < arity[v] && m > 0; ++st) {
+            double pr = (double)db->marg[db->state_off[v] + st] / (double)m;
+            if (pr > 0) h -= pr * std::log2(pr);
+        }
+        db->entropy[v] = (float)h;
+    }
+    if (flags & FC_DB_BITVECTORS) {
+        size_t bytes = sizeof(uint64_t) * (size_t)sum_r * (size_t)db->words;
+        if ((rc = db_alloc((void **)&db->d_bits, bytes, db))) return rc;
+        dim3 grid((unsigned)((db->words + 3) / 4), (unsigned)n);
+        hipLaunchKernelGGL(k_bitvectors, grid, dim3(256), 0, s, db->d_cols, m, db->m_pad,
+                           db->words, db->d_arity, db->d_soff, db->d_bits);
+        FC_HIP(hipGetLastError());
+        FC_HIP(hipStreamSynchronize(s));
+    }
+    *out = db;
+    guard.db = nullptr;
+    return FC_OK;
+}
+
+extern "C" int fc_db_info(const fc_db *db, int64_t *m, int32_t *n, int32_t *has_bits,
+                          int64_t *device_bytes) {
+    if (!db) {
+        set_error("fc_db_info: NULL handle");
+        return FC_ERR_INVALID;
+    }
+    if (m) *m = db->m;
+    if (n) *n = db->n;
+    if (has_bits) *has_bits = db->d_bits != nullptr;
+    if (device_bytes) *device_bytes = db->device_bytes;
+    return FC_OK;
+}
+
+extern "C" int fc_db_marginals(const fc_db *db, int64_t *counts, float *entropy_bits) {
+    if (!db) {
+        set_error("fc_db_marginals: NULL handle");
+        return FC_ERR_INVALID;
+    }
+    if (counts) std::memcpy(counts, db->marg.data(), sizeof(int64_t) * db->marg.size());
+    if (entropy_bits) std::memcpy(entropy_bits, db->entropy.data(), sizeof(float) * db->n);
+    return FC_OK;
+}

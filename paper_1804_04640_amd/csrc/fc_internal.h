@@ -1,0 +1,116 @@
+// Internal declarations of the fastcount library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fastcount.h"
+
+namespace fc {
+
+// Rows are stored in tiles of this many instances; every column is padded to
+// a whole number of tiles with state 0 and the padding is removed from the
+// counts arithmetically (it always lands in key 0).
+constexpr int64_t kTileRows = 4096;
+constexpr int kWaves = 4;            // waves per counting workgroup
+constexpr int kBlock = 64 * kWaves;  // threads per counting workgroup
+constexpr int kXcds = 8;             // MI355X: 8 XCDs, workgroups round-robin
+constexpr int kLdsBytesMax = 160 * 1024;
+
+// Work descriptor of one counting unit (one query, or one key window of a
+// partitioned query).  64 bytes, read once per workgroup.
+struct alignas(16) QDesc {
+    int64_t table_off;  // cell offset of the query's table
+    int32_t var[FC_MAX_VARS];
+    int32_t cells;      // cells of the whole table
+    int32_t k;          // variables in the query
+    int32_t win_base;   // first key of the window (0 when not partitioned)
+    int32_t win_cells;  // keys in the window
+    int32_t qid;        // query index in the caller's batch
+    int32_t pad;
+};
+static_assert(sizeof(QDesc) == 64, "QDesc must be 64 bytes");
+
+struct Tuning {
+    int64_t chunk_rows = 0;   // 0: automatic
+    int bitmap_max_cells = 16;
+    int bitmap_words = 2;     // 64-row words per thread per tree walk
+    int hist_min_chunks = 0;  // 0: automatic
+};
+
+}  // namespace fc
+
+struct fc_db {
+    int device = 0;
+    int cu_count = 256;
+    int64_t m = 0, m_pad = 0, words = 0;
+    int32_t n = 0;
+    std::vector<uint8_t> arity;      // n
+    std::vector<int32_t> state_off;  // n+1, prefix sums of arities
+    std::vector<int64_t> marg;       // sum of arities
+    std::vector<float> entropy;      // n, bits
+    uint8_t *d_cols = nullptr;       // [n][m_pad] states
+    uint64_t *d_bits = nullptr;      // [sum r][words] per-state bit-vectors
+    uint8_t *d_arity = nullptr;      // [n]
+    int32_t *d_soff = nullptr;       // [n+1]
+    int32_t *d_marg = nullptr;       // [sum r]
+    int64_t device_bytes = 0;
+    fc::Tuning tune;
+};
+
+namespace fc {
+
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define FC_HIP(call)                                                        \
+    do {                                                                    \
+        hipError_t e_ = (call);                                             \
+        if (e_ != hipSuccess) {                                             \
+            ::fc::set_error("%s: %s", #call, hipGetErrorString(e_));        \
+            return FC_ERR_DEVICE;                                           \
+        }                                                                   \
+    } while (0)
+
+// Device pointer test (torch tensors, hipMalloc); host memory otherwise.
+bool is_device_ptr(const void *p);
+
+// Zero `n` int32 values with a kernel (graph-capture safe, no memset node).
+hipError_t fill_zero_i32(int32_t *p, int64_t n, hipStream_t s);
+
+// Stream-ordered scratch owned by one call.
+struct DevBuf {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() {
+        if (p) (void)hipFreeAsync(p, s);
+    }
+    hipError_t alloc(size_t bytes, hipStream_t st) {
+        s = st;
+        return hipMallocAsync(&p, bytes ? bytes : 16, st);
+    }
+};
+
+// Pinned host staging buffers, reused across calls; one per concurrent call.
+struct Staging {
+    void *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;  // last H2D copy out of this buffer
+};
+Staging *staging_acquire(size_t bytes);
+void staging_release(Staging *st, hipStream_t s);
+
+// Reducer launch (fc_reduce.hip).  descs: one QDesc per query (device).
+hipError_t launch_reduce(const fc_db *db, const QDesc *descs, int64_t nq,
+                         const int32_t *tables, uint32_t reducers, double ess,
+                         float *scores, float *err, hipStream_t s);
+
+}  // namespace fc

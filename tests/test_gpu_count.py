@@ -1,0 +1,160 @@
+"""GPU parity: tables of every strategy are bit-identical to the CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as orc
+from paper_1804_04640_amd import _lib, synth
+from paper_1804_04640_amd.api import Database
+from tests.golden_io import fig1_database, fig1_expected
+
+pytestmark = pytest.mark.gpu
+
+
+def check_tables(w, tables, toff, idx=None):
+    T = tables.cpu().numpy() if isinstance(tables, torch.Tensor) else tables
+    for i in (range(w.nq) if idx is None else idx):
+        q = w.query(i)
+        ref = orc.count(w.D, w.arity, q)
+        got = T[toff[i]:toff[i] + len(ref)]
+        assert np.array_equal(ref, got), "query %d vars %s" % (i, list(q))
+
+
+def test_fig1_example():
+    D, ar = fig1_database()
+    with Database(D, ar) as db:
+        T = db.count([0, 2, 1])
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(T.cpu().numpy(), fig1_expected()["table"])
+        assert db.count_assignment([0, 1, 2], [2, 1, 0]) == 2
+
+
+@pytest.mark.parametrize("strategy", ["auto", "hist", "bitmap", "partition"])
+def test_cfg1_full_batch(strategy):
+    w = synth.cfg1()
+    print("cfg1 strategy=%s nq=%d m=%d" % (strategy, w.nq, w.m), flush=True)
+    with Database(w.D, w.arity) as db:
+        tables, toff = db.count_batch((w.vars_flat, w.var_off), strategy=strategy)
+        torch.cuda.synchronize()
+        check_tables(w, tables, toff)
+
+
+def test_cfg1_per_query_path():
+    w = synth.cfg1()
+    with Database(w.D, w.arity) as db:
+        for i in range(0, w.nq, 7):
+            q = w.query(i)
+            np.testing.assert_array_equal(db.count(q).cpu().numpy(), orc.count(w.D, w.arity, q))
+
+
+@pytest.mark.parametrize("strategy", ["auto", "hist", "bitmap", "partition"])
+def test_cfg2_small_strategies(strategy):
+    w = synth.cfg2(m=100_003, nq=400)        # ragged tail: m is not a tile multiple
+    print("cfg2-small strategy=%s" % strategy, flush=True)
+    with Database(w.D, w.arity) as db:
+        tables, toff = db.count_batch((w.vars_flat, w.var_off), strategy=strategy)
+        torch.cuda.synchronize()
+        check_tables(w, tables, toff)
+
+
+def test_cfg3_small_auto_and_host_output():
+    w = synth.cfg3(m=60_001, nq=300)
+    with Database(w.D, w.arity) as db:
+        tables, toff = db.count_batch((w.vars_flat, w.var_off))
+        torch.cuda.synchronize()
+        check_tables(w, tables, toff)
+        # host output buffer (numpy): the call stages and synchronises
+        host = np.full(int(toff[-1]), -7, np.int32)
+        _lib.fc_count_batch(db.handle, w.vars_flat.ctypes.data, w.var_off.ctypes.data, w.nq,
+                            host.ctypes.data, 0, 0, 0)
+        check_tables(w, host, toff)
+
+
+def test_large_table_partition_path():
+    # 6 variables of arity 8: 262144 cells > LDS, so the MSD partition runs
+    rng = np.random.default_rng(7)
+    m = 70_001
+    ar = np.full(6, 8, np.uint8)
+    D = rng.integers(0, 8, size=(6, m)).astype(np.uint8)
+    with Database(D, ar) as db:
+        for vs in ([0, 1, 2, 3, 4, 5], [5, 3, 1, 0, 2, 4]):
+            got = db.count(vs).cpu().numpy()
+            np.testing.assert_array_equal(got, orc.count(D, ar, vs))
+
+
+def test_batch_equals_alone():
+    w = synth.cfg3(m=30_000, nq=200)
+    with Database(w.D, w.arity) as db:
+        tables, toff = db.count_batch((w.vars_flat, w.var_off))
+        T = tables.cpu().numpy()
+        for i in range(0, w.nq, 9):
+            alone = db.count(w.query(i)).cpu().numpy()
+            np.testing.assert_array_equal(T[toff[i]:toff[i + 1]], alone)
+
+
+def test_repeat_runs_identical():
+    w = synth.cfg2(m=50_000, nq=300)
+    with Database(w.D, w.arity) as db:
+        a, _ = db.count_batch((w.vars_flat, w.var_off))
+        b, _ = db.count_batch((w.vars_flat, w.var_off))
+        assert torch.equal(a, b)
+
+
+def test_edge_cases():
+    # empty database, k = 1, arity 1, m smaller than a tile
+    D = np.zeros((3, 0), np.uint8)
+    ar = np.array([2, 3, 1], np.uint8)
+    with Database(D, ar) as db:
+        assert db.count([0, 1]).cpu().numpy().tolist() == [0] * 6
+    rng = np.random.default_rng(3)
+    D = np.stack([rng.integers(0, 2, 5), np.zeros(5), rng.integers(0, 255, 5)]).astype(np.uint8)
+    ar = np.array([2, 1, 255], np.uint8)
+    with Database(D, ar) as db:
+        for vs in ([1], [0, 1], [2], [2, 0, 1]):
+            np.testing.assert_array_equal(db.count(vs).cpu().numpy(), orc.count(D, ar, vs))
+
+
+def test_validation_errors_name_the_query():
+    w = synth.cfg1()
+    with Database(w.D, w.arity) as db:
+        bad = [[0, 1], [2, 2], [3]]
+        with pytest.raises(_lib.FastcountError) as e:
+            db.count_batch(bad)
+        assert e.value.code == _lib.FC_ERR_INVALID and "query 1" in str(e.value)
+        with pytest.raises(_lib.FastcountError):
+            db.count_batch([[0, 99]])
+        with pytest.raises(_lib.FastcountError):
+            db.count_batch([list(range(9))])
+    with pytest.raises(_lib.FastcountError) as e:
+        Database(np.array([[0, 3]], np.uint8), np.array([3], np.uint8))
+    assert "arity" in str(e.value)
+
+
+def test_row_major_and_device_input():
+    w = synth.cfg1(m=5000, nq=50)
+    with Database(np.ascontiguousarray(w.D.T), w.arity, layout="row") as db:
+        tables, toff = db.count_batch((w.vars_flat, w.var_off))
+        check_tables(w, tables, toff)
+    with Database(torch.from_numpy(w.D).cuda(), w.arity) as db:
+        tables, toff = db.count_batch((w.vars_flat, w.var_off))
+        check_tables(w, tables, toff)
+
+
+def test_marginals_and_assignment():
+    w = synth.cfg2(m=40_000, nq=10)
+    with Database(w.D, w.arity) as db:
+        cnt, ent = db.marginals()
+        off = 0
+        for v in range(w.n):
+            np.testing.assert_array_equal(cnt[off:off + w.arity[v]],
+                                          np.bincount(w.D[v], minlength=w.arity[v]))
+            off += w.arity[v]
+        rng = np.random.default_rng(0)
+        for _ in range(20):
+            k = int(rng.integers(1, 6))
+            vs = rng.choice(w.n, k, replace=False)
+            st = [int(rng.integers(0, w.arity[v])) for v in vs]
+            assert db.count_assignment(vs, st) == orc.count_assignment(w.D, w.arity, vs, st)
+    with Database(w.D, w.arity, bitvectors=False) as db:
+        assert db.count_assignment([0, 1], [0, 0]) == orc.count_assignment(w.D, w.arity, [0, 1],
+                                                                           [0, 0])
