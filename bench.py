@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Benchmark of the counting hot path on one MI355X.
+
+One step = one batch of counting queries through the whole path: plan and
+upload, count every query's contingency table (bitmap / histogram /
+partition kernels), stream the tables into the fused reducers, scores left
+on the device.  The database is resident in HBM before timing starts.
+
+Default workload: BN-family scoring -- n=37 variables with arities U{2,3,4},
+m=1,000,000 instances forward-sampled from a random DAG (in-degree <= 4,
+Dirichlet(1) CPTs), 50,000 family queries (child + 0..4 parents), fused MDL.
+
+The JSON line carries query-rows/s (sum over queries of m per second), the
+batched vs per-query comparison, p50/p99 latencies, the dominant kernel's
+roofline figures (measured with HIP events on the launch stream) and the CPU
+oracle timed on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import hashlib
+import glob
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA
+
+
+def src_hash() -> str:
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1804_04640_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def workload(name: str):
+    from paper_1804_04640_amd import synth
+    if name == "cfg2":
+        return synth.cfg2(), ("mdl",)
+    if name == "cfg1":
+        return synth.cfg1(), ("mdl",)
+    if name == "cfg3":
+        return synth.cfg3(), ("bdeu", "mi")
+    if name == "cfg5":
+        return synth.cfg5(), ("mdl",)
+    raise SystemExit("unknown workload %s" % name)
+
+
+def percentile(xs, p):
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), p)) if len(xs) else None
+
+
+def cpu_baseline(w, reducers, budget_s: float):
+    """The CPU oracle, as it stands, on a bounded sample of the same queries,
+    one query per thread (query-level parallelism)."""
+    from oracle import oracle as orc
+
+    def one(i):
+        q = w.query(i)
+        T = orc.count(w.D, w.arity, q)
+        r = int(w.arity[q[-1]])
+        return [orc.score(name, T, r, w.ess) for name in reducers]
+
+    t0 = time.perf_counter()
+    probe = 8
+    for i in range(probe):
+        one(i)
+    per_q = (time.perf_counter() - t0) / probe
+    threads = max(1, min(16, os.cpu_count() or 1))
+    sample = int(min(w.nq, max(64, budget_s / max(per_q, 1e-6))))
+    ids = list(range(sample))
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(one, ids))
+    dt = time.perf_counter() - t0
+    return {"value": sample * w.m / dt, "unit": "query-rows/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "first %d of %d queries (m=%d), count + %s, %d threads, %.1f s wall"
+                      % (sample, w.nq, w.m, "+".join(reducers), threads, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg5"])
+    ap.add_argument("--strategy", default="auto", choices=["auto", "hist", "bitmap", "partition"])
+    ap.add_argument("--per-query", type=int, default=2000,
+                    help="queries timed on the plain per-query path (0: skip)")
+    ap.add_argument("--cpu-budget", type=float, default=15.0,
+                    help="seconds of single-thread oracle work in the CPU baseline (0: skip)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (counter scale)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration << 20
+        a = torch.ones(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "launches": 3}))
+        return
+    if args.gpus != 1:
+        print("bench.py: this build runs on exactly one GPU; --gpus %d is not supported "
+              "(sharding across GPUs is a design note only)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1804_04640_amd import _lib
+    from paper_1804_04640_amd.api import Database
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    w, reducers = workload(args.workload)
+    print("# workload %s generated in %.1fs: %s" % (w.name, time.time() - t0, w.desc),
+          file=sys.stderr, flush=True)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        db = Database(w.D, w.arity, stream=stream)
+        q = (w.vars_flat, w.var_off)
+        nq = w.nq
+        ks = np.diff(w.var_off)
+        rows = float(nq) * w.m
+        alg_bytes = float(ks.sum()) * w.m
+        scores = torch.empty(len(reducers) * nq, dtype=torch.float32, device="cuda")
+        errs = torch.empty_like(scores)
+
+        def step():
+            db.count_reduce(q, reducers, ess=w.ess, strategy=args.strategy, out=scores,
+                            err_out=errs, stream=stream)
+
+        for _ in range(args.warmup):
+            step()
+        stream.synchronize()
+        print("# warmup done", file=sys.stderr, flush=True)
+        _lib.fc_profile_enable(True)
+        _lib.fc_profile_read(reset=True)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for a, b in evs:
+            a.record(stream)
+            step()
+            b.record(stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        _lib.fc_profile_enable(False)
+        prof = _lib.fc_profile_read(reset=True)
+        step_ms = [a.elapsed_time(b) for a, b in evs]
+        print("# timed %d steps: %.2f ms/step (wall)" % (args.steps, 1e3 * wall / args.steps),
+              file=sys.stderr, flush=True)
+
+        # plain per-query path: one call (one counting launch + reduce) per query
+        per_query = None
+        if args.per_query > 0:
+            n = min(args.per_query, nq)
+            lat = []
+            one = torch.empty(len(reducers), dtype=torch.float32, device="cuda")
+            for i in range(min(20, n)):                       # warm the path
+                db.count_reduce([w.query(i)], reducers, ess=w.ess, out=one, with_err=False,
+                                stream=stream)
+            stream.synchronize()
+            t1 = time.perf_counter()
+            for i in range(n):
+                s0 = time.perf_counter()
+                db.count_reduce([w.query(i)], reducers, ess=w.ess, out=one, with_err=False,
+                                stream=stream)
+                stream.synchronize()
+                lat.append(1e3 * (time.perf_counter() - s0))
+            dt = time.perf_counter() - t1
+            per_query = {"value": n * w.m / dt, "unit": "query-rows/s",
+                         "sample": "first %d queries, one call each, synchronised" % n,
+                         "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99)}
+
+    ms = float(np.mean(step_ms))
+    value = rows / (ms * 1e-3)
+    # dominant kernel: the one with the largest summed time
+    dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    counting = {k: v for k, v in prof.items() if v["alg_bytes"] > 0}
+    c_ms = sum(v["ms"] for v in counting.values())
+    c_bytes = sum(v["alg_bytes"] for v in counting.values())
+    achieved = dom["alg_bytes"] / (dom["ms"] * 1e-3) / 1e9 if dom["ms"] > 0 else 0.0
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tfile):
+        try:
+            tj = json.load(open(tfile))
+            ent = tj.get(args.workload, {}).get(dom_name)
+            if ent and ent.get("src_hash") == src_hash():
+                traffic = ent["bytes_per_launch"]
+        except Exception:
+            traffic = None
+    out = {
+        "metric": "exact query-rows counted/s + HBM GB/s frac; batched vs per-query; p50/p99 ms",
+        "value": value,
+        "unit": "query-rows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8 states, int32 counts, f32 reducers",
+        "data": "synthetic",
+        "config": {"workload": w.name, "desc": w.desc, "queries": nq, "m": w.m, "n": w.n,
+                   "reducers": list(reducers), "strategy": args.strategy,
+                   "parallelism": "single GPU"},
+        "batched": {"p50_ms": percentile(step_ms, 50), "p99_ms": percentile(step_ms, 99),
+                    "effective_GBps": alg_bytes / (ms * 1e-3) / 1e9,
+                    "effective_hbm_frac": alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "counting_kernels_GBps": c_bytes / (c_ms * 1e-3) / 1e9 if c_ms else None,
+                    "kernels": {k: {"launches": v["launches"], "avg_us": 1e3 * v["ms"] / v["launches"],
+                                    "share": v["ms"] / sum(x["ms"] for x in prof.values())}
+                                for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}},
+        "per_query": per_query,
+        "batched_vs_per_query": (value / per_query["value"]) if per_query else None,
+        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "avg_launch_us": 1e3 * dom["ms"] / dom["launches"],
+                     "alg_bytes_per_launch": dom["alg_bytes"] / dom["launches"],
+                     "traffic": traffic},
+        "cpu_baseline": None,
+    }
+    if args.cpu_budget > 0:
+        out["cpu_baseline"] = cpu_baseline(w, reducers, args.cpu_budget)
+    db.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -208,6 +208,31 @@ int fc_batch_footprint(const fc_db *db, const int32_t *vars_flat,
                        const int64_t *var_off, int64_t nq, uint32_t flags,
                        int64_t *bytes);
 
+/*
+ * Launch profiling (observability).  While enabled, the library brackets
+ * every kernel launch with a pair of HIP events on the launch's stream and
+ * attributes to it the algorithmic work it performs: bytes of state columns
+ * a column scan must read (k bytes per query and instance) for counting
+ * kernels, and 2 m n^2 integer operations for the co-occurrence Gram.
+ */
+typedef struct fc_kernel_stat {
+    char name[48];     /* kernel instance, e.g. "k_hist<3,1>"              */
+    int64_t launches;  /* launches timed since the last reset              */
+    double ms;         /* summed event-measured duration                   */
+    double alg_bytes;  /* summed algorithmic bytes                         */
+    double alg_ops;    /* summed algorithmic integer operations            */
+} fc_kernel_stat;
+
+/* Turn launch profiling on (1) or off (0) for the whole process. */
+int fc_profile_enable(int on);
+
+/*
+ * Synchronise the recorded events and write up to `cap` per-kernel
+ * aggregates to `out`; returns the number of distinct kernels (which may
+ * exceed cap) or a negative FC_ERR_* code.  reset != 0 clears the totals.
+ */
+int fc_profile_read(fc_kernel_stat *out, int32_t cap, int32_t reset);
+
 /* Message of the last failed call on this host thread ("" if none). */
 const char *fc_last_error(void);
 

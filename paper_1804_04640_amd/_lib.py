@@ -34,7 +34,7 @@ FC_RED_MI = 8
 # every symbol the header declares
 EXPORTS = ("fc_db_create", "fc_db_destroy", "fc_db_info", "fc_db_marginals", "fc_table_cells",
            "fc_count", "fc_count_assignment", "fc_count_batch", "fc_count_reduce", "fc_pairs",
-           "fc_batch_footprint", "fc_last_error")
+           "fc_batch_footprint", "fc_profile_enable", "fc_profile_read", "fc_last_error")
 
 
 class FastcountError(RuntimeError):
@@ -45,6 +45,11 @@ class FastcountError(RuntimeError):
 
 class fc_reduce_params(ctypes.Structure):
     _fields_ = [("ess", ctypes.c_double)]
+
+
+class fc_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("alg_bytes", ctypes.c_double), ("alg_ops", ctypes.c_double)]
 
 
 class fc_pair_rec(ctypes.Structure):
@@ -81,6 +86,8 @@ def load():
             "fc_count_reduce": (ctypes.c_int, [P, P, P, i64, u32, P, P, P, P, P, u32, P]),
             "fc_pairs": (ctypes.c_int, [P, P, i32, ctypes.c_double, P, P, i64, P, P]),
             "fc_batch_footprint": (ctypes.c_int, [P, P, P, i64, u32, P]),
+            "fc_profile_enable": (ctypes.c_int, [ctypes.c_int]),
+            "fc_profile_read": (ctypes.c_int, [P, i32, i32]),
             "fc_last_error": (ctypes.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -158,3 +165,20 @@ def fc_batch_footprint(db, vars_flat, var_off, nq, flags):
     b = ctypes.c_int64()
     check(load().fc_batch_footprint(db, vars_flat, var_off, nq, flags, ctypes.byref(b)))
     return b.value
+
+
+def fc_profile_enable(on):
+    return check(load().fc_profile_enable(1 if on else 0))
+
+
+def fc_profile_read(reset=True):
+    """Per-kernel aggregates since the last reset: {name: dict}."""
+    n = check(load().fc_profile_read(None, 0, 0))
+    arr = (fc_kernel_stat * max(n, 1))()
+    n = check(load().fc_profile_read(ctypes.addressof(arr), n, 1 if reset else 0))
+    out = {}
+    for i in range(min(n, len(arr))):
+        s = arr[i]
+        out[s.name.decode()] = {"launches": int(s.launches), "ms": float(s.ms),
+                                "alg_bytes": float(s.alg_bytes), "alg_ops": float(s.alg_ops)}
+    return out

@@ -18,6 +18,7 @@
 // Partial tables of row chunks are summed into the output with int32
 // atomics, which is exact and order independent.
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 
 #include "fc_internal.h"
@@ -234,6 +235,8 @@ __global__ void k_assign_cols(const uint8_t *__restrict__ cols, int64_t m, int64
 enum Strat { S_HIST = 1, S_BITMAP = 2, S_PART = 3 };
 
 struct Launch {
+    char name[32];    // kernel instance (profiling)
+    double alg_bytes; // k bytes per query and instance, summed
     int strat;
     int K;
     bool small;
@@ -419,6 +422,15 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
                         L.lds_bytes = (int32_t)(maxc * kBlock * 4);
                     else
                         L.lds_bytes = kClassLds[cls];
+                    double bytes = 0.0;
+                    for (auto &d : b)
+                        bytes += (double)d.k * (double)db->m * ((double)d.win_cells / (double)d.cells);
+                    L.alg_bytes = bytes;
+                    if (st == S_BITMAP)
+                        snprintf(L.name, sizeof L.name, "k_bitmap<%d,%d>", K,
+                                 db->tune.bitmap_words >= 4 ? 4 : db->tune.bitmap_words == 2 ? 2 : 1);
+                    else
+                        snprintf(L.name, sizeof L.name, "k_hist<%d,%d>", K, sm);
                     P.work.insert(P.work.end(), b.begin(), b.end());
                     P.launches.push_back(L);
                 }
@@ -560,9 +572,16 @@ static int run_batch(fc_db *db, Plan &P, int32_t *tables, uint32_t reducers, dou
         FC_HIP(hipGetLastError());
     }
     if (db->m > 0)
-        for (const Launch &L : P.launches) FC_HIP(launch_count(db, L, dw, tables, s));
-    if (reducers && nqd)
+        for (const Launch &L : P.launches) {
+            ProfScope ps(L.name, s, L.alg_bytes, 0.0);
+            FC_HIP(launch_count(db, L, dw, tables, s));
+            ps.end(s);
+        }
+    if (reducers && nqd) {
+        ProfScope ps("k_reduce", s, 0.0, 0.0);
         FC_HIP(launch_reduce(db, dw + nw, (int64_t)nqd, tables, reducers, ess, scores, err, s));
+        ps.end(s);
+    }
     return FC_OK;
 }
 

@@ -108,6 +108,14 @@ struct Staging {
 Staging *staging_acquire(size_t bytes);
 void staging_release(Staging *st, hipStream_t s);
 
+// Launch profiling: RAII bracket of one launch with events on its stream.
+bool profiling_on();
+struct ProfScope {
+    int slot = -1;
+    ProfScope(const char *name, hipStream_t s, double alg_bytes, double alg_ops);
+    void end(hipStream_t s);
+};
+
 // Reducer launch (fc_reduce.hip).  descs: one QDesc per query (device).
 hipError_t launch_reduce(const fc_db *db, const QDesc *descs, int64_t nq,
                          const int32_t *tables, uint32_t reducers, double ess,
