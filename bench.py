@@ -53,6 +53,8 @@ def workload(name: str):
         return synth.cfg3(), ("bdeu", "mi")
     if name == "cfg5":
         return synth.cfg5(), ("mdl",)
+    if name == "cfg4":
+        return synth.cfg4(), ()
     raise SystemExit("unknown workload %s" % name)
 
 
@@ -89,17 +91,82 @@ def cpu_baseline(w, reducers, budget_s: float):
                       % (sample, w.nq, w.m, "+".join(reducers), threads, dt)}
 
 
+def bench_pairs(args, w):
+    """All-pairs co-occurrence: one step = Gram on MFMA + pair records."""
+    import torch
+    from oracle import oracle as orc
+    from paper_1804_04640_amd import _lib
+    from paper_1804_04640_amd.api import Database
+
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        db = Database(w.D, w.arity, stream=stream)
+        n, m = w.n, w.m
+        cap = n * (n - 1) // 2
+
+        def step():
+            return db.pairs(w.minsup, cap=cap, stream=stream)
+
+        for _ in range(args.warmup):
+            recs, _, total = step()
+        _lib.fc_profile_enable(True)
+        _lib.fc_profile_read(reset=True)
+        times = []
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            recs, _, total = step()
+            torch.cuda.synchronize()
+            times.append(1e3 * (time.perf_counter() - t0))
+        _lib.fc_profile_enable(False)
+        prof = _lib.fc_profile_read(reset=True)
+    g = prof["k_gram"]
+    ms = float(np.mean(times))
+    pair_rows = n * (n - 1) / 2 * m
+    achieved = g["alg_ops"] / (g["ms"] * 1e-3) / 1e12
+    out = {
+        "metric": "exact query-rows counted/s + HBM GB/s frac; batched vs per-query; p50/p99 ms",
+        "value": pair_rows / (ms * 1e-3), "unit": "pair-rows/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "i8 MFMA, int32 accumulation", "data": "synthetic",
+        "config": {"workload": w.name, "desc": w.desc, "items": n, "m": m,
+                   "minsup": w.minsup, "pairs_above_minsup": int(total)},
+        "p50_ms": percentile(times, 50), "p99_ms": percentile(times, 99),
+        "roofline": {"bound": "mfma", "kernel": "k_gram", "achieved": achieved,
+                     "peak": INT8_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / INT8_PEAK_TOPS,
+                     "avg_launch_us": 1e3 * g["ms"] / g["launches"],
+                     "alg_ops_per_launch": g["alg_ops"] / g["launches"], "traffic": None},
+        "cpu_baseline": None,
+    }
+    if args.cpu_budget > 0:
+        t0 = time.perf_counter()
+        sub = max(1, min(m, int(m * args.cpu_budget / 60.0)))
+        orc.gram(np.ascontiguousarray(w.D[:, :sub]))
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": n * (n - 1) / 2 * sub / dt, "unit": "pair-rows/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": "co-occurrence of all %d items over the first %d "
+                                         "instances, 1 thread" % (n, sub)}
+    db.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg5"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"])
     ap.add_argument("--strategy", default="auto", choices=["auto", "hist", "bitmap", "partition"])
     ap.add_argument("--per-query", type=int, default=2000,
                     help="queries timed on the plain per-query path (0: skip)")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of single-thread oracle work in the CPU baseline (0: skip)")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="run the device autotuner on a sample of the batch before timing")
+    ap.add_argument("--tune", default=None,
+                    help="JSON tuning to install instead (keys of fc_tuning)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter scale)")
     args = ap.parse_args()
@@ -127,6 +194,8 @@ def main():
     w, reducers = workload(args.workload)
     print("# workload %s generated in %.1fs: %s" % (w.name, time.time() - t0, w.desc),
           file=sys.stderr, flush=True)
+    if args.workload == "cfg4":
+        return bench_pairs(args, w)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         db = Database(w.D, w.arity, stream=stream)
@@ -137,6 +206,20 @@ def main():
         alg_bytes = float(ks.sum()) * w.m
         scores = torch.empty(len(reducers) * nq, dtype=torch.float32, device="cuda")
         errs = torch.empty_like(scores)
+        tuning = None
+        if args.tune:
+            t = db.tuning()
+            t.update(json.loads(args.tune))
+            db.set_tuning(t)
+            tuning = db.tuning()
+        elif args.autotune:
+            t0 = time.time()
+            rng = np.random.default_rng(0)
+            ids = np.sort(rng.choice(nq, size=min(nq, max(2000, nq // 20)), replace=False))
+            tuning = db.autotune([w.query(int(i)) for i in ids], stream=stream)
+            print("# autotuned on %d queries in %.1fs: %s" % (len(ids), time.time() - t0,
+                                                              json.dumps(tuning)),
+                  file=sys.stderr, flush=True)
 
         def step():
             db.count_reduce(q, reducers, ess=w.ess, strategy=args.strategy, out=scores,
@@ -219,7 +302,7 @@ def main():
         "dtype": "u8 states, int32 counts, f32 reducers",
         "data": "synthetic",
         "config": {"workload": w.name, "desc": w.desc, "queries": nq, "m": w.m, "n": w.n,
-                   "reducers": list(reducers), "strategy": args.strategy,
+                   "reducers": list(reducers), "strategy": args.strategy, "tuning": tuning,
                    "parallelism": "single GPU"},
         "batched": {"p50_ms": percentile(step_ms, 50), "p99_ms": percentile(step_ms, 99),
                     "effective_GBps": alg_bytes / (ms * 1e-3) / 1e9,

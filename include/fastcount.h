@@ -209,6 +209,36 @@ int fc_batch_footprint(const fc_db *db, const int32_t *vars_flat,
                        int64_t *bytes);
 
 /*
+ * Tuning of one database handle: which strategy FC_STRAT_AUTO gives each
+ * query shape (Section 3.1: the traversal can be switched per query context)
+ * and the row-chunk sizes of the counting launches.  Counts never depend on
+ * these values, only the time they take.
+ */
+typedef struct fc_tuning {
+    int64_t chunk_rows;        /* histogram instances per workgroup, >= 4096 */
+    int64_t bitmap_chunk_rows; /* bitmap instances per workgroup, >= 4096    */
+    int32_t bitmap_words;      /* 64-instance words per tree walk: 1, 2 or 4 */
+    /* bitmap_cells[k-1][b]: FC_STRAT_AUTO counts a query of k variables with
+     * the Bitmap strategy when its table has at most 2^(b+2) cells and this
+     * entry is non-zero (b = 0..5: up to 4, 8, 16, 32, 64, 128 cells).      */
+    uint8_t bitmap_cells[FC_MAX_VARS][6];
+} fc_tuning;
+
+int fc_db_get_tuning(const fc_db *db, fc_tuning *t);
+
+/* Validates and installs `t` (FC_ERR_INVALID on an out-of-range field). */
+int fc_db_set_tuning(fc_db *db, const fc_tuning *t);
+
+/*
+ * Autotuner: times a representative batch (vars_flat/var_off as in
+ * fc_count_batch) on the device with every candidate -- Bitmap against
+ * histogram per (k, table-size bucket), then the row-chunk sizes -- and
+ * installs the fastest choices in the handle.  Synchronises `stream`.
+ */
+int fc_autotune(fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
+                int64_t nq, void *stream);
+
+/*
  * Launch profiling (observability).  While enabled, the library brackets
  * every kernel launch with a pair of HIP events on the launch's stream and
  * attributes to it the algorithmic work it performs: bytes of state columns

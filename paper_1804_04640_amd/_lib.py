@@ -34,7 +34,8 @@ FC_RED_MI = 8
 # every symbol the header declares
 EXPORTS = ("fc_db_create", "fc_db_destroy", "fc_db_info", "fc_db_marginals", "fc_table_cells",
            "fc_count", "fc_count_assignment", "fc_count_batch", "fc_count_reduce", "fc_pairs",
-           "fc_batch_footprint", "fc_profile_enable", "fc_profile_read", "fc_last_error")
+           "fc_batch_footprint", "fc_db_get_tuning", "fc_db_set_tuning", "fc_autotune",
+           "fc_profile_enable", "fc_profile_read", "fc_last_error")
 
 
 class FastcountError(RuntimeError):
@@ -45,6 +46,28 @@ class FastcountError(RuntimeError):
 
 class fc_reduce_params(ctypes.Structure):
     _fields_ = [("ess", ctypes.c_double)]
+
+
+class fc_tuning(ctypes.Structure):
+    _fields_ = [("chunk_rows", ctypes.c_int64), ("bitmap_chunk_rows", ctypes.c_int64),
+                ("bitmap_words", ctypes.c_int32),
+                ("bitmap_cells", (ctypes.c_uint8 * 6) * FC_MAX_VARS)]
+
+    def to_dict(self):
+        return {"chunk_rows": int(self.chunk_rows), "bitmap_chunk_rows": int(self.bitmap_chunk_rows),
+                "bitmap_words": int(self.bitmap_words),
+                "bitmap_cells": [[int(x) for x in row] for row in self.bitmap_cells]}
+
+    @classmethod
+    def from_dict(cls, d):
+        t = cls()
+        t.chunk_rows = int(d["chunk_rows"])
+        t.bitmap_chunk_rows = int(d["bitmap_chunk_rows"])
+        t.bitmap_words = int(d["bitmap_words"])
+        for k, row in enumerate(d["bitmap_cells"]):
+            for b, x in enumerate(row):
+                t.bitmap_cells[k][b] = int(x)
+        return t
 
 
 class fc_kernel_stat(ctypes.Structure):
@@ -86,6 +109,9 @@ def load():
             "fc_count_reduce": (ctypes.c_int, [P, P, P, i64, u32, P, P, P, P, P, u32, P]),
             "fc_pairs": (ctypes.c_int, [P, P, i32, ctypes.c_double, P, P, i64, P, P]),
             "fc_batch_footprint": (ctypes.c_int, [P, P, P, i64, u32, P]),
+            "fc_db_get_tuning": (ctypes.c_int, [P, P]),
+            "fc_db_set_tuning": (ctypes.c_int, [P, P]),
+            "fc_autotune": (ctypes.c_int, [P, P, P, i64, P]),
             "fc_profile_enable": (ctypes.c_int, [ctypes.c_int]),
             "fc_profile_read": (ctypes.c_int, [P, i32, i32]),
             "fc_last_error": (ctypes.c_char_p, []),
@@ -165,6 +191,20 @@ def fc_batch_footprint(db, vars_flat, var_off, nq, flags):
     b = ctypes.c_int64()
     check(load().fc_batch_footprint(db, vars_flat, var_off, nq, flags, ctypes.byref(b)))
     return b.value
+
+
+def fc_db_get_tuning(db):
+    t = fc_tuning()
+    check(load().fc_db_get_tuning(db, ctypes.byref(t)))
+    return t
+
+
+def fc_db_set_tuning(db, t):
+    return check(load().fc_db_set_tuning(db, ctypes.byref(t)))
+
+
+def fc_autotune(db, vars_flat, var_off, nq, stream):
+    return check(load().fc_autotune(db, vars_flat, var_off, nq, stream))
 
 
 def fc_profile_enable(on):

@@ -11,6 +11,9 @@ torch, every step of the counting path runs in the HIP library.
 from __future__ import annotations
 
 import ctypes
+import hashlib
+import json
+import os
 from typing import Dict, Iterable, Optional, Sequence
 
 import numpy as np
@@ -199,6 +202,42 @@ class Database:
         flat, off = flatten_queries(queries)
         return L.fc_batch_footprint(self.handle, _np_ptr(flat), _np_ptr(off), len(off) - 1,
                                     STRATEGIES[strategy])
+
+    # ----------------------------------------------------------- tuning
+    def tuning(self) -> dict:
+        return L.fc_db_get_tuning(self.handle).to_dict()
+
+    def set_tuning(self, d: dict) -> None:
+        L.fc_db_set_tuning(self.handle, L.fc_tuning.from_dict(d))
+
+    def tuning_key(self) -> str:
+        props = torch.cuda.get_device_properties(self.device)
+        arch = getattr(props, "gcnArchName", props.name)
+        h = hashlib.sha1(self.arity.tobytes()).hexdigest()[:12]
+        return "%s/n%d/m%d/r%s/bits%d" % (arch, self.n, self.m, h, int(self.bitvectors))
+
+    def autotune(self, sample_queries, cache: Optional[str] = None, stream=None) -> dict:
+        """Run the device autotuner on a representative batch and install the
+        result; with `cache`, reuse/store the choice in a JSON file keyed by GPU
+        architecture and database shape."""
+        key = self.tuning_key()
+        db_json = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                db_json = json.load(f)
+            if key in db_json:
+                self.set_tuning(db_json[key])
+                return db_json[key]
+        flat, off = flatten_queries(sample_queries)
+        L.fc_autotune(self.handle, _np_ptr(flat), _np_ptr(off), len(off) - 1, _stream(stream))
+        t = self.tuning()
+        if cache:
+            db_json[key] = t
+            tmp = cache + ".tmp%d" % os.getpid()
+            with open(tmp, "w") as f:
+                json.dump(db_json, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return t
 
     # ----------------------------------------------------------- pairs
     def pairs(self, minsup: float, items: Optional[Iterable[int]] = None, gram: bool = False,

@@ -26,6 +26,7 @@
 namespace fc {
 
 constexpr int kHistMaxCells = 40000;  // odd row stride * 4 B <= 160 KiB
+constexpr int kLaneCols = 64;         // cells * 64 lanes * 4 B = 16 KiB at most
 
 __device__ __forceinline__ void map_block(int64_t b, int32_t nd, int32_t chunks, int32_t &d,
                                           int32_t &c) {
@@ -111,6 +112,100 @@ __global__ __launch_bounds__(kBlock) void k_hist(const uint8_t *__restrict__ col
     for (int32_t cell = threadIdx.x; cell < (int32_t)win; cell += kBlock) {
         uint32_t sum = 0;
         for (int32_t p = 0; p < copies; ++p) sum += lds[p * cs + cell];
+        if (cell == 0 && has_pad) sum -= (uint32_t)pad_rows;  // padding rows are key 0
+        if (sum) atomicAdd(&out[cell], (int32_t)sum);
+    }
+}
+
+// LDS histogram for tables whose copies fit 64 KiB (no key window): the key
+// of two instances at a time is formed in the 16-bit halves of one register
+// with packed multiply-adds, directly as an LDS byte address (strides are
+// pre-scaled by 4 and the lane's copy offset is the accumulator's start).
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pk_mad_u16(uint32_t a, uint32_t b, uint32_t c) {
+    const u16x2 x = __builtin_bit_cast(u16x2, a), y = __builtin_bit_cast(u16x2, b),
+                z = __builtin_bit_cast(u16x2, c);
+    return __builtin_bit_cast(uint32_t, (u16x2)(x * y + z));
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_hist16(const uint8_t *__restrict__ cols,
+                                                   int64_t m_pad,
+                                                   const uint8_t *__restrict__ arity,
+                                                   const QDesc *__restrict__ descs, int32_t nd,
+                                                   int32_t chunks, int32_t lds_words,
+                                                   int32_t pad_rows,
+                                                   int32_t *__restrict__ tables) {
+    extern __shared__ uint32_t lds[];
+    int32_t di, c;
+    map_block(blockIdx.x, nd, chunks, di, c);
+    const QDesc &q = descs[di];
+    const int32_t cells = q.cells;
+    uint32_t sb[K];
+    const uint8_t *colp[K];
+    {
+        uint32_t s = 1;
+#pragma unroll
+        for (int t = K - 1; t >= 0; --t) {
+            const int32_t v = q.var[t];
+            sb[t] = (s * 4u) * 0x00010001u;  // byte stride in both halves
+            s *= arity[v];
+            colp[t] = cols + (int64_t)v * m_pad;
+        }
+    }
+    // Two layouts.  Tables up to kLaneCols cells: cell x of lane l lives at
+    // word x*64 + l, so a lane always hits its own bank and no ds_add of a
+    // wave conflicts, whatever the keys.  Larger tables: `copies` histograms
+    // with an odd row stride, lanes spread over the copies.
+    const bool lanecols = cells <= kLaneCols;
+    const int32_t cs = cells | 1;
+    int32_t copies = lds_words / cs;
+    copies = copies >= 64 ? 64 : copies >= 32 ? 32 : copies >= 16 ? 16 : copies >= 8 ? 8
+           : copies >= 4 ? 4 : copies >= 2 ? 2 : 1;
+    const int32_t used = lanecols ? cells * 64 : copies * cs;
+    for (int32_t i = threadIdx.x; i < used; i += kBlock) lds[i] = 0;
+    __syncthreads();
+    if (lanecols) {
+#pragma unroll
+        for (int t = 0; t < K; ++t) sb[t] *= 64u;
+    }
+    const int64_t tiles = m_pad / kTileRows;
+    const int64_t r0 = (int64_t)c * tiles / chunks * kTileRows;
+    const int64_t r1 = (int64_t)(c + 1) * tiles / chunks * kTileRows;
+    const uint32_t slot = lanecols ? (threadIdx.x & 63u) : (threadIdx.x & (copies - 1)) * (uint32_t)cs;
+    const uint32_t init = (slot * 4u) * 0x00010001u;
+    char *base = reinterpret_cast<char *>(lds);
+
+    for (int64_t row = r0 + (int64_t)threadIdx.x * 16; row < r1; row += kBlock * 16) {
+        uint4 v[K];
+#pragma unroll
+        for (int t = 0; t < K; ++t) v[t] = *reinterpret_cast<const uint4 *>(colp[t] + row);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            uint32_t alo = init, ahi = init;  // instances (0,2) and (1,3) of this dword
+#pragma unroll
+            for (int t = 0; t < K; ++t) {
+                const uint32_t w = d == 0 ? v[t].x : d == 1 ? v[t].y : d == 2 ? v[t].z : v[t].w;
+                alo = pk_mad_u16(__builtin_amdgcn_perm(w, w, 0x0c020c00u), sb[t], alo);
+                ahi = pk_mad_u16(__builtin_amdgcn_perm(w, w, 0x0c030c01u), sb[t], ahi);
+            }
+            atomicAdd(reinterpret_cast<uint32_t *>(base + (alo & 0xFFFFu)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + (ahi & 0xFFFFu)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + (alo >> 16)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + (ahi >> 16)), 1u);
+        }
+    }
+    __syncthreads();
+    const bool has_pad = (r1 == m_pad) && (r0 < r1);
+    int32_t *out = tables + q.table_off;
+    for (int32_t cell = threadIdx.x; cell < cells; cell += kBlock) {
+        uint32_t sum = 0;
+        if (lanecols) {
+            const uint32_t lane = threadIdx.x & 63u;  // staggered: no two lanes share a bank
+            for (uint32_t j = 0; j < 64; ++j) sum += lds[cell * 64 + ((j + lane) & 63u)];
+        } else {
+            for (int32_t p = 0; p < copies; ++p) sum += lds[p * cs + cell];
+        }
         if (cell == 0 && has_pad) sum -= (uint32_t)pad_rows;  // padding rows are key 0
         if (sum) atomicAdd(&out[cell], (int32_t)sum);
     }
@@ -240,6 +335,7 @@ struct Launch {
     int strat;
     int K;
     bool small;
+    bool packed16;    // k_hist16: whole table, 16-bit byte-address keys
     int64_t first;    // first descriptor
     int32_t count;    // descriptors
     int32_t chunks;
@@ -254,9 +350,12 @@ struct Plan {
     bool packed = true;         // tables back to back in query order
 };
 
-static const int32_t kClassCap[] = {16, 64, 256, 1024, 4096, 16384, kHistMaxCells};
+// LDS size classes; every class but the last keeps its byte addresses below
+// 2^16 (the packed 16-bit key path).
+static const int32_t kClassCap[] = {16, 64, 256, 1024, 4096, 16383, kHistMaxCells};
 static const int32_t kClassLds[] = {64 * 17 * 4,  64 * 65 * 4,   16 * 257 * 4, 4 * 1025 * 4,
-                                    4097 * 4,     16385 * 4,     kHistMaxCells * 4 + 4};
+                                    4097 * 4,     16383 * 4,     kHistMaxCells * 4 + 4};
+constexpr int kHist16Classes = 6;
 
 static int hist_class(int64_t cells) {
     for (int i = 0; i < 7; ++i)
@@ -324,15 +423,20 @@ static int validate(const fc_db *db, const int32_t *vars_flat, const int64_t *va
     return FC_OK;
 }
 
-static int32_t pick_chunks(const fc_db *db, int64_t nd, int64_t cells) {
+// Row chunks per descriptor.  Small chunks keep one row range of every
+// column of the batch inside an XCD's L2 (the XCD-aware block order deals
+// chunk x, x+8, ... of every descriptor to XCD x); each chunk costs one flush
+// of the partial table, so chunks never get shorter than 8 cells per row.
+static int32_t pick_chunks(const fc_db *db, int64_t nd, int64_t cells, int strat) {
     const int64_t tiles = db->m_pad / kTileRows;
-    int64_t min_rows = db->tune.chunk_rows > 0 ? db->tune.chunk_rows : 32768;
-    if (min_rows < 8 * cells) min_rows = 8 * cells;  // keep flushes << scans
-    int64_t max_chunks = std::max<int64_t>(1, db->m_pad / min_rows);
-    int64_t want = (4 * (int64_t)db->cu_count + nd - 1) / nd;
-    if (want < kXcds) want = kXcds;
-    if (db->tune.hist_min_chunks > 0) want = std::max<int64_t>(want, db->tune.hist_min_chunks);
-    int64_t ch = std::min(want, std::min(max_chunks, tiles));
+    int64_t rows = strat == S_BITMAP ? db->tune.bitmap_chunk_rows : db->tune.chunk_rows;
+    if (rows <= 0) rows = 65536;
+    rows = std::max<int64_t>(rows, 8 * cells);
+    int64_t ch = (db->m_pad + rows - 1) / rows;
+    // enough workgroups for a small batch (4 per CU)
+    const int64_t want = (4 * (int64_t)db->cu_count + nd - 1) / nd;
+    if (ch < want) ch = std::min<int64_t>(want, std::max<int64_t>(1, db->m_pad / (8 * cells)));
+    ch = std::min(ch, tiles);
     if (ch >= kXcds) ch -= ch % kXcds;
     if (ch < 1) ch = 1;
     return (int32_t)ch;
@@ -380,7 +484,7 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
             st = c <= kHistMaxCells ? S_HIST : S_PART;
         else if (forced == FC_STRAT_PARTITION)
             st = S_PART;
-        else if (db->d_bits && c <= db->tune.bitmap_max_cells)
+        else if (db->d_bits && db->tune.bitmap_for((int)k, c))
             st = S_BITMAP;
         else
             st = c <= kHistMaxCells ? S_HIST : S_PART;
@@ -417,7 +521,8 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
                     L.count = (int32_t)b.size();
                     int64_t maxc = 0;
                     for (auto &d : b) maxc = std::max<int64_t>(maxc, d.win_cells);
-                    L.chunks = pick_chunks(db, L.count, maxc);
+                    L.chunks = pick_chunks(db, L.count, maxc, st);
+                    L.packed16 = st == S_HIST && cls < kHist16Classes;
                     if (st == S_BITMAP)
                         L.lds_bytes = (int32_t)(maxc * kBlock * 4);
                     else
@@ -429,6 +534,8 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
                     if (st == S_BITMAP)
                         snprintf(L.name, sizeof L.name, "k_bitmap<%d,%d>", K,
                                  db->tune.bitmap_words >= 4 ? 4 : db->tune.bitmap_words == 2 ? 2 : 1);
+                    else if (L.packed16)
+                        snprintf(L.name, sizeof L.name, "k_hist16<%d>", K);
                     else
                         snprintf(L.name, sizeof L.name, "k_hist<%d,%d>", K, sm);
                     P.work.insert(P.work.end(), b.begin(), b.end());
@@ -443,7 +550,11 @@ static hipError_t launch_hist_k(const fc_db *db, const Launch &L, const QDesc *d
                                 int32_t *tables, hipStream_t s) {
     const int64_t blocks = (int64_t)L.count * L.chunks;
     const int32_t pad = (int32_t)(db->m_pad - db->m);
-    if (L.small)
+    if (L.packed16)
+        hipLaunchKernelGGL((k_hist16<K>), dim3((unsigned)blocks), dim3(kBlock), L.lds_bytes, s,
+                           db->d_cols, db->m_pad, db->d_arity, d, L.count, L.chunks,
+                           L.lds_bytes / 4, pad, tables);
+    else if (L.small)
         hipLaunchKernelGGL((k_hist<K, true>), dim3((unsigned)blocks), dim3(kBlock), L.lds_bytes,
                            s, db->d_cols, db->m_pad, db->d_arity, d, L.count, L.chunks,
                            L.lds_bytes / 4, pad, tables);
@@ -503,6 +614,8 @@ static void set_attrs_k() {
     (void)hipFuncSetAttribute((const void *)k_hist<K, true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
     (void)hipFuncSetAttribute((const void *)k_hist<K, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
+    (void)hipFuncSetAttribute((const void *)k_hist16<K>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
     (void)hipFuncSetAttribute((const void *)k_bitmap<K, 1>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
@@ -787,5 +900,167 @@ extern "C" int fc_batch_footprint(const fc_db *db, const int32_t *vars_flat,
     *bytes = (int64_t)sizeof(int32_t) * P.total_cells +
              (int64_t)sizeof(QDesc) * (int64_t)(P.work.size() + P.query.size()) +
              (int64_t)sizeof(float) * 2 * 4 * nq;
+    return FC_OK;
+}
+
+// ------------------------------------------------------------------ tuning
+extern "C" int fc_db_get_tuning(const fc_db *db, fc_tuning *t) {
+    clear_error();
+    if (!db || !t) {
+        set_error("fc_db_get_tuning: NULL argument");
+        return FC_ERR_INVALID;
+    }
+    t->chunk_rows = db->tune.chunk_rows;
+    t->bitmap_chunk_rows = db->tune.bitmap_chunk_rows;
+    t->bitmap_words = db->tune.bitmap_words;
+    std::memcpy(t->bitmap_cells, db->tune.bitmap_cells, sizeof t->bitmap_cells);
+    return FC_OK;
+}
+
+extern "C" int fc_db_set_tuning(fc_db *db, const fc_tuning *t) {
+    clear_error();
+    if (!db || !t) {
+        set_error("fc_db_set_tuning: NULL argument");
+        return FC_ERR_INVALID;
+    }
+    if (t->chunk_rows < kTileRows || t->bitmap_chunk_rows < kTileRows ||
+        (t->bitmap_words != 1 && t->bitmap_words != 2 && t->bitmap_words != 4)) {
+        set_error("fc_db_set_tuning: chunk rows must be >= %lld and bitmap_words 1, 2 or 4",
+                  (long long)kTileRows);
+        return FC_ERR_INVALID;
+    }
+    db->tune.chunk_rows = t->chunk_rows;
+    db->tune.bitmap_chunk_rows = t->bitmap_chunk_rows;
+    db->tune.bitmap_words = t->bitmap_words;
+    std::memcpy(db->tune.bitmap_cells, t->bitmap_cells, sizeof t->bitmap_cells);
+    return FC_OK;
+}
+
+namespace fc {
+
+// Device time of one batch under the current tuning (median of `reps`).
+static int time_batch(fc_db *db, const std::vector<int32_t> &flat,
+                      const std::vector<int64_t> &off, uint32_t flags, int32_t *tables,
+                      hipStream_t s, int reps, float &ms_out) {
+    const int64_t nq = (int64_t)off.size() - 1;
+    hipEvent_t a, b;
+    FC_HIP(hipEventCreate(&a));
+    FC_HIP(hipEventCreate(&b));
+    float best = 1e30f;
+    int rc = FC_OK;
+    for (int r = 0; r <= reps && rc == FC_OK; ++r) {  // first run warms up
+        (void)hipEventRecord(a, s);
+        rc = fc_count_batch(db, flat.data(), off.data(), nq, tables, nullptr, flags, s);
+        (void)hipEventRecord(b, s);
+        if (rc == FC_OK && hipEventSynchronize(b) == hipSuccess) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, a, b);
+            if (r > 0) best = std::min(best, ms);
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc) return rc;
+    ms_out = best;
+    return FC_OK;
+}
+
+}  // namespace fc
+
+extern "C" int fc_autotune(fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
+                           int64_t nq, void *stream) {
+    clear_error();
+    std::vector<int64_t> cells;
+    int rc = validate(db, vars_flat, var_off, nq, nullptr, cells);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    FC_HIP(hipSetDevice(db->device));
+    int64_t total = 1024 * 128;  // room for a replicated bucket (<= 128 cells each)
+    {
+        int64_t sum = 0;
+        for (int64_t c : cells) sum += c;
+        total = std::max(total, sum);
+    }
+    DevBuf dt;
+    FC_HIP(dt.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(total, 1), s));
+    int32_t *tables = (int32_t *)dt.p;
+    std::vector<int32_t> flat(vars_flat, vars_flat + var_off[nq]);
+    std::vector<int64_t> off(var_off, var_off + nq + 1);
+    const int64_t cand[] = {16384, 32768, 65536, 131072, 262144, 524288};
+    auto sweep_chunks = [&](int which) -> int {
+        int64_t best = which == 0 ? db->tune.chunk_rows : db->tune.bitmap_chunk_rows;
+        float best_ms = 1e30f;
+        for (int64_t c : cand) {
+            if (which == 0) db->tune.chunk_rows = c; else db->tune.bitmap_chunk_rows = c;
+            float ms = 0.f;
+            int r = time_batch(db, flat, off, FC_STRAT_AUTO | FC_NO_GRAPH, tables, s, 5, ms);
+            if (r) return r;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+        if (which == 0) db->tune.chunk_rows = best; else db->tune.bitmap_chunk_rows = best;
+        return FC_OK;
+    };
+    // 1. Histogram chunk size with the current strategy choice.
+    if ((rc = sweep_chunks(0))) return rc;
+    // 2. Bitmap against histogram per (k, size bucket), on the sample's own
+    //    queries of that shape, repeated to at least 1024 queries so the
+    //    timing is not dominated by launch latency.
+    if (db->d_bits) {
+        for (int k = 1; k <= FC_MAX_VARS; ++k)
+            for (int bkt = 0; bkt < 6; ++bkt) {
+                const int64_t lo = bkt == 0 ? 0 : (int64_t(4) << (bkt - 1)), hi = int64_t(4) << bkt;
+                std::vector<int32_t> f;
+                std::vector<int64_t> o(1, 0);
+                for (int64_t i = 0; i < nq; ++i)
+                    if (var_off[i + 1] - var_off[i] == k && cells[(size_t)i] > lo &&
+                        cells[(size_t)i] <= hi) {
+                        f.insert(f.end(), vars_flat + var_off[i], vars_flat + var_off[i + 1]);
+                        o.push_back((int64_t)f.size());
+                    }
+                if (o.size() < 2) continue;
+                const size_t nb = o.size() - 1, fl = f.size();
+                for (size_t rep = 1; o.size() - 1 < 1024; ++rep)
+                    for (size_t i = 0; i < nb && o.size() - 1 < 1024; ++i) {
+                        f.insert(f.end(), f.begin() + o[i], f.begin() + o[i + 1]);
+                        o.push_back((int64_t)f.size());
+                    }
+                (void)fl;
+                int64_t need = 0;
+                for (size_t i = 0; i + 1 < o.size(); ++i) {
+                    int64_t c = 1;
+                    for (int64_t t = o[i]; t < o[i + 1]; ++t) c *= db->arity[f[(size_t)t]];
+                    need += c;
+                }
+                if (need > total) continue;  // the scratch table is sized for the sample
+                float tb = 0.f, th = 0.f;
+                if ((rc = time_batch(db, f, o, FC_STRAT_BITMAP | FC_NO_GRAPH, tables, s, 5, tb)))
+                    return rc;
+                if ((rc = time_batch(db, f, o, FC_STRAT_HIST | FC_NO_GRAPH, tables, s, 5, th)))
+                    return rc;
+                db->tune.bitmap_cells[k - 1][bkt] = tb < th ? 1 : 0;
+            }
+    }
+    // 3. Chunk sizes again, for the strategy mix just chosen.
+    if ((rc = sweep_chunks(0))) return rc;
+    if (db->d_bits && (rc = sweep_chunks(1))) return rc;
+    // 4. Words per bitmap tree walk.
+    if (db->d_bits) {
+        int bestw = db->tune.bitmap_words;
+        float best_ms = 1e30f;
+        for (int wv : {1, 2, 4}) {
+            db->tune.bitmap_words = wv;
+            float ms = 0.f;
+            if ((rc = time_batch(db, flat, off, FC_STRAT_AUTO | FC_NO_GRAPH, tables, s, 5, ms)))
+                return rc;
+            if (ms < best_ms) {
+                best_ms = ms;
+                bestw = wv;
+            }
+        }
+        db->tune.bitmap_words = bestw;
+    }
     return FC_OK;
 }

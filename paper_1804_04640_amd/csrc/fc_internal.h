@@ -37,10 +37,20 @@ struct alignas(16) QDesc {
 static_assert(sizeof(QDesc) == 64, "QDesc must be 64 bytes");
 
 struct Tuning {
-    int64_t chunk_rows = 0;   // 0: automatic
-    int bitmap_max_cells = 16;
-    int bitmap_words = 2;     // 64-row words per thread per tree walk
-    int hist_min_chunks = 0;  // 0: automatic
+    int64_t chunk_rows = 65536;         // histogram rows per workgroup (at least)
+    int64_t bitmap_chunk_rows = 65536;  // bitmap rows per workgroup (at least)
+    int bitmap_words = 2;               // 64-row words per thread per tree walk
+    // bitmap_cells[k-1][b]: bitmap for k variables and <= 2^(b+2) cells
+    uint8_t bitmap_cells[FC_MAX_VARS][6] = {};
+    Tuning() {
+        for (int k = 0; k < FC_MAX_VARS; ++k)
+            for (int b = 0; b < 3; ++b) bitmap_cells[k][b] = 1;  // up to 16 cells
+    }
+    bool bitmap_for(int k, int64_t cells) const {
+        for (int b = 0; b < 6; ++b)
+            if (cells <= (int64_t(4) << b)) return bitmap_cells[k - 1][b] != 0;
+        return false;
+    }
 };
 
 }  // namespace fc
