@@ -91,6 +91,76 @@ def cpu_baseline(w, reducers, budget_s: float):
                       % (sample, w.nq, w.m, "+".join(reducers), threads, dt)}
 
 
+def bench_serve(args):
+    """Serving: D resident, hill-climbing family batches (10..5000 queries of
+    2..7 variables) arriving as a Poisson process at fractions of the
+    measured saturation rate; continuous batching against the plain
+    per-query path."""
+    import torch
+    from paper_1804_04640_amd import synth
+    from paper_1804_04640_amd.api import Database
+    from paper_1804_04640_amd.serving import (CountServer, GpuBackend, PerQueryServer,
+                                              poisson_arrivals, run_load)
+
+    t0 = time.time()
+    w = synth.cfg5(nbatches=256)
+    print("# %s generated in %.1fs" % (w.desc, time.time() - t0), file=sys.stderr, flush=True)
+    db = Database(w.D, w.arity)
+    batches = []
+    for ids in w.batches:
+        qs = [w.query(int(j)) for j in ids]
+        off = np.zeros(len(qs) + 1, np.int64)
+        off[1:] = np.cumsum([len(q) for q in qs])
+        batches.append((np.concatenate(qs).astype(np.int32), off))
+    sample = [q for b in batches[:16] for q in
+              (b[0][b[1][i]:b[1][i + 1]] for i in range(len(b[1]) - 1))]
+    tuning = db.autotune(sample[:4000])
+    n = args.serve_requests
+    load = [batches[i % len(batches)] for i in range(n)]
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(free * 0.5)
+    rng = np.random.default_rng(5)
+
+    def server():
+        return CountServer(GpuBackend(db, ("mdl",), slots=4), mem_budget=budget)
+
+    run_load(server(), load[:64], np.zeros(64))                       # warm up
+    sat = run_load(server(), load, np.zeros(n))                       # all at once
+    lam_sat = n / sat["seconds"]
+    print("# saturation %.1f requests/s, %.3e queries/s" % (lam_sat, sat["queries_per_s"]),
+          file=sys.stderr, flush=True)
+    rates = []
+    for frac in (0.25, 0.5, 0.75, 0.9):
+        st = run_load(server(), load, poisson_arrivals(rng, frac * lam_sat, n))
+        st.pop("done")
+        st["rate_frac"], st["rate_rps"] = frac, frac * lam_sat
+        rates.append(st)
+        print("# lambda=%.2f*sat: p50 %.2f ms p99 %.2f ms" % (frac, st["p50_ms"], st["p99_ms"]),
+              file=sys.stderr, flush=True)
+    # the plain per-query path as a server: its own saturation, then Poisson
+    # load at half of it (it cannot sustain the batched server's rates)
+    npq = min(24, n)
+    pq = run_load(PerQueryServer(db, ("mdl",)), load[:npq], np.zeros(npq))
+    pq_sat = npq / pq["seconds"]
+    pq_half = run_load(PerQueryServer(db, ("mdl",)), load[:npq],
+                       poisson_arrivals(rng, 0.5 * pq_sat, npq))
+    for d in (pq, pq_half, sat):
+        d.pop("done", None)
+    out = {"metric": "serving: queries/s and p50/p99 ms from arrival to result",
+           "value": sat["queries_per_s"], "unit": "queries/s (saturation)",
+           "config": {"workload": w.name, "desc": w.desc, "requests": n, "slots": 4,
+                      "mem_budget_bytes": budget, "tuning": tuning},
+           "saturation": {"requests_per_s": lam_sat, **sat},
+           "poisson": rates,
+           "per_query_path": {"saturation_requests_per_s": pq_sat,
+                              "saturation_queries_per_s": pq["queries_per_s"],
+                              "at_half_its_saturation": pq_half,
+                              "note": "requests of the same stream, one launch per query"},
+           "batched_vs_per_query_saturation": sat["queries_per_s"] / pq["queries_per_s"]}
+    db.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_pairs(args, w):
     """All-pairs co-occurrence: one step = Gram on MFMA + pair records."""
     import torch
@@ -167,6 +237,9 @@ def main():
                     help="run the device autotuner on a sample of the batch before timing")
     ap.add_argument("--tune", default=None,
                     help="JSON tuning to install instead (keys of fc_tuning)")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving mode (hill-climbing batches, Poisson arrivals, p50/p99)")
+    ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter scale)")
     args = ap.parse_args()
@@ -196,6 +269,8 @@ def main():
           file=sys.stderr, flush=True)
     if args.workload == "cfg4":
         return bench_pairs(args, w)
+    if args.serve:
+        return bench_serve(args)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         db = Database(w.D, w.arity, stream=stream)
