@@ -1,0 +1,85 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times (autotuned tuning installed): oracle comparisons on sampled
+queries, and properties that hold at any size checked on every query."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as orc
+from paper_1804_04640_amd import synth
+from paper_1804_04640_amd.api import Database
+
+pytestmark = pytest.mark.gpu
+REL = 1e-6
+
+
+def autotuned(w):
+    db = Database(w.D, w.arity)
+    rng = np.random.default_rng(0)
+    ids = np.sort(rng.choice(w.nq, size=min(w.nq, max(2000, w.nq // 20)), replace=False))
+    db.autotune([w.query(int(i)) for i in ids])
+    return db
+
+
+def check_full(w, reducers, nsample):
+    print("%s: %d queries, m=%d" % (w.name, w.nq, w.m), flush=True)
+    db = autotuned(w)
+    sc, er, tables, toff = db.count_reduce((w.vars_flat, w.var_off), reducers, ess=w.ess,
+                                           keep_tables=True)
+    torch.cuda.synchronize()
+    T = tables.cpu().numpy()
+    # every table sums to m (all queries)
+    sums = np.add.reduceat(T.astype(np.int64), toff[:-1]) if w.nq else []
+    assert np.all(sums == w.m)
+    assert np.all(T >= 0)
+    rng = np.random.default_rng(1)
+    sample = rng.choice(w.nq, size=min(nsample, w.nq), replace=False)
+    # the largest tables are always in the sample
+    cells = np.diff(toff)
+    sample = np.unique(np.concatenate([sample, np.argsort(cells)[-5:]]))
+    scores = {r: sc[r].cpu().numpy() for r in reducers}
+    errs = {r: er[r].cpu().numpy() for r in reducers}
+    worst = {r: 0.0 for r in reducers}
+    for i in sample:
+        q = w.query(int(i))
+        ref = orc.count(w.D, w.arity, q)
+        np.testing.assert_array_equal(T[toff[i]:toff[i + 1]], ref, err_msg="query %d" % i)
+        r = int(w.arity[q[-1]])
+        for name in reducers:
+            s_ref = orc.score(name, ref, r, w.ess)
+            d = abs(float(scores[name][i]) - s_ref)
+            tol = REL * abs(s_ref) if s_ref != 0 else 1e-6
+            assert d <= tol, (name, int(i), float(scores[name][i]), s_ref)
+            assert d <= float(errs[name][i]) + 1e-30
+            if s_ref:
+                worst[name] = max(worst[name], d / abs(s_ref))
+    print("worst relative error over %d sampled queries: %s" % (len(sample), worst), flush=True)
+    db.close()
+
+
+def test_bn_family_full():
+    check_full(synth.cfg2(), ("mdl",), 300)
+
+
+def test_batched_uneven_full():
+    check_full(synth.cfg3(), ("bdeu", "mi"), 150)
+
+
+def test_serving_database_full():
+    w = synth.cfg5(nbatches=16)
+    check_full(w, ("mdl",), 150)
+
+
+def test_all_pairs_full():
+    w = synth.cfg4()
+    n, m = w.D.shape
+    with Database(w.D, w.arity) as db:
+        recs, G, total = db.pairs(w.minsup, gram=True)
+        G = G.cpu().numpy()
+    ref = orc.gram(w.D)
+    np.testing.assert_array_equal(G, ref)
+    exp = orc.pairs(ref, m, w.minsup)
+    assert total == len(exp)
+    got = [(int(r["a"]), int(r["b"]), int(r["n_ab"])) for r in recs]
+    assert got == [e[:3] for e in exp]
+    print("pairs above minsup: %d" % total, flush=True)
