@@ -290,7 +290,7 @@ def main():
         elif args.autotune:
             t0 = time.time()
             rng = np.random.default_rng(0)
-            ids = np.sort(rng.choice(nq, size=min(nq, max(2000, nq // 20)), replace=False))
+            ids = np.sort(rng.choice(nq, size=min(nq, max(4000, nq // 10)), replace=False))
             tuning = db.autotune([w.query(int(i)) for i in ids], stream=stream)
             print("# autotuned on %d queries in %.1fs: %s" % (len(ids), time.time() - t0,
                                                               json.dumps(tuning)),

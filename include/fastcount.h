@@ -73,7 +73,6 @@ typedef struct fc_db fc_db;
                               /* part counted in LDS (Section 3.3)          */
 #define FC_STRAT_SORT FC_STRAT_PARTITION
 #define FC_STRAT_MASK 0xFu
-#define FC_NO_GRAPH 0x10u     /* launch directly, never through a hipGraph  */
 
 /* Reducers (bit mask; several may be fused into one counting pass). */
 #define FC_RED_LL 1u   /* log-likelihood of Eq. (1), bits (Fig. 2)          */
@@ -162,8 +161,9 @@ int fc_count_assignment(fc_db *db, const int32_t *vars, const uint8_t *states,
  * is written at tables[table_off[i] .. table_off[i] + cells_i).  var_off and
  * table_off hold nq+1 int64 values; table_off may be NULL, meaning tables are
  * packed back to back in query order.  flags: an FC_STRAT_* value (forced
- * strategies exist for testing; every strategy returns identical tables) and
- * optionally FC_NO_GRAPH.
+ * strategies exist for testing; every strategy returns identical tables;
+ * where a forced strategy cannot hold a table -- Bitmap beyond 128 cells,
+ * histogram beyond LDS -- the next one that can is used).
  */
 int fc_count_batch(fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
                    int64_t nq, int32_t *tables, const int64_t *table_off,
@@ -209,6 +209,30 @@ int fc_batch_footprint(const fc_db *db, const int32_t *vars_flat,
                        int64_t *bytes);
 
 /*
+ * Captured batch (hipGraph).  fc_graph_create plans a batch once, uploads its
+ * plan into buffers the graph owns and records every device step -- table
+ * zeroing, counting, reducers -- into a graph; each fc_graph_launch replays
+ * all of that work on `stream` with no host planning, for callers that run
+ * the same batch repeatedly.  Arguments are those of fc_count_reduce
+ * (reducers may be 0: counts only, then `tables` is required); every output
+ * buffer must be device memory and stay valid while the graph exists.  The
+ * graph reads the database, which must outlive it.
+ */
+typedef struct fc_graph fc_graph;
+
+int fc_graph_create(fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
+                    int64_t nq, uint32_t reducers, const fc_reduce_params *p,
+                    float *scores, float *err, int32_t *tables,
+                    const int64_t *table_off, uint32_t flags, void *stream,
+                    fc_graph **out);
+
+/* Replay the captured batch on `stream` (asynchronous). */
+int fc_graph_launch(fc_graph *g, void *stream);
+
+/* Wait for the graph's launches, then free it (NULL is a no-op). */
+void fc_graph_destroy(fc_graph *g);
+
+/*
  * Tuning of one database handle: which strategy FC_STRAT_AUTO gives each
  * query shape (Section 3.1: the traversal can be switched per query context)
  * and the row-chunk sizes of the counting launches.  Counts never depend on
@@ -218,6 +242,9 @@ typedef struct fc_tuning {
     int64_t chunk_rows;        /* histogram instances per workgroup, >= 4096 */
     int64_t bitmap_chunk_rows; /* bitmap instances per workgroup, >= 4096    */
     int32_t bitmap_words;      /* 64-instance words per tree walk: 1, 2 or 4 */
+    int32_t persistent_max_queries; /* batches of at most this many queries
+                                  count their small tables in one persistent
+                                  launch fed by per-XCD work queues (0: never) */
     /* bitmap_cells[k-1][b]: FC_STRAT_AUTO counts a query of k variables with
      * the Bitmap strategy when its table has at most 2^(b+2) cells and this
      * entry is non-zero (b = 0..5: up to 4, 8, 16, 32, 64, 128 cells).      */

@@ -25,7 +25,6 @@ FC_STRAT_HIST = 1
 FC_STRAT_BITMAP = 2
 FC_STRAT_PARTITION = 3
 FC_STRAT_SORT = FC_STRAT_PARTITION
-FC_NO_GRAPH = 0x10
 FC_RED_LL = 1
 FC_RED_MDL = 2
 FC_RED_BDEU = 4
@@ -34,7 +33,8 @@ FC_RED_MI = 8
 # every symbol the header declares
 EXPORTS = ("fc_db_create", "fc_db_destroy", "fc_db_info", "fc_db_marginals", "fc_table_cells",
            "fc_count", "fc_count_assignment", "fc_count_batch", "fc_count_reduce", "fc_pairs",
-           "fc_batch_footprint", "fc_db_get_tuning", "fc_db_set_tuning", "fc_autotune",
+           "fc_batch_footprint", "fc_graph_create", "fc_graph_launch", "fc_graph_destroy",
+           "fc_db_get_tuning", "fc_db_set_tuning", "fc_autotune",
            "fc_profile_enable", "fc_profile_read", "fc_last_error")
 
 
@@ -50,12 +50,13 @@ class fc_reduce_params(ctypes.Structure):
 
 class fc_tuning(ctypes.Structure):
     _fields_ = [("chunk_rows", ctypes.c_int64), ("bitmap_chunk_rows", ctypes.c_int64),
-                ("bitmap_words", ctypes.c_int32),
+                ("bitmap_words", ctypes.c_int32), ("persistent_max_queries", ctypes.c_int32),
                 ("bitmap_cells", (ctypes.c_uint8 * 6) * FC_MAX_VARS)]
 
     def to_dict(self):
         return {"chunk_rows": int(self.chunk_rows), "bitmap_chunk_rows": int(self.bitmap_chunk_rows),
                 "bitmap_words": int(self.bitmap_words),
+                "persistent_max_queries": int(self.persistent_max_queries),
                 "bitmap_cells": [[int(x) for x in row] for row in self.bitmap_cells]}
 
     @classmethod
@@ -64,6 +65,7 @@ class fc_tuning(ctypes.Structure):
         t.chunk_rows = int(d["chunk_rows"])
         t.bitmap_chunk_rows = int(d["bitmap_chunk_rows"])
         t.bitmap_words = int(d["bitmap_words"])
+        t.persistent_max_queries = int(d.get("persistent_max_queries", 256))
         for k, row in enumerate(d["bitmap_cells"]):
             for b, x in enumerate(row):
                 t.bitmap_cells[k][b] = int(x)
@@ -109,6 +111,9 @@ def load():
             "fc_count_reduce": (ctypes.c_int, [P, P, P, i64, u32, P, P, P, P, P, u32, P]),
             "fc_pairs": (ctypes.c_int, [P, P, i32, ctypes.c_double, P, P, i64, P, P]),
             "fc_batch_footprint": (ctypes.c_int, [P, P, P, i64, u32, P]),
+            "fc_graph_create": (ctypes.c_int, [P, P, P, i64, u32, P, P, P, P, P, u32, P, P]),
+            "fc_graph_launch": (ctypes.c_int, [P, P]),
+            "fc_graph_destroy": (None, [P]),
             "fc_db_get_tuning": (ctypes.c_int, [P, P]),
             "fc_db_set_tuning": (ctypes.c_int, [P, P]),
             "fc_autotune": (ctypes.c_int, [P, P, P, i64, P]),
@@ -191,6 +196,22 @@ def fc_batch_footprint(db, vars_flat, var_off, nq, flags):
     b = ctypes.c_int64()
     check(load().fc_batch_footprint(db, vars_flat, var_off, nq, flags, ctypes.byref(b)))
     return b.value
+
+
+def fc_graph_create(db, vars_flat, var_off, nq, reducers, params, scores, err, tables, table_off,
+                    flags, stream):
+    h = ctypes.c_void_p()
+    check(load().fc_graph_create(db, vars_flat, var_off, nq, reducers, params, scores, err, tables,
+                                 table_off, flags, stream, ctypes.byref(h)))
+    return h.value
+
+
+def fc_graph_launch(g, stream):
+    return check(load().fc_graph_launch(g, stream))
+
+
+def fc_graph_destroy(g):
+    load().fc_graph_destroy(g)
 
 
 def fc_db_get_tuning(db):

@@ -150,7 +150,7 @@ class Database:
         return toff
 
     def count_batch(self, queries, strategy: str = "auto", tables: Optional[torch.Tensor] = None,
-                    table_off: Optional[np.ndarray] = None, graph: bool = True, stream=None):
+                    table_off: Optional[np.ndarray] = None, stream=None):
         """Returns (tables int32 tensor, table_off int64 numpy [nq+1])."""
         flat, off = flatten_queries(queries)
         nq = len(off) - 1
@@ -162,7 +162,7 @@ class Database:
             tptr = _np_ptr(toff)
         if tables is None:
             tables = self._empty(max(1, int(toff[-1])), torch.int32)
-        flags = STRATEGIES[strategy] | (0 if graph else L.FC_NO_GRAPH)
+        flags = STRATEGIES[strategy]
         L.fc_count_batch(self.handle, _np_ptr(flat), _np_ptr(off), nq, tables.data_ptr(), tptr,
                          flags, _stream(stream))
         return tables, toff
@@ -197,6 +197,12 @@ class Database:
         sc = {r: scores[i * nq:(i + 1) * nq] for i, r in enumerate(names)}
         er = {r: err[i * nq:(i + 1) * nq] for i, r in enumerate(names)} if err is not None else None
         return sc, er, tables, toff
+
+    def graph(self, queries, reducers: Sequence[str] = ("mdl",), ess: float = 1.0,
+              keep_tables: bool = False, strategy: str = "auto", stream=None) -> "BatchGraph":
+        """Capture the batch once (plan, upload, every device step) and
+        return an object whose replay() reruns all of its device work."""
+        return BatchGraph(self, queries, reducers, ess, keep_tables, strategy, stream)
 
     def footprint(self, queries, strategy: str = "auto") -> int:
         flat, off = flatten_queries(queries)
@@ -256,3 +262,47 @@ class Database:
                        ("support", np.float32), ("conf_ab", np.float32), ("conf_ba", np.float32)])
         arr = np.frombuffer(recs, dtype=dt, count=min(total, cap)).copy()
         return arr, (g.view(ni, ni) if g is not None else None), total
+
+
+class BatchGraph:
+    """A batch captured into a hipGraph; outputs live in tensors it owns."""
+
+    def __init__(self, db: Database, queries, reducers, ess, keep_tables, strategy, stream):
+        flat, off = flatten_queries(queries)
+        nq = len(off) - 1
+        self.db = db
+        self.names = [r for r in ("ll", "mdl", "bdeu", "mi") if r in reducers]
+        mask = 0
+        for r in self.names:
+            mask |= REDUCER_BITS[r]
+        self.scores = db._empty(max(1, len(self.names) * nq), torch.float32)
+        self.err = db._empty(max(1, len(self.names) * nq), torch.float32) if self.names else None
+        self.tables, self.table_off = None, None
+        if keep_tables or not self.names:
+            self.table_off = db.table_offsets((flat, off))
+            self.tables = db._empty(max(1, int(self.table_off[-1])), torch.int32)
+        params = L.fc_reduce_params(float(ess))
+        self._g = L.fc_graph_create(db.handle, _np_ptr(flat), _np_ptr(off), nq, mask,
+                                    ctypes.addressof(params),
+                                    self.scores.data_ptr() if self.names else 0,
+                                    self.err.data_ptr() if self.err is not None else 0,
+                                    self.tables.data_ptr() if self.tables is not None else 0, 0,
+                                    STRATEGIES[strategy], _stream(stream))
+        self.nq = nq
+
+    def replay(self, stream=None):
+        L.fc_graph_launch(self._g, _stream(stream))
+
+    def result(self) -> Dict[str, torch.Tensor]:
+        return {r: self.scores[i * self.nq:(i + 1) * self.nq] for i, r in enumerate(self.names)}
+
+    def close(self):
+        if getattr(self, "_g", None):
+            L.fc_graph_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

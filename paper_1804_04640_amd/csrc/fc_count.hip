@@ -27,6 +27,7 @@ namespace fc {
 
 constexpr int kHistMaxCells = 40000;  // odd row stride * 4 B <= 160 KiB
 constexpr int kLaneCols = 64;         // cells * 64 lanes * 4 B = 16 KiB at most
+constexpr int32_t kPersistentLds = 64 * 65 * 4;  // groups up to this LDS share one launch
 
 __device__ __forceinline__ void map_block(int64_t b, int32_t nd, int32_t chunks, int32_t &d,
                                           int32_t &c) {
@@ -54,15 +55,11 @@ __device__ __forceinline__ uint32_t byte_of(const uint4 &v, int i) {
 // LDS histogram count of one descriptor over one row chunk.
 // SMALL: every stride is below 2^24, so 24-bit multiplies suffice.
 template <int K, bool SMALL>
-__global__ __launch_bounds__(kBlock) void k_hist(const uint8_t *__restrict__ cols, int64_t m_pad,
-                                                 const uint8_t *__restrict__ arity,
-                                                 const QDesc *__restrict__ descs, int32_t nd,
-                                                 int32_t chunks, int32_t lds_words,
-                                                 int32_t pad_rows, int32_t *__restrict__ tables) {
-    extern __shared__ uint32_t lds[];
-    int32_t di, c;
-    map_block(blockIdx.x, nd, chunks, di, c);
-    const QDesc &q = descs[di];
+__device__ __forceinline__ void hist_body(const uint8_t *__restrict__ cols, int64_t m_pad,
+                                          const uint8_t *__restrict__ arity, const QDesc &q,
+                                          int32_t c, int32_t chunks, int32_t lds_words,
+                                          int32_t pad_rows, int32_t *__restrict__ tables,
+                                          uint32_t *lds) {
     const int32_t win_base = q.win_base;
     const uint32_t win = (uint32_t)q.win_cells;
 
@@ -117,6 +114,18 @@ __global__ __launch_bounds__(kBlock) void k_hist(const uint8_t *__restrict__ col
     }
 }
 
+template <int K, bool SMALL>
+__global__ __launch_bounds__(kBlock) void k_hist(const uint8_t *__restrict__ cols, int64_t m_pad,
+                                                 const uint8_t *__restrict__ arity,
+                                                 const QDesc *__restrict__ descs, int32_t nd,
+                                                 int32_t chunks, int32_t lds_words,
+                                                 int32_t pad_rows, int32_t *__restrict__ tables) {
+    extern __shared__ uint32_t lds[];
+    int32_t di, c;
+    map_block(blockIdx.x, nd, chunks, di, c);
+    hist_body<K, SMALL>(cols, m_pad, arity, descs[di], c, chunks, lds_words, pad_rows, tables, lds);
+}
+
 // LDS histogram for tables whose copies fit 64 KiB (no key window): the key
 // of two instances at a time is formed in the 16-bit halves of one register
 // with packed multiply-adds, directly as an LDS byte address (strides are
@@ -129,17 +138,11 @@ __device__ __forceinline__ uint32_t pk_mad_u16(uint32_t a, uint32_t b, uint32_t 
 }
 
 template <int K>
-__global__ __launch_bounds__(kBlock) void k_hist16(const uint8_t *__restrict__ cols,
-                                                   int64_t m_pad,
-                                                   const uint8_t *__restrict__ arity,
-                                                   const QDesc *__restrict__ descs, int32_t nd,
-                                                   int32_t chunks, int32_t lds_words,
-                                                   int32_t pad_rows,
-                                                   int32_t *__restrict__ tables) {
-    extern __shared__ uint32_t lds[];
-    int32_t di, c;
-    map_block(blockIdx.x, nd, chunks, di, c);
-    const QDesc &q = descs[di];
+__device__ __forceinline__ void hist16_body(const uint8_t *__restrict__ cols, int64_t m_pad,
+                                            const uint8_t *__restrict__ arity, const QDesc &q,
+                                            int32_t c, int32_t chunks, int32_t lds_words,
+                                            int32_t pad_rows, int32_t *__restrict__ tables,
+                                            uint32_t *lds) {
     const int32_t cells = q.cells;
     uint32_t sb[K];
     const uint8_t *colp[K];
@@ -211,6 +214,20 @@ __global__ __launch_bounds__(kBlock) void k_hist16(const uint8_t *__restrict__ c
     }
 }
 
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_hist16(const uint8_t *__restrict__ cols,
+                                                   int64_t m_pad,
+                                                   const uint8_t *__restrict__ arity,
+                                                   const QDesc *__restrict__ descs, int32_t nd,
+                                                   int32_t chunks, int32_t lds_words,
+                                                   int32_t pad_rows,
+                                                   int32_t *__restrict__ tables) {
+    extern __shared__ uint32_t lds[];
+    int32_t di, c;
+    map_block(blockIdx.x, nd, chunks, di, c);
+    hist16_body<K>(cols, m_pad, arity, descs[di], c, chunks, lds_words, pad_rows, tables, lds);
+}
+
 // Bitmap count (Alg. 1) of one descriptor over one chunk of 64-row words.
 template <int L, int K, int W>
 struct Walk {
@@ -240,16 +257,12 @@ struct Walk {
 };
 
 template <int K, int W>
-__global__ __launch_bounds__(kBlock) void k_bitmap(const uint64_t *__restrict__ bits,
-                                                   int64_t words,
-                                                   const int32_t *__restrict__ soff,
-                                                   const uint8_t *__restrict__ arity,
-                                                   const QDesc *__restrict__ descs, int32_t nd,
-                                                   int32_t chunks, int32_t *__restrict__ tables) {
-    extern __shared__ uint32_t acc[];  // [cells][kBlock], thread-private columns
-    int32_t di, c;
-    map_block(blockIdx.x, nd, chunks, di, c);
-    const QDesc &q = descs[di];
+__device__ __forceinline__ void bitmap_body(const uint64_t *__restrict__ bits, int64_t words,
+                                            const int32_t *__restrict__ soff,
+                                            const uint8_t *__restrict__ arity, const QDesc &q,
+                                            int32_t c, int32_t chunks,
+                                            int32_t *__restrict__ tables,
+                                            uint32_t *acc /* [cells][kBlock] */) {
     const int32_t cells = q.cells;
     int32_t base[K], rad[K];
 #pragma unroll
@@ -276,6 +289,109 @@ __global__ __launch_bounds__(kBlock) void k_bitmap(const uint64_t *__restrict__ 
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
         if (lane == 0 && s) atomicAdd(&out[cell], (int32_t)s);
+    }
+}
+
+template <int K, int W>
+__global__ __launch_bounds__(kBlock) void k_bitmap(const uint64_t *__restrict__ bits,
+                                                   int64_t words,
+                                                   const int32_t *__restrict__ soff,
+                                                   const uint8_t *__restrict__ arity,
+                                                   const QDesc *__restrict__ descs, int32_t nd,
+                                                   int32_t chunks, int32_t *__restrict__ tables) {
+    extern __shared__ uint32_t acc[];  // [cells][kBlock], thread-private columns
+    int32_t di, c;
+    map_block(blockIdx.x, nd, chunks, di, c);
+    bitmap_body<K, W>(bits, words, soff, arity, descs[di], c, chunks, tables, acc);
+}
+
+// One persistent launch over many launch groups.  Each group is a set of
+// descriptors counted with one strategy and one K; its (descriptor, chunk)
+// blocks get virtual indices [vbase, vbase + nv), vbase a multiple of 8, and
+// virtual block v belongs to XCD v % 8 (the same order map_block gives a
+// normal launch).  A resident workgroup reads its XCD from HW_REG_XCC_ID,
+// claims that XCD's virtual blocks through an atomic head, and steals from
+// the other XCDs' sequences when its own runs dry; it exits when all eight
+// are exhausted, so every wave reaches the exit.
+struct PGroup {
+    int64_t vbase;
+    int64_t nv;       // padded to a multiple of 8
+    int32_t first;    // first descriptor
+    int32_t nd;
+    int32_t chunks;
+    int32_t kind;     // PK_* << 4 | K
+};
+enum { PK_HIST16 = 1, PK_HIST_S = 2, PK_HIST_B = 3, PK_BITMAP = 4 };
+
+template <int K, int W>
+__device__ __forceinline__ void persistent_case(int type, const uint8_t *cols, int64_t m_pad,
+                                                const uint64_t *bits, int64_t words,
+                                                const int32_t *soff, const uint8_t *arity,
+                                                const QDesc &q, int32_t c, int32_t chunks,
+                                                int32_t lds_words, int32_t pad, int32_t *tables,
+                                                uint32_t *lds) {
+    switch (type) {
+        case PK_HIST16:
+            hist16_body<K>(cols, m_pad, arity, q, c, chunks, lds_words, pad, tables, lds);
+            break;
+        case PK_HIST_S:
+            hist_body<K, true>(cols, m_pad, arity, q, c, chunks, lds_words, pad, tables, lds);
+            break;
+        case PK_HIST_B:
+            hist_body<K, false>(cols, m_pad, arity, q, c, chunks, lds_words, pad, tables, lds);
+            break;
+        default:
+            bitmap_body<K, W>(bits, words, soff, arity, q, c, chunks, tables, lds);
+            break;
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_count_persistent(
+    const uint8_t *__restrict__ cols, int64_t m_pad, const uint64_t *__restrict__ bits,
+    int64_t words, const int32_t *__restrict__ soff, const uint8_t *__restrict__ arity,
+    const QDesc *__restrict__ descs, const PGroup *__restrict__ groups, int32_t ngroups,
+    int64_t total_v, uint32_t *__restrict__ heads, int32_t lds_words, int32_t pad_rows,
+    int32_t *__restrict__ tables) {
+    extern __shared__ uint32_t lds[];
+    __shared__ int64_t s_v;
+    const uint32_t xcc = __builtin_amdgcn_s_getreg((3 << 11) | 20) & 7u;  // HW_REG_XCC_ID
+    for (;;) {
+        __syncthreads();  // the previous block is done with LDS and s_v
+        if (threadIdx.x == 0) {
+            int64_t v = -1;
+            for (uint32_t s = 0; s < kXcds; ++s) {
+                const uint32_t x = (xcc + s) & 7u;
+                const int64_t cand = (int64_t)atomicAdd(&heads[x], 1u) * kXcds + x;
+                if (cand < total_v) {
+                    v = cand;
+                    break;
+                }
+            }
+            s_v = v;
+        }
+        __syncthreads();
+        const int64_t v = s_v;
+        if (v < 0) break;
+        int32_t g = 0;
+        while (g + 1 < ngroups && groups[g + 1].vbase <= v) ++g;
+        const PGroup G = groups[g];
+        const int64_t b = v - G.vbase;
+        if (b >= (int64_t)G.nd * G.chunks) continue;  // padding block
+        int32_t di, c;
+        map_block(b, G.nd, G.chunks, di, c);
+        const QDesc &q = descs[G.first + di];
+        const int type = G.kind >> 4;
+        switch (G.kind & 15) {
+            case 1: persistent_case<1, W>(type, cols, m_pad, bits, words, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+            case 2: persistent_case<2, W>(type, cols, m_pad, bits, words, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+            case 3: persistent_case<3, W>(type, cols, m_pad, bits, words, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+            case 4: persistent_case<4, W>(type, cols, m_pad, bits, words, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+            case 5: persistent_case<5, W>(type, cols, m_pad, bits, words, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+            case 6: persistent_case<6, W>(type, cols, m_pad, bits, words, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+            case 7: persistent_case<7, W>(type, cols, m_pad, bits, words, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+            default: persistent_case<8, W>(type, cols, m_pad, bits, words, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+        }
     }
 }
 
@@ -630,72 +746,163 @@ static void ensure_attrs() {
     if (g_lds_attr_set) return;
     set_attrs_k<1>(); set_attrs_k<2>(); set_attrs_k<3>(); set_attrs_k<4>();
     set_attrs_k<5>(); set_attrs_k<6>(); set_attrs_k<7>(); set_attrs_k<8>();
+    for (const void *f : {(const void *)k_count_persistent<1>, (const void *)k_count_persistent<2>,
+                          (const void *)k_count_persistent<4>})
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kPersistentLds);
     (void)hipGetLastError();
     g_lds_attr_set = true;
 }
 
-// Runs a whole batch: plan upload, table zeroing, counting launches, and the
-// optional reducers.  tables: device buffer of P.total_cells cells.
-static int run_batch(fc_db *db, Plan &P, int32_t *tables, uint32_t reducers, double ess,
-                     float *scores, float *err, hipStream_t s) {
-    ensure_attrs();
-    const size_t nw = P.work.size(), nqd = reducers ? P.query.size() : 0;
-    const size_t bytes = sizeof(QDesc) * (nw + nqd);
-    DevBuf d_desc;
-    if (bytes) {
-        FC_HIP(d_desc.alloc(bytes, s));
-        Staging *st = staging_acquire(bytes);
-        if (!st) {
-            set_error("pinned staging allocation of %zu bytes failed", bytes);
-            return FC_ERR_NOMEM;
+
+template <int W>
+static hipError_t launch_persistent_w(const fc_db *db, const PGroup *d_groups, int32_t ngroups,
+                                      int64_t vtotal, uint32_t *heads, int32_t lds,
+                                      const QDesc *dw, int32_t *tables, hipStream_t s) {
+    static int per_cu[5] = {0, 0, 0, 0, 0};
+    if (!per_cu[W]) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_count_persistent<W>, kBlock,
+                                                         kPersistentLds) != hipSuccess || nb < 1) {
+            (void)hipGetLastError();
+            nb = 2;
         }
-        std::memcpy(st->host, P.work.data(), sizeof(QDesc) * nw);
-        if (nqd) std::memcpy((QDesc *)st->host + nw, P.query.data(), sizeof(QDesc) * nqd);
-        hipError_t e = hipMemcpyAsync(d_desc.p, st->host, bytes, hipMemcpyHostToDevice, s);
-        staging_release(st, s);
-        if (e != hipSuccess) {
-            set_error("plan upload failed: %s", hipGetErrorString(e));
-            return FC_ERR_DEVICE;
+        per_cu[W] = nb;
+    }
+    int64_t grid = (int64_t)per_cu[W] * db->cu_count;
+    grid = std::min<int64_t>(grid, vtotal);
+    grid = std::max<int64_t>(grid, 1);
+    hipLaunchKernelGGL((k_count_persistent<W>), dim3((unsigned)grid), dim3(kBlock), lds, s,
+                       db->d_cols, db->m_pad, db->d_bits, db->words, db->d_soff, db->d_arity, dw,
+                       d_groups, ngroups, vtotal, heads, lds / 4, (int32_t)(db->m_pad - db->m),
+                       tables);
+    return hipGetLastError();
+}
+
+// Device image of a planned batch: one buffer with the counting descriptors,
+// the per-query descriptors (reducers, zeroing of caller-placed tables), the
+// persistent group table and the eight queue heads.
+struct Image {
+    std::vector<PGroup> groups;
+    std::vector<const Launch *> solo;
+    int64_t vtotal = 0;
+    int32_t plds = 0;
+    double pbytes = 0.0;
+    bool with_query = false;
+    size_t off_query = 0, off_groups = 0, off_heads = 0, bytes = 0;
+};
+
+static void make_image(const fc_db *db, const Plan &P, uint32_t reducers, Image &I) {
+    for (const Launch &L : P.launches) {
+        if ((int64_t)P.query.size() <= db->tune.persistent_max_queries &&
+            L.lds_bytes <= kPersistentLds) {
+            PGroup g;
+            g.vbase = I.vtotal;
+            g.nv = ((int64_t)L.count * L.chunks + kXcds - 1) / kXcds * kXcds;
+            g.first = (int32_t)L.first;
+            g.nd = L.count;
+            g.chunks = L.chunks;
+            const int type = L.strat == S_BITMAP ? PK_BITMAP
+                           : L.packed16 ? PK_HIST16 : L.small ? PK_HIST_S : PK_HIST_B;
+            g.kind = (type << 4) | L.K;
+            I.vtotal += g.nv;
+            I.groups.push_back(g);
+            I.pbytes += L.alg_bytes;
+            I.plds = std::max(I.plds, L.lds_bytes);
+        } else {
+            I.solo.push_back(&L);
         }
     }
-    const QDesc *dw = (const QDesc *)d_desc.p;
+    I.with_query = reducers != 0 || !P.packed;
+    size_t b = sizeof(QDesc) * P.work.size();
+    I.off_query = b;
+    if (I.with_query) b += sizeof(QDesc) * P.query.size();
+    I.off_groups = b;
+    b += sizeof(PGroup) * I.groups.size();
+    I.off_heads = b;
+    b += 64;
+    I.bytes = b;
+}
+
+static void fill_image(const Plan &P, const Image &I, void *host) {
+    char *h = (char *)host;
+    std::memcpy(h, P.work.data(), sizeof(QDesc) * P.work.size());
+    if (I.with_query) std::memcpy(h + I.off_query, P.query.data(), sizeof(QDesc) * P.query.size());
+    std::memcpy(h + I.off_groups, I.groups.data(), sizeof(PGroup) * I.groups.size());
+    std::memset(h + I.off_heads, 0, 64);
+}
+
+// Every device step of a batch whose image is resident at `dimg`: zero the
+// tables and queue heads (kernels, no memset nodes), count, reduce.  Safe to
+// record into a hipGraph.
+static int enqueue_batch(fc_db *db, const Plan &P, const Image &I, void *dimg, int32_t *tables,
+                         uint32_t reducers, double ess, float *scores, float *err,
+                         hipStream_t s) {
+    const QDesc *dw = (const QDesc *)dimg;
+    const QDesc *dq = (const QDesc *)((char *)dimg + I.off_query);
     if (P.packed) {
         FC_HIP(fill_zero_i32(tables, P.total_cells, s));
     } else if (!P.query.empty()) {
-        // zero each query's table once, from the per-query list
-        DevBuf dq;
-        const QDesc *src = dw + nw;
-        if (!nqd) {
-            FC_HIP(dq.alloc(sizeof(QDesc) * P.query.size(), s));
-            Staging *st = staging_acquire(sizeof(QDesc) * P.query.size());
-            if (!st) {
-                set_error("pinned staging allocation failed");
-                return FC_ERR_NOMEM;
-            }
-            std::memcpy(st->host, P.query.data(), sizeof(QDesc) * P.query.size());
-            hipError_t e = hipMemcpyAsync(dq.p, st->host, sizeof(QDesc) * P.query.size(),
-                                          hipMemcpyHostToDevice, s);
-            staging_release(st, s);
-            FC_HIP(e);
-            src = (const QDesc *)dq.p;
-        }
-        int32_t nd = (int32_t)P.query.size();
+        const int32_t nd = (int32_t)P.query.size();
         hipLaunchKernelGGL(k_zero_tables, dim3((unsigned)std::min<int32_t>(nd, 65536)), dim3(256),
-                           0, s, src, nd, tables);
+                           0, s, dq, nd, tables);
         FC_HIP(hipGetLastError());
     }
-    if (db->m > 0)
-        for (const Launch &L : P.launches) {
-            ProfScope ps(L.name, s, L.alg_bytes, 0.0);
-            FC_HIP(launch_count(db, L, dw, tables, s));
+    if (db->m > 0) {
+        if (!I.groups.empty()) {
+            uint32_t *heads = (uint32_t *)((char *)dimg + I.off_heads);
+            FC_HIP(fill_zero_i32((int32_t *)heads, 16, s));
+            const int W = db->tune.bitmap_words >= 4 ? 4 : db->tune.bitmap_words == 2 ? 2 : 1;
+            char name[32];
+            snprintf(name, sizeof name, "k_count_persistent<%d>", W);
+            const PGroup *g = (const PGroup *)((char *)dimg + I.off_groups);
+            const int32_t ng = (int32_t)I.groups.size();
+            ProfScope ps(name, s, I.pbytes, 0.0);
+            hipError_t e;
+            if (W == 4)
+                e = launch_persistent_w<4>(db, g, ng, I.vtotal, heads, I.plds, dw, tables, s);
+            else if (W == 2)
+                e = launch_persistent_w<2>(db, g, ng, I.vtotal, heads, I.plds, dw, tables, s);
+            else
+                e = launch_persistent_w<1>(db, g, ng, I.vtotal, heads, I.plds, dw, tables, s);
+            ps.end(s);
+            FC_HIP(e);
+        }
+        for (const Launch *L : I.solo) {
+            ProfScope ps(L->name, s, L->alg_bytes, 0.0);
+            FC_HIP(launch_count(db, *L, dw, tables, s));
             ps.end(s);
         }
-    if (reducers && nqd) {
+    }
+    if (reducers && !P.query.empty()) {
         ProfScope ps("k_reduce", s, 0.0, 0.0);
-        FC_HIP(launch_reduce(db, dw + nw, (int64_t)nqd, tables, reducers, ess, scores, err, s));
+        FC_HIP(launch_reduce(db, dq, (int64_t)P.query.size(), tables, reducers, ess, scores, err, s));
         ps.end(s);
     }
     return FC_OK;
+}
+
+// Runs a whole batch: one plan upload, then the device steps.
+// tables: device buffer of P.total_cells cells.
+static int run_batch(fc_db *db, Plan &P, int32_t *tables, uint32_t reducers, double ess,
+                     float *scores, float *err, hipStream_t s) {
+    ensure_attrs();
+    Image I;
+    make_image(db, P, reducers, I);
+    DevBuf dimg;
+    FC_HIP(dimg.alloc(I.bytes, s));
+    Staging *st = staging_acquire(I.bytes);
+    if (!st) {
+        set_error("pinned staging allocation of %zu bytes failed", I.bytes);
+        return FC_ERR_NOMEM;
+    }
+    fill_image(P, I, st->host);
+    hipError_t e = hipMemcpyAsync(dimg.p, st->host, I.bytes, hipMemcpyHostToDevice, s);
+    staging_release(st, s);
+    if (e != hipSuccess) {
+        set_error("plan upload failed: %s", hipGetErrorString(e));
+        return FC_ERR_DEVICE;
+    }
+    return enqueue_batch(db, P, I, dimg.p, tables, reducers, ess, scores, err, s);
 }
 
 }  // namespace fc
@@ -913,6 +1120,7 @@ extern "C" int fc_db_get_tuning(const fc_db *db, fc_tuning *t) {
     t->chunk_rows = db->tune.chunk_rows;
     t->bitmap_chunk_rows = db->tune.bitmap_chunk_rows;
     t->bitmap_words = db->tune.bitmap_words;
+    t->persistent_max_queries = db->tune.persistent_max_queries;
     std::memcpy(t->bitmap_cells, db->tune.bitmap_cells, sizeof t->bitmap_cells);
     return FC_OK;
 }
@@ -932,6 +1140,7 @@ extern "C" int fc_db_set_tuning(fc_db *db, const fc_tuning *t) {
     db->tune.chunk_rows = t->chunk_rows;
     db->tune.bitmap_chunk_rows = t->bitmap_chunk_rows;
     db->tune.bitmap_words = t->bitmap_words;
+    db->tune.persistent_max_queries = t->persistent_max_queries < 0 ? 0 : t->persistent_max_queries;
     std::memcpy(db->tune.bitmap_cells, t->bitmap_cells, sizeof t->bitmap_cells);
     return FC_OK;
 }
@@ -988,21 +1197,44 @@ extern "C" int fc_autotune(fc_db *db, const int32_t *vars_flat, const int64_t *v
     std::vector<int64_t> off(var_off, var_off + nq + 1);
     const int64_t cand[] = {16384, 32768, 65536, 131072, 262144, 524288};
     auto sweep_chunks = [&](int which) -> int {
-        int64_t best = which == 0 ? db->tune.chunk_rows : db->tune.bitmap_chunk_rows;
-        float best_ms = 1e30f;
+        // the current value is kept unless another is at least 3% faster
+        const int64_t cur = which == 0 ? db->tune.chunk_rows : db->tune.bitmap_chunk_rows;
+        int64_t best = cur;
+        float best_ms = 1e30f, cur_ms = 1e30f;
         for (int64_t c : cand) {
             if (which == 0) db->tune.chunk_rows = c; else db->tune.bitmap_chunk_rows = c;
             float ms = 0.f;
-            int r = time_batch(db, flat, off, FC_STRAT_AUTO | FC_NO_GRAPH, tables, s, 5, ms);
+            int r = time_batch(db, flat, off, FC_STRAT_AUTO, tables, s, 5, ms);
             if (r) return r;
+            if (c == cur) cur_ms = ms;
             if (ms < best_ms) {
                 best_ms = ms;
                 best = c;
             }
         }
+        if (!(best_ms < 0.97f * cur_ms)) best = cur;
         if (which == 0) db->tune.chunk_rows = best; else db->tune.bitmap_chunk_rows = best;
         return FC_OK;
     };
+    // 0. Batch size up to which one persistent launch beats one launch per
+    //    group: prefixes of the sample of growing size, stop at the first loss.
+    {
+        int32_t thr = 0;
+        for (int64_t nsub : {16, 64, 256, 1024, 4096}) {
+            if (nsub > nq) break;
+            std::vector<int32_t> f(vars_flat, vars_flat + var_off[nsub]);
+            std::vector<int64_t> o(var_off, var_off + nsub + 1);
+            float ms_p = 0.f, ms_s = 0.f;
+            db->tune.persistent_max_queries = (int32_t)nsub;
+            if ((rc = time_batch(db, f, o, FC_STRAT_AUTO, tables, s, 5, ms_p)))
+                return rc;
+            db->tune.persistent_max_queries = 0;
+            if ((rc = time_batch(db, f, o, FC_STRAT_AUTO, tables, s, 5, ms_s)))
+                return rc;
+            if (ms_p < ms_s) thr = (int32_t)nsub; else break;
+        }
+        db->tune.persistent_max_queries = thr;
+    }
     // 1. Histogram chunk size with the current strategy choice.
     if ((rc = sweep_chunks(0))) return rc;
     // 2. Bitmap against histogram per (k, size bucket), on the sample's own
@@ -1022,7 +1254,7 @@ extern "C" int fc_autotune(fc_db *db, const int32_t *vars_flat, const int64_t *v
                     }
                 if (o.size() < 2) continue;
                 const size_t nb = o.size() - 1, fl = f.size();
-                for (size_t rep = 1; o.size() - 1 < 1024; ++rep)
+                while (o.size() - 1 < 1024)
                     for (size_t i = 0; i < nb && o.size() - 1 < 1024; ++i) {
                         f.insert(f.end(), f.begin() + o[i], f.begin() + o[i + 1]);
                         o.push_back((int64_t)f.size());
@@ -1036,11 +1268,14 @@ extern "C" int fc_autotune(fc_db *db, const int32_t *vars_flat, const int64_t *v
                 }
                 if (need > total) continue;  // the scratch table is sized for the sample
                 float tb = 0.f, th = 0.f;
-                if ((rc = time_batch(db, f, o, FC_STRAT_BITMAP | FC_NO_GRAPH, tables, s, 5, tb)))
+                if ((rc = time_batch(db, f, o, FC_STRAT_BITMAP, tables, s, 5, tb)))
                     return rc;
-                if ((rc = time_batch(db, f, o, FC_STRAT_HIST | FC_NO_GRAPH, tables, s, 5, th)))
+                if ((rc = time_batch(db, f, o, FC_STRAT_HIST, tables, s, 5, th)))
                     return rc;
-                db->tune.bitmap_cells[k - 1][bkt] = tb < th ? 1 : 0;
+                // switch away from the current choice only on a clear win
+                const bool cur_bitmap = db->tune.bitmap_cells[k - 1][bkt] != 0;
+                if (cur_bitmap && th < 0.97f * tb) db->tune.bitmap_cells[k - 1][bkt] = 0;
+                if (!cur_bitmap && tb < 0.97f * th) db->tune.bitmap_cells[k - 1][bkt] = 1;
             }
     }
     // 3. Chunk sizes again, for the strategy mix just chosen.
@@ -1048,19 +1283,139 @@ extern "C" int fc_autotune(fc_db *db, const int32_t *vars_flat, const int64_t *v
     if (db->d_bits && (rc = sweep_chunks(1))) return rc;
     // 4. Words per bitmap tree walk.
     if (db->d_bits) {
-        int bestw = db->tune.bitmap_words;
-        float best_ms = 1e30f;
+        const int curw = db->tune.bitmap_words;
+        int bestw = curw;
+        float best_ms = 1e30f, cur_ms = 1e30f;
         for (int wv : {1, 2, 4}) {
             db->tune.bitmap_words = wv;
             float ms = 0.f;
-            if ((rc = time_batch(db, flat, off, FC_STRAT_AUTO | FC_NO_GRAPH, tables, s, 5, ms)))
+            if ((rc = time_batch(db, flat, off, FC_STRAT_AUTO, tables, s, 5, ms)))
                 return rc;
+            if (wv == curw) cur_ms = ms;
             if (ms < best_ms) {
                 best_ms = ms;
                 bestw = wv;
             }
         }
-        db->tune.bitmap_words = bestw;
+        db->tune.bitmap_words = best_ms < 0.97f * cur_ms ? bestw : curw;
     }
+    return FC_OK;
+}
+
+// ------------------------------------------------------------------ graphs
+struct fc_graph {
+    fc_db *db = nullptr;
+    fc::Plan P;
+    fc::Image I;
+    void *dimg = nullptr;
+    int32_t *scratch = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" void fc_graph_destroy(fc_graph *g) {
+    if (!g) return;
+    if (g->cap) (void)hipStreamSynchronize(g->cap);
+    (void)hipDeviceSynchronize();
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->cap) (void)hipStreamDestroy(g->cap);
+    if (g->dimg) (void)hipFree(g->dimg);
+    if (g->scratch) (void)hipFree(g->scratch);
+    (void)hipGetLastError();
+    delete g;
+}
+
+extern "C" int fc_graph_create(fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
+                               int64_t nq, uint32_t reducers, const fc_reduce_params *p,
+                               float *scores, float *err, int32_t *tables,
+                               const int64_t *table_off, uint32_t flags, void *stream,
+                               fc_graph **out) {
+    clear_error();
+    if (!out) {
+        set_error("fc_graph_create: out is NULL");
+        return FC_ERR_INVALID;
+    }
+    *out = nullptr;
+    std::vector<int64_t> cells;
+    int rc = validate(db, vars_flat, var_off, nq, table_off, cells);
+    if (rc) return rc;
+    if (nq < 1) {
+        set_error("fc_graph_create: empty batch");
+        return FC_ERR_INVALID;
+    }
+    if (reducers & ~(uint32_t)(FC_RED_LL | FC_RED_MDL | FC_RED_BDEU | FC_RED_MI)) {
+        set_error("fc_graph_create: unknown reducer mask %#x", reducers);
+        return FC_ERR_INVALID;
+    }
+    if (!reducers && !tables) {
+        set_error("fc_graph_create: counts only (no reducer) needs tables");
+        return FC_ERR_INVALID;
+    }
+    if ((tables && !is_device_ptr(tables)) || (reducers && !is_device_ptr(scores)) ||
+        (err && !is_device_ptr(err))) {
+        set_error("fc_graph_create: every output must be device memory");
+        return FC_ERR_INVALID;
+    }
+    if (!tables && table_off) {
+        set_error("fc_graph_create: table_off given without tables");
+        return FC_ERR_INVALID;
+    }
+    const double ess = p ? p->ess : 1.0;
+    if (!(ess > 0.0)) {
+        set_error("fc_graph_create: ess must be > 0");
+        return FC_ERR_INVALID;
+    }
+    FC_HIP(hipSetDevice(db->device));
+    ensure_attrs();
+    fc_graph *g = new (std::nothrow) fc_graph();
+    if (!g) {
+        set_error("fc_graph_create: host allocation failed");
+        return FC_ERR_NOMEM;
+    }
+    g->db = db;
+    struct Guard {
+        fc_graph *g;
+        ~Guard() { if (g) fc_graph_destroy(g); }
+    } guard{g};
+    if ((rc = build_plan(db, vars_flat, var_off, nq, table_off, flags, cells, g->P))) return rc;
+    make_image(db, g->P, reducers, g->I);
+    FC_HIP(hipMalloc(&g->dimg, g->I.bytes));
+    std::vector<char> host(g->I.bytes);
+    fill_image(g->P, g->I, host.data());
+    FC_HIP(hipMemcpy(g->dimg, host.data(), g->I.bytes, hipMemcpyHostToDevice));
+    int32_t *t = tables;
+    if (!t) {
+        FC_HIP(hipMalloc(&g->scratch, sizeof(int32_t) * (size_t)std::max<int64_t>(g->P.total_cells, 1)));
+        t = g->scratch;
+    }
+    FC_HIP(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking));
+    FC_HIP(hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
+    set_capturing(true);
+    rc = enqueue_batch(db, g->P, g->I, g->dimg, t, reducers, ess, scores, err, g->cap);
+    set_capturing(false);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(g->cap, &graph);
+    g->graph = graph;
+    if (rc) return rc;
+    FC_HIP(e);
+    FC_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    (void)stream;
+    *out = g;
+    guard.g = nullptr;
+    return FC_OK;
+}
+
+extern "C" int fc_graph_launch(fc_graph *g, void *stream) {
+    clear_error();
+    if (!g || !g->exec) {
+        set_error("fc_graph_launch: NULL graph");
+        return FC_ERR_INVALID;
+    }
+    FC_HIP(hipSetDevice(g->db->device));
+    ProfScope ps("graph", (hipStream_t)stream, 0.0, 0.0);
+    FC_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    ps.end((hipStream_t)stream);
     return FC_OK;
 }

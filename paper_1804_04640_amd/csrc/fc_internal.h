@@ -40,6 +40,7 @@ struct Tuning {
     int64_t chunk_rows = 65536;         // histogram rows per workgroup (at least)
     int64_t bitmap_chunk_rows = 65536;  // bitmap rows per workgroup (at least)
     int bitmap_words = 2;               // 64-row words per thread per tree walk
+    int persistent_max_queries = 256;   // small batches: one persistent launch
     // bitmap_cells[k-1][b]: bitmap for k variables and <= 2^(b+2) cells
     uint8_t bitmap_cells[FC_MAX_VARS][6] = {};
     Tuning() {
@@ -120,6 +121,7 @@ void staging_release(Staging *st, hipStream_t s);
 
 // Launch profiling: RAII bracket of one launch with events on its stream.
 bool profiling_on();
+void set_capturing(bool on);  // this thread is recording a graph: no event brackets
 struct ProfScope {
     int slot = -1;
     ProfScope(const char *name, hipStream_t s, double alg_bytes, double alg_ops);

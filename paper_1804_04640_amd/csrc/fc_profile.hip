@@ -60,10 +60,14 @@ void drain() {
 }
 }  // namespace
 
+static thread_local bool t_capturing = false;
+
 bool profiling_on() { return g_on.load(std::memory_order_relaxed); }
 
+void set_capturing(bool on) { t_capturing = on; }
+
 ProfScope::ProfScope(const char *name, hipStream_t s, double alg_bytes, double alg_ops) {
-    if (!profiling_on()) return;
+    if (!profiling_on() || t_capturing) return;
     std::lock_guard<std::mutex> lk(g_mu);
     if (g_pending.size() > 4096) drain();
     Pending p;

@@ -158,3 +158,48 @@ def test_marginals_and_assignment():
     with Database(w.D, w.arity, bitvectors=False) as db:
         assert db.count_assignment([0, 1], [0, 0]) == orc.count_assignment(w.D, w.arity, [0, 1],
                                                                            [0, 0])
+
+
+@pytest.mark.parametrize("persistent", [0, 100000])
+def test_persistent_and_solo_launches_agree(persistent):
+    w = synth.cfg3(m=50_001, nq=300)
+    with Database(w.D, w.arity) as db:
+        t = db.tuning()
+        t["persistent_max_queries"] = persistent
+        db.set_tuning(t)
+        for strategy in ("auto", "hist", "bitmap"):
+            tables, toff = db.count_batch((w.vars_flat, w.var_off), strategy=strategy)
+            check_tables(w, tables, toff)
+
+
+def test_graph_replays_match_eager():
+    # replays interleaved with eager work, every replay checked
+    w = synth.cfg2(m=60_000, nq=250)
+    with Database(w.D, w.arity) as db:
+        g = db.graph((w.vars_flat, w.var_off), ("mdl", "bdeu"), keep_tables=True)
+        eager, _, tables, toff = db.count_reduce((w.vars_flat, w.var_off), ("mdl", "bdeu"),
+                                                 keep_tables=True)
+        torch.cuda.synchronize()
+        for rep in range(4):
+            g.replay()
+            other, _, _, _ = db.count_reduce([w.query(rep)], ("mdl",))   # eager work between
+            torch.cuda.synchronize()
+            res = g.result()
+            for name in ("mdl", "bdeu"):
+                assert torch.equal(res[name], eager[name]), (rep, name)
+            assert torch.equal(g.tables, tables)
+        check_tables(w, g.tables, toff, idx=range(0, w.nq, 5))
+        g.close()
+
+
+def test_tuning_roundtrip_and_validation():
+    w = synth.cfg1()
+    with Database(w.D, w.arity) as db:
+        t = db.tuning()
+        t["chunk_rows"] = 32768
+        t["bitmap_cells"][2][3] = 1
+        db.set_tuning(t)
+        assert db.tuning() == t
+        t["bitmap_words"] = 3
+        with pytest.raises(_lib.FastcountError):
+            db.set_tuning(t)
