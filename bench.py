@@ -237,6 +237,8 @@ def main():
                     help="run the device autotuner on a sample of the batch before timing")
     ap.add_argument("--tune", default=None,
                     help="JSON tuning to install instead (keys of fc_tuning)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of autotuner results to reuse / fill")
     ap.add_argument("--serve", action="store_true",
                     help="serving mode (hill-climbing batches, Poisson arrivals, p50/p99)")
     ap.add_argument("--serve-requests", type=int, default=1000)
@@ -291,7 +293,8 @@ def main():
             t0 = time.time()
             rng = np.random.default_rng(0)
             ids = np.sort(rng.choice(nq, size=min(nq, max(4000, nq // 10)), replace=False))
-            tuning = db.autotune([w.query(int(i)) for i in ids], stream=stream)
+            tuning = db.autotune([w.query(int(i)) for i in ids], cache=args.tune_cache,
+                                 stream=stream)
             print("# autotuned on %d queries in %.1fs: %s" % (len(ids), time.time() - t0,
                                                               json.dumps(tuning)),
                   file=sys.stderr, flush=True)

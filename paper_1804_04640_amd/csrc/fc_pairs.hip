@@ -27,7 +27,7 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int kGT = 128;                 // items per tile side
-constexpr int kGW = 4;                   // 64-instance words per K step
+constexpr int kGW = 2;                   // 64-instance words per K step
 constexpr int kPanel = kGW * 4 * kGT * 16;  // bytes: [word][group][item][16]
 
 __device__ __forceinline__ void map_pair(int64_t b, int32_t npairs, int32_t splits, int32_t &p,
@@ -70,8 +70,6 @@ __global__ __launch_bounds__(256) void k_gram(const uint64_t *__restrict__ bits,
         J = I + rem;
     }
     const bool diag = I == J;
-    uint8_t *PA = lds;
-    uint8_t *PB = diag ? lds : lds + kPanel;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int item = t >> 1, half = t & 1;
     const int32_t ra = rowidx[I * kGT + item];
@@ -91,14 +89,18 @@ __global__ __launch_bounds__(256) void k_gram(const uint64_t *__restrict__ bits,
 
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
     const int grp = lane >> 4, col = lane & 15;
-    for (int64_t w = w0; w < w1; w += kGW) {  // (w1 - w0) is a multiple of 64 words
-        uint64_t xa[kGW], xb[kGW];
+    // Double-buffered panels (A and B of buffer `cur` at lds + cur * 2 * kPanel)
+    // and register prefetch of the next step's words: one barrier per step.
+    uint64_t xa[kGW], xb[kGW];
 #pragma unroll
-        for (int g = 0; g < kGW; ++g) {
-            xa[g] = ra >= 0 ? pa[w + g] : 0ull;
-            xb[g] = rb >= 0 ? pb[w + g] : 0ull;
-        }
-        __syncthreads();  // the previous step's MFMA reads are done
+    for (int g = 0; g < kGW; ++g) {
+        xa[g] = (ra >= 0 && w0 < w1) ? pa[w0 + g] : 0ull;
+        xb[g] = (rb >= 0 && w0 < w1 && !diag) ? pb[w0 + g] : 0ull;
+    }
+    int cur = 0;
+    for (int64_t w = w0; w < w1; w += kGW) {  // (w1 - w0) is a multiple of 64 words
+        uint8_t *PA = lds + cur * 2 * kPanel;
+        uint8_t *PB = diag ? PA : PA + kPanel;
 #pragma unroll
         for (int g = 0; g < kGW; ++g) {
             const uint32_t va = (uint32_t)(xa[g] >> (32 * half));
@@ -112,7 +114,14 @@ __global__ __launch_bounds__(256) void k_gram(const uint64_t *__restrict__ bits,
                     *reinterpret_cast<uint4 *>(PB + off) = expand16((vb >> (16 * gg)) & 0xFFFFu);
             }
         }
-        __syncthreads();
+        if (w + kGW < w1) {  // next step's words, in flight during the MFMAs
+#pragma unroll
+            for (int g = 0; g < kGW; ++g) {
+                xa[g] = ra >= 0 ? pa[w + kGW + g] : 0ull;
+                xb[g] = (rb >= 0 && !diag) ? pb[w + kGW + g] : 0ull;
+            }
+        }
+        __syncthreads();  // panels of `cur` complete; the other buffer is free
 #pragma unroll
         for (int g = 0; g < kGW; ++g) {
             v4i a[4], b[4];
@@ -127,6 +136,7 @@ __global__ __launch_bounds__(256) void k_gram(const uint64_t *__restrict__ bits,
                 for (int j = 0; j < 4; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], b[j], acc[i][j], 0, 0, 0);
         }
+        cur ^= 1;
     }
     // D layout of a 16x16 MFMA tile: lane l, element e -> row 4*(l/16)+e, column l%16
 #pragma unroll
@@ -255,7 +265,7 @@ extern "C" int fc_pairs(fc_db *db, const int32_t *items, int32_t ni, double mins
     static bool attr = false;
     if (!attr) {
         (void)hipFuncSetAttribute((const void *)k_gram, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  2 * kPanel);
+                                  4 * kPanel);
         (void)hipGetLastError();
         attr = true;
     }
@@ -277,7 +287,7 @@ extern "C" int fc_pairs(fc_db *db, const int32_t *items, int32_t ni, double mins
     if (db->m > 0) {
         const double ops = 2.0 * (double)db->m * (double)ni * (double)(ni + 1) / 2.0;
         ProfScope ps("k_gram", s, 0.0, ops);
-        hipLaunchKernelGGL(k_gram, dim3((unsigned)(npairs * splits)), dim3(256), 2 * kPanel, s,
+        hipLaunchKernelGGL(k_gram, dim3((unsigned)(npairs * splits)), dim3(256), 4 * kPanel, s,
                            db->d_bits, db->words, (const int32_t *)dRow.p, ntiles, npairs,
                            (int32_t)splits, C, (int32_t)ldc);
         FC_HIP(hipGetLastError());
