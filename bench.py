@@ -161,6 +161,42 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_arm(args, w):
+    """Bottom-up association-rule mining (itemsets of up to 6 items, minsup
+    0.001, minconf 0.3) on the planted-transaction database."""
+    import torch
+    from paper_1804_04640_amd import _lib, arm
+    from paper_1804_04640_amd.api import Database
+
+    db = Database(w.D, w.arity)
+    arm.mine(db, minsup=w.minsup, minconf=0.3, max_size=6)           # warm up
+    _lib.fc_profile_enable(True)
+    _lib.fc_profile_read(reset=True)
+    times = []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        freq, rules = arm.mine(db, minsup=w.minsup, minconf=0.3, max_size=6)
+        torch.cuda.synchronize()
+        times.append(1e3 * (time.perf_counter() - t0))
+    _lib.fc_profile_enable(False)
+    prof = _lib.fc_profile_read(reset=True)
+    levels = {}
+    for s in freq:
+        levels[len(s)] = levels.get(len(s), 0) + 1
+    a = prof.get("k_assign_batch", {"ms": 0.0, "launches": 1, "alg_bytes": 0.0})
+    out = {"metric": "association-rule mining time (bottom-up, single-assignment counts)",
+           "value": float(np.median(times)), "unit": "ms", "higher_is_better": False,
+           "config": {"workload": w.name, "desc": w.desc, "minsup": w.minsup, "minconf": 0.3,
+                      "max_size": 6},
+           "frequent_itemsets_by_size": levels, "rules": len(rules),
+           "kernels": {k: {"launches": v["launches"], "avg_us": 1e3 * v["ms"] / v["launches"]}
+                       for k, v in prof.items()},
+           "assign_batch_GBps": (a["alg_bytes"] / (a["ms"] * 1e-3) / 1e9) if a["ms"] else None}
+    db.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_pairs(args, w):
     """All-pairs co-occurrence: one step = Gram on MFMA + pair records."""
     import torch
@@ -242,6 +278,8 @@ def main():
     ap.add_argument("--serve", action="store_true",
                     help="serving mode (hill-climbing batches, Poisson arrivals, p50/p99)")
     ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--arm", action="store_true",
+                    help="with --workload cfg4: bottom-up association-rule mining")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter scale)")
     args = ap.parse_args()
@@ -269,6 +307,8 @@ def main():
     w, reducers = workload(args.workload)
     print("# workload %s generated in %.1fs: %s" % (w.name, time.time() - t0, w.desc),
           file=sys.stderr, flush=True)
+    if args.workload == "cfg4" and args.arm:
+        return bench_arm(args, w)
     if args.workload == "cfg4":
         return bench_pairs(args, w)
     if args.serve:

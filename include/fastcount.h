@@ -156,6 +156,18 @@ int fc_count_assignment(fc_db *db, const int32_t *vars, const uint8_t *states,
                         int32_t k, int64_t *count, void *stream);
 
 /*
+ * Many single-assignment counts in one submission (the queries of the
+ * association-rule search of Section 4.3, each a path of |Pa|+1 bitmap
+ * intersections and a popcount).  Query i assigns states_flat[var_off[i] ..
+ * var_off[i+1]) to vars_flat[var_off[i] .. var_off[i+1]); counts[i] (int64,
+ * device or host memory) receives Count(...).  Uses the bit-vectors when the
+ * handle has them, the state columns otherwise.
+ */
+int fc_count_assignments(fc_db *db, const int32_t *vars_flat,
+                         const int64_t *var_off, const uint8_t *states_flat,
+                         int64_t nq, int64_t *counts, void *stream);
+
+/*
  * Many queries of uneven size in one submission (concurrent query groups,
  * Section 3.1).  Query i is vars_flat[var_off[i] .. var_off[i+1]); its table
  * is written at tables[table_off[i] .. table_off[i] + cells_i).  var_off and

@@ -201,3 +201,33 @@ def brute_count(D, arity, vars_) -> np.ndarray:
             mask &= D[v] == s
         out[idx] = int(mask.sum())
     return out
+
+
+def arm_bruteforce(D, minsup: float, minconf: float, max_size: int = 6):
+    """Association rules over binary columns D [n][m] by exhaustive
+    enumeration (Section 4.3): every itemset S of at most `max_size` items
+    whose support Count(S)/m exceeds minsup (each support counted directly,
+    no pruning), and every rule S - {X} => X with confidence
+    Count(S)/Count(S - {X}) above minconf.  Small n only.
+    Returns (itemsets {tuple: count}, sorted rules
+    [(antecedent, consequent, support, confidence)])."""
+    import itertools
+    A = np.asarray(D).astype(bool)
+    n, m = A.shape
+    freq = {}
+    for k in range(1, max_size + 1):
+        for S in itertools.combinations(range(n), k):
+            c = int(np.logical_and.reduce(A[list(S)], axis=0).sum())
+            if m > 0 and c / m > minsup:
+                freq[S] = c
+    rules = []
+    for S, c in freq.items():
+        if len(S) < 2:
+            continue
+        for x in range(len(S)):
+            ante = S[:x] + S[x + 1:]
+            conf = c / freq[ante]
+            if conf > minconf:
+                rules.append((ante, S[x], c / m, conf))
+    rules.sort()
+    return freq, rules

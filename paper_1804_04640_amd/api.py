@@ -138,6 +138,24 @@ class Database:
         s = np.ascontiguousarray(states, np.uint8)
         return L.fc_count_assignment(self.handle, _np_ptr(v), _np_ptr(s), len(v), _stream(stream))
 
+    def count_assignments(self, queries, states, stream=None) -> np.ndarray:
+        """Batched single-assignment counts; `states` mirrors `queries`
+        (a list of state lists, or a flat uint8 array aligned with vars_flat).
+        Returns an int64 numpy array."""
+        flat, off = flatten_queries(queries)
+        if isinstance(states, np.ndarray) and states.ndim == 1 and len(states) == len(flat):
+            st = np.ascontiguousarray(states, np.uint8)
+        else:
+            st = np.concatenate([np.asarray(x, np.uint8).ravel() for x in states]) \
+                if len(states) else np.zeros(0, np.uint8)
+            st = np.ascontiguousarray(st, np.uint8)
+        if len(st) != len(flat):
+            raise ValueError("states do not match the queries")
+        out = np.zeros(len(off) - 1, np.int64)
+        L.fc_count_assignments(self.handle, _np_ptr(flat), _np_ptr(off), _np_ptr(st), len(off) - 1,
+                               _np_ptr(out), _stream(stream))
+        return out
+
     def table_offsets(self, queries) -> np.ndarray:
         flat, off = flatten_queries(queries)
         # out-of-range variables are clipped here only to size the buffer; the

@@ -442,6 +442,77 @@ __global__ void k_assign_cols(const uint8_t *__restrict__ cols, int64_t m, int64
     if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(out, cnt);
 }
 
+// Batched single-assignment counts: work unit (query, chunk of 64-instance
+// words), XCD-ordered like the tables.  Each thread ANDs two words of the k
+// bit-vector rows at a time and popcounts; one atomic per workgroup.
+struct ADesc {
+    int32_t row[FC_MAX_VARS];  // bit-vector rows (variable's first row + state)
+    int32_t k;
+    int32_t pad[3];
+};
+
+__global__ __launch_bounds__(kBlock) void k_assign_batch(const uint64_t *__restrict__ bits,
+                                                         int64_t words,
+                                                         const ADesc *__restrict__ descs,
+                                                         int32_t nd, int32_t chunks,
+                                                         unsigned long long *__restrict__ out) {
+    __shared__ unsigned long long part[kWaves];
+    int32_t di, c;
+    map_block(blockIdx.x, nd, chunks, di, c);
+    const ADesc &q = descs[di];
+    const int64_t tiles = words / (kTileRows / 64);
+    const int64_t w0 = (int64_t)c * tiles / chunks * (kTileRows / 64);
+    const int64_t w1 = (int64_t)(c + 1) * tiles / chunks * (kTileRows / 64);
+    unsigned long long cnt = 0;
+    for (int64_t w = w0 + 2 * (int64_t)threadIdx.x; w < w1; w += 2 * kBlock) {
+        uint64_t x0 = ~0ull, x1 = ~0ull;
+        for (int32_t t = 0; t < q.k; ++t) {
+            const ulonglong2 v = *reinterpret_cast<const ulonglong2 *>(bits + (int64_t)q.row[t] * words + w);
+            x0 &= v.x;
+            x1 &= v.y;
+        }
+        cnt += (unsigned long long)(__popcll(x0) + __popcll(x1));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s = 0;
+        for (int i = 0; i < kWaves; ++i) s += part[i];
+        if (s) atomicAdd(&out[di], s);
+    }
+}
+
+// The same counts from the state columns (no bit-vectors).
+__global__ __launch_bounds__(kBlock) void k_assign_batch_cols(
+    const uint8_t *__restrict__ cols, int64_t m, int64_t m_pad, const int32_t *__restrict__ vflat,
+    const int64_t *__restrict__ voff, const uint8_t *__restrict__ sflat, int32_t nd,
+    int32_t chunks, unsigned long long *__restrict__ out) {
+    __shared__ unsigned long long part[kWaves];
+    int32_t di, c;
+    map_block(blockIdx.x, nd, chunks, di, c);
+    const int64_t o0 = voff[di], o1 = voff[di + 1];
+    const int64_t tiles = m_pad / kTileRows;
+    const int64_t r0 = (int64_t)c * tiles / chunks * kTileRows;
+    const int64_t r1 = std::min<int64_t>(m, (int64_t)(c + 1) * tiles / chunks * kTileRows);
+    unsigned long long cnt = 0;
+    for (int64_t p = r0 + threadIdx.x; p < r1; p += kBlock) {
+        bool ok = true;
+        for (int64_t t = o0; t < o1; ++t) ok = ok && cols[(int64_t)vflat[t] * m_pad + p] == sflat[t];
+        cnt += ok ? 1ull : 0ull;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s = 0;
+        for (int i = 0; i < kWaves; ++i) s += part[i];
+        if (s) atomicAdd(&out[di], s);
+    }
+}
+
 // ------------------------------------------------------------------ planner
 enum Strat { S_HIST = 1, S_BITMAP = 2, S_PART = 3 };
 
@@ -1417,5 +1488,103 @@ extern "C" int fc_graph_launch(fc_graph *g, void *stream) {
     ProfScope ps("graph", (hipStream_t)stream, 0.0, 0.0);
     FC_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
     ps.end((hipStream_t)stream);
+    return FC_OK;
+}
+
+extern "C" int fc_count_assignments(fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
+                                    const uint8_t *states_flat, int64_t nq, int64_t *counts,
+                                    void *stream) {
+    clear_error();
+    std::vector<int64_t> cells;
+    int rc = validate(db, vars_flat, var_off, nq, nullptr, cells);
+    if (rc) return rc;
+    if (nq > 0 && (!states_flat || !counts)) {
+        set_error("fc_count_assignments: states_flat and counts must not be NULL");
+        return FC_ERR_INVALID;
+    }
+    for (int64_t i = 0; i < nq; ++i)
+        for (int64_t t = var_off[i]; t < var_off[i + 1]; ++t)
+            if (states_flat[t] >= db->arity[vars_flat[t]]) {
+                set_error("fc_count_assignments: query %lld: state %u of variable %d is not below "
+                          "its arity %u", (long long)i, states_flat[t], vars_flat[t],
+                          db->arity[vars_flat[t]]);
+                return FC_ERR_INVALID;
+            }
+    if (nq == 0) return FC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    FC_HIP(hipSetDevice(db->device));
+    const bool cdev = is_device_ptr(counts);
+    DevBuf dout, dq;
+    unsigned long long *out = (unsigned long long *)counts;
+    if (!cdev) {
+        FC_HIP(dout.alloc(sizeof(int64_t) * (size_t)nq, s));
+        out = (unsigned long long *)dout.p;
+    }
+    FC_HIP(fill_zero_i32((int32_t *)out, 2 * nq, s));
+    // enough workgroups, chunks a multiple of 8 (XCD order), >= 64K instances each
+    const int64_t tiles = db->m_pad / kTileRows;
+    int64_t ch = std::max<int64_t>(1, db->m_pad / 65536);
+    ch = std::min(ch, tiles);
+    if (ch >= kXcds) ch -= ch % kXcds;
+    if (db->m > 0) {
+        const double alg = (double)var_off[nq] * (double)db->m / 8.0;  // k bits per instance
+        ProfScope ps("k_assign_batch", s, alg, 0.0);
+        if (db->d_bits) {
+            std::vector<ADesc> h((size_t)nq);
+            for (int64_t i = 0; i < nq; ++i) {
+                ADesc &d = h[(size_t)i];
+                std::memset(&d, 0, sizeof d);
+                d.k = (int32_t)(var_off[i + 1] - var_off[i]);
+                for (int32_t t = 0; t < d.k; ++t) {
+                    const int32_t v = vars_flat[var_off[i] + t];
+                    d.row[t] = db->state_off[v] + states_flat[var_off[i] + t];
+                }
+            }
+            FC_HIP(dq.alloc(sizeof(ADesc) * (size_t)nq, s));
+            Staging *st = staging_acquire(sizeof(ADesc) * (size_t)nq);
+            if (!st) {
+                set_error("pinned staging allocation failed");
+                return FC_ERR_NOMEM;
+            }
+            std::memcpy(st->host, h.data(), sizeof(ADesc) * (size_t)nq);
+            hipError_t e = hipMemcpyAsync(dq.p, st->host, sizeof(ADesc) * (size_t)nq,
+                                          hipMemcpyHostToDevice, s);
+            staging_release(st, s);
+            FC_HIP(e);
+            hipLaunchKernelGGL(k_assign_batch, dim3((unsigned)(nq * ch)), dim3(kBlock), 0, s,
+                               db->d_bits, db->words, (const ADesc *)dq.p, (int32_t)nq,
+                               (int32_t)ch, out);
+        } else {
+            const size_t nv = (size_t)var_off[nq];
+            const size_t bytes = sizeof(int32_t) * nv + sizeof(int64_t) * ((size_t)nq + 1) + nv;
+            FC_HIP(dq.alloc(bytes, s));
+            Staging *st = staging_acquire(bytes);
+            if (!st) {
+                set_error("pinned staging allocation failed");
+                return FC_ERR_NOMEM;
+            }
+            char *hp = (char *)st->host;
+            std::memcpy(hp, vars_flat, sizeof(int32_t) * nv);
+            std::memcpy(hp + sizeof(int32_t) * nv, var_off, sizeof(int64_t) * ((size_t)nq + 1));
+            std::memcpy(hp + sizeof(int32_t) * nv + sizeof(int64_t) * ((size_t)nq + 1),
+                        states_flat, nv);
+            hipError_t e = hipMemcpyAsync(dq.p, st->host, bytes, hipMemcpyHostToDevice, s);
+            staging_release(st, s);
+            FC_HIP(e);
+            char *dp = (char *)dq.p;
+            hipLaunchKernelGGL(k_assign_batch_cols, dim3((unsigned)(nq * ch)), dim3(kBlock), 0, s,
+                               db->d_cols, db->m, db->m_pad, (const int32_t *)dp,
+                               (const int64_t *)(dp + sizeof(int32_t) * nv),
+                               (const uint8_t *)(dp + sizeof(int32_t) * nv +
+                                                 sizeof(int64_t) * ((size_t)nq + 1)),
+                               (int32_t)nq, (int32_t)ch, out);
+        }
+        FC_HIP(hipGetLastError());
+        ps.end(s);
+    }
+    if (!cdev) {
+        FC_HIP(hipMemcpyAsync(counts, out, sizeof(int64_t) * (size_t)nq, hipMemcpyDeviceToHost, s));
+        FC_HIP(hipStreamSynchronize(s));
+    }
     return FC_OK;
 }

@@ -233,3 +233,33 @@ def test_pairs_threshold_is_strict():
     assert [(a, b, n) for a, b, n, *_ in recs] == [(0, 2, 5)]
     a, b, nab, s, cab, cba = recs[0]
     assert (s, cab, cba) == (5 / 20, 5 / 10, 5 / 6)
+
+
+# ------------------------------------------------------------ association rules
+def test_arm_hand_example():
+    # transactions over items 0..3:  {0,1,2} {0,1} {0,2} {1,2} {0,1,2,3}
+    T = [[0, 1, 2], [0, 1], [0, 2], [1, 2], [0, 1, 2, 3]]
+    D = np.zeros((4, 5), np.uint8)
+    for p, t in enumerate(T):
+        D[t, p] = 1
+    freq, rules = orc.arm_bruteforce(D, 0.3, 0.6)
+    assert freq == {(0,): 4, (1,): 4, (2,): 4, (0, 1): 3, (0, 2): 3, (1, 2): 3, (0, 1, 2): 2}
+    # six pair rules at 3/4 and three triple rules at 2/3
+    assert len(rules) == 9
+    assert sorted(r[3] for r in rules) == [2 / 3] * 3 + [3 / 4] * 6
+    _, rules7 = orc.arm_bruteforce(D, 0.3, 0.7)
+    assert len(rules7) == 6 and all(len(r[0]) == 1 for r in rules7)
+
+
+def test_arm_antimonotone_and_counts():
+    rng = np.random.default_rng(4)
+    D = (rng.random((9, 400)) < 0.45).astype(np.uint8)
+    freq, rules = orc.arm_bruteforce(D, 0.1, 0.5, max_size=4)
+    ar = np.full(9, 2, np.uint8)
+    for S, c in freq.items():
+        assert c == orc.count_assignment(D, ar, list(S), [1] * len(S))
+        for x in range(len(S)):
+            if len(S) > 1:
+                assert S[:x] + S[x + 1:] in freq          # every subset is frequent
+    for ante, x, sup, conf in rules:
+        assert conf > 0.5 and sup > 0.1
