@@ -156,6 +156,19 @@ int fc_count_assignment(fc_db *db, const int32_t *vars, const uint8_t *states,
                         int32_t k, int64_t *count, void *stream);
 
 /*
+ * Sparse table of one query for key spaces far beyond the data (prod r_v up
+ * to 2^63, e.g. many high-arity variables): the distinct configurations that
+ * occur -- at most min(q_i r_i, m), Section 3.2 -- as mixed-radix keys (int64,
+ * same digit order as the dense table) in increasing order with their int32
+ * counts, found by sorting the instances' keys and run-length encoding them
+ * (the MSD order of Section 3.3 carried to the last digit).  keys and counts
+ * (device or host memory) hold `cap` entries; *nnz receives the number of
+ * distinct configurations, which may exceed cap.  Synchronises `stream`.
+ */
+int fc_count_sparse(fc_db *db, const int32_t *vars, int32_t k, int64_t *keys,
+                    int32_t *counts, int64_t cap, int64_t *nnz, void *stream);
+
+/*
  * Many single-assignment counts in one submission (the queries of the
  * association-rule search of Section 4.3, each a path of |Pa|+1 bitmap
  * intersections and a popcount).  Query i assigns states_flat[var_off[i] ..

@@ -311,3 +311,59 @@ int orc_gram(const uint8_t *cols, int64_t m, int32_t n, int64_t *gram)
     free(len);
     return ORC_OK;
 }
+
+static int cmp_i64(const void *a, const void *b)
+{
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
+/*
+ * Sparse table of a query (Section 2; only configurations that occur, at
+ * most min(q_i r_i, m) of them, Section 3.2): the mixed-radix key of every
+ * instance (first variable most significant), sorted, and each run of equal
+ * keys counted.  keys_out and counts_out must hold m entries.  Returns the
+ * number of distinct keys, or -1 (invalid query, state out of range, or a
+ * key space of 2^63 or more).
+ */
+int64_t orc_count_sparse(const uint8_t *cols, int64_t m, int32_t n,
+                         const uint8_t *arity, const int32_t *vars, int32_t k,
+                         int64_t *keys_out, int64_t *counts_out)
+{
+    if (check_query(n, arity, vars, k) != ORC_OK || m < 0)
+        return -1;
+    double space = 1.0;
+    for (int32_t t = 0; t < k; ++t)
+        space *= (double)arity[vars[t]];
+    if (space >= 9.2e18)
+        return -1;
+    int64_t *key = (int64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    if (!key)
+        return -1;
+    for (int64_t p = 0; p < m; ++p) {
+        int64_t idx = 0;
+        for (int32_t t = 0; t < k; ++t) {
+            int32_t v = vars[t];
+            uint8_t s = cols[(int64_t)v * m + p];
+            if (s >= arity[v]) {
+                free(key);
+                return -1;
+            }
+            idx = idx * arity[v] + s;
+        }
+        key[p] = idx;
+    }
+    qsort(key, (size_t)m, sizeof(int64_t), cmp_i64);
+    int64_t nd = 0;
+    for (int64_t p = 0; p < m; ++p) {
+        if (nd > 0 && keys_out[nd - 1] == key[p]) {
+            counts_out[nd - 1] += 1;
+        } else {
+            keys_out[nd] = key[p];
+            counts_out[nd] = 1;
+            ++nd;
+        }
+    }
+    free(key);
+    return nd;
+}

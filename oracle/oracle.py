@@ -64,6 +64,8 @@ def _load():
                 f.restype = f64
             lib.orc_bdeu.argtypes = [P, i64, i32, f64]
             lib.orc_bdeu.restype = f64
+            lib.orc_count_sparse.argtypes = [P, i64, i32, P, P, i32, P, P]
+            lib.orc_count_sparse.restype = i64
             lib.orc_gram.argtypes = [P, i64, i32, P]
             lib.orc_gram.restype = ctypes.c_int
             _lib = lib
@@ -113,6 +115,22 @@ def count_assignment(D, arity, vars_, states) -> int:
     if r < 0:
         raise ValueError("invalid assignment query")
     return int(r)
+
+
+def count_sparse(D, arity, vars_):
+    """(keys int64, counts int64) of the configurations that occur, sorted by
+    mixed-radix key (first variable most significant)."""
+    D = _cols(D)
+    arity = np.ascontiguousarray(arity, dtype=np.uint8)
+    v = np.ascontiguousarray(vars_, dtype=np.int32)
+    n, m = D.shape
+    keys = np.empty(max(m, 1), np.int64)
+    cnt = np.empty(max(m, 1), np.int64)
+    nd = _load().orc_count_sparse(_ptr(D), m, n, _ptr(arity), _ptr(v), len(v), _ptr(keys),
+                                  _ptr(cnt))
+    if nd < 0:
+        raise ValueError("invalid sparse query")
+    return keys[:nd].copy(), cnt[:nd].copy()
 
 
 def _qr(table, r_child):

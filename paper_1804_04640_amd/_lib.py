@@ -32,7 +32,7 @@ FC_RED_MI = 8
 
 # every symbol the header declares
 EXPORTS = ("fc_db_create", "fc_db_destroy", "fc_db_info", "fc_db_marginals", "fc_table_cells",
-           "fc_count", "fc_count_assignment", "fc_count_assignments", "fc_count_batch", "fc_count_reduce", "fc_pairs",
+           "fc_count", "fc_count_assignment", "fc_count_assignments", "fc_count_sparse", "fc_count_batch", "fc_count_reduce", "fc_pairs",
            "fc_batch_footprint", "fc_graph_create", "fc_graph_launch", "fc_graph_destroy",
            "fc_db_get_tuning", "fc_db_set_tuning", "fc_autotune",
            "fc_profile_enable", "fc_profile_read", "fc_last_error")
@@ -108,6 +108,7 @@ def load():
             "fc_count": (ctypes.c_int, [P, P, i32, P, i64, P]),
             "fc_count_assignment": (ctypes.c_int, [P, P, P, i32, P, P]),
             "fc_count_assignments": (ctypes.c_int, [P, P, P, P, i64, P, P]),
+            "fc_count_sparse": (ctypes.c_int, [P, P, i32, P, P, i64, P, P]),
             "fc_count_batch": (ctypes.c_int, [P, P, P, i64, P, P, u32, P]),
             "fc_count_reduce": (ctypes.c_int, [P, P, P, i64, u32, P, P, P, P, P, u32, P]),
             "fc_pairs": (ctypes.c_int, [P, P, i32, ctypes.c_double, P, P, i64, P, P]),
@@ -179,6 +180,12 @@ def fc_count_assignment(db, vars_, states, k, stream):
 def fc_count_assignments(db, vars_flat, var_off, states_flat, nq, counts, stream):
     return check(load().fc_count_assignments(db, vars_flat, var_off, states_flat, nq, counts,
                                              stream))
+
+
+def fc_count_sparse(db, vars_, k, keys, counts, cap, stream):
+    nnz = ctypes.c_int64()
+    check(load().fc_count_sparse(db, vars_, k, keys, counts, cap, ctypes.byref(nnz), stream))
+    return nnz.value
 
 
 def fc_count_batch(db, vars_flat, var_off, nq, tables, table_off, flags, stream):

@@ -138,6 +138,18 @@ class Database:
         s = np.ascontiguousarray(states, np.uint8)
         return L.fc_count_assignment(self.handle, _np_ptr(v), _np_ptr(s), len(v), _stream(stream))
 
+    def count_sparse(self, vars_, cap: Optional[int] = None, stream=None):
+        """(keys int64, counts int32) of the configurations that occur, in
+        increasing mixed-radix key order (host numpy arrays)."""
+        v = np.ascontiguousarray(vars_, np.int32)
+        cap = self.m if cap is None else int(cap)
+        keys = np.zeros(max(cap, 1), np.int64)
+        cnt = np.zeros(max(cap, 1), np.int32)
+        nnz = L.fc_count_sparse(self.handle, _np_ptr(v), len(v), _np_ptr(keys), _np_ptr(cnt), cap,
+                                _stream(stream))
+        n = min(nnz, cap)
+        return keys[:n], cnt[:n], nnz
+
     def count_assignments(self, queries, states, stream=None) -> np.ndarray:
         """Batched single-assignment counts; `states` mirrors `queries`
         (a list of state lists, or a flat uint8 array aligned with vars_flat).

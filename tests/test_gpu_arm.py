@@ -54,3 +54,28 @@ def test_mining_on_planted_transactions():
         # nothing frequent was missed among itemsets of size <= 3
         ref, _ = orc.arm_bruteforce(w.D[:, :], 0.002, 0.3, max_size=2)
         assert {s: c for s, c in freq.items() if len(s) <= 2} == ref
+
+
+def test_sparse_tables():
+    from paper_1804_04640_amd import synth as S
+    rng = S.rng_for(77)
+    n = 10
+    ar = rng.integers(3, 100, size=n).astype(np.uint8)         # Mildew-like arities
+    order, parents = S.random_dag(rng, n, 3)
+    D = S.forward_sample(rng, ar, order, parents, 150_001, 0.5)
+    with Database(D, ar) as db:
+        for vs in ([0, 1, 2, 3, 4, 5, 6, 7], [9, 3, 5], [4], list(range(10))[:8][::-1]):
+            keys, cnt, nnz = db.count_sparse(vs)
+            rk, rc = orc.count_sparse(D, ar, vs)
+            assert nnz == len(rk)
+            np.testing.assert_array_equal(keys, rk)
+            np.testing.assert_array_equal(cnt, rc)
+        # a small table: sparse equals the dense table's non-zeros
+        vs = [2, 5]
+        dense = db.count(vs).cpu().numpy()
+        keys, cnt, _ = db.count_sparse(vs)
+        nz = np.nonzero(dense)[0]
+        np.testing.assert_array_equal(keys, nz)
+        np.testing.assert_array_equal(cnt, dense[nz])
+        keys, cnt, nnz = db.count_sparse([0, 1, 2], cap=5)
+        assert len(keys) == 5 and nnz > 5

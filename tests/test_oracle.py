@@ -263,3 +263,29 @@ def test_arm_antimonotone_and_counts():
                 assert S[:x] + S[x + 1:] in freq          # every subset is frequent
     for ante, x, sup, conf in rules:
         assert conf > 0.5 and sup > 0.1
+
+
+# ------------------------------------------------------------ sparse tables
+@pytest.mark.parametrize("seed", range(15))
+def test_sparse_table_is_dense_nonzeros(seed):
+    rng, D, ar = rand_db(seed, n=5, m=int(np.random.default_rng(seed).integers(1, 400)), rmax=7)
+    vs = [int(v) for v in rng.permutation(5)[: int(rng.integers(1, 6))]]
+    T = orc.count(D, ar, vs)
+    keys, cnt = orc.count_sparse(D, ar, vs)
+    nz = np.nonzero(T)[0]
+    np.testing.assert_array_equal(keys, nz)
+    np.testing.assert_array_equal(cnt, T[nz])
+    assert len(keys) <= min(T.size, D.shape[1])
+
+
+def test_sparse_table_huge_key_space():
+    rng = np.random.default_rng(2)
+    ar = np.full(8, 99, np.uint8)                      # 99^8 ~ 9.2e15 cells
+    D = rng.integers(0, 99, size=(8, 3000)).astype(np.uint8)
+    D[:, 1000:1010] = D[:, 0:1]                        # ten copies of instance 0
+    keys, cnt = orc.count_sparse(D, ar, list(range(8)))
+    assert int(cnt.sum()) == 3000 and np.all(np.diff(keys) > 0)
+    key0 = 0
+    for v in range(8):
+        key0 = key0 * 99 + int(D[v, 0])
+    assert int(cnt[np.searchsorted(keys, key0)]) >= 11
