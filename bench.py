@@ -161,6 +161,42 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_parents(args):
+    """Exact parent-set assignment (every child, every |Pa| <= MAX_PA, MDL)
+    over a 37-variable random-DAG sample with m = 100,000 instances."""
+    import torch
+    from paper_1804_04640_amd import _lib, parents, synth
+    from paper_1804_04640_amd.api import Database
+
+    w = synth.cfg2(m=100_000, nq=1)
+    db = Database(w.D, w.arity)
+    rng = np.random.default_rng(0)
+    sample = [np.concatenate([rng.choice(np.delete(np.arange(w.n), c), size=int(rng.integers(0, args.parents + 1)), replace=False), [c]]).astype(np.int32)
+              for c in rng.integers(0, w.n, size=4000)]
+    tuning = db.autotune(sample)
+    parents.best_parents(db, max_pa=1)                                # warm up
+    _lib.fc_profile_enable(True)
+    _lib.fc_profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    best, stats = parents.best_parents(db, max_pa=args.parents, score="mdl")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    _lib.fc_profile_enable(False)
+    prof = _lib.fc_profile_read(reset=True)
+    gpu_ms = sum(v["ms"] for v in prof.values())
+    out = {"metric": "exact parent-set assignment time (all children, MDL)",
+           "value": dt, "unit": "s", "higher_is_better": False,
+           "config": {"workload": "bn-family n=37 m=100000", "max_parents": args.parents,
+                      "tuning": tuning},
+           "families_scored": stats["scored"], "families_pruned": stats["pruned"],
+           "levels": stats["levels"], "gpu_kernel_s": gpu_ms / 1e3,
+           "query_rows_per_s": stats["scored"] * w.m / dt,
+           "best_parents": {int(c): list(p) for c, (p, _) in sorted(best.items())}}
+    db.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_arm(args, w):
     """Bottom-up association-rule mining (itemsets of up to 6 items, minsup
     0.001, minconf 0.3) on the planted-transaction database."""
@@ -278,6 +314,9 @@ def main():
     ap.add_argument("--serve", action="store_true",
                     help="serving mode (hill-climbing batches, Poisson arrivals, p50/p99)")
     ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--parents", type=int, default=0, metavar="MAX_PA",
+                    help="exact parent-set assignment with |Pa| <= MAX_PA on a 37-variable "
+                         "DAG sample of m=100,000 (MDL)")
     ap.add_argument("--arm", action="store_true",
                     help="with --workload cfg4: bottom-up association-rule mining")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -307,6 +346,8 @@ def main():
     w, reducers = workload(args.workload)
     print("# workload %s generated in %.1fs: %s" % (w.name, time.time() - t0, w.desc),
           file=sys.stderr, flush=True)
+    if args.parents:
+        return bench_parents(args)
     if args.workload == "cfg4" and args.arm:
         return bench_arm(args, w)
     if args.workload == "cfg4":

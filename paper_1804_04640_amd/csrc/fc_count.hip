@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <thread>
 
 #include "fc_internal.h"
 
@@ -531,7 +532,9 @@ struct Launch {
 
 struct Plan {
     std::vector<QDesc> work;    // counting descriptors, grouped by launch
-    std::vector<QDesc> query;   // one per query, in query order (reducers)
+    std::vector<QDesc> query;   // one per query, in query order, when needed
+    bool windows = false;       // some query is split into key windows
+    int64_t nq = 0;
     std::vector<Launch> launches;
     int64_t total_cells = 0;    // table buffer size in cells
     bool packed = true;         // tables back to back in query order
@@ -629,9 +632,128 @@ static int32_t pick_chunks(const fc_db *db, int64_t nd, int64_t cells, int strat
     return (int32_t)ch;
 }
 
+// Planning: validation, cells, table offsets, strategy per query shape, and
+// the grouping of descriptors into launches, in two passes over contiguous
+// query ranges (several host threads for large batches): pass 1 validates and
+// counts the descriptors of every launch bucket, pass 2 writes each
+// descriptor straight into its final slot.  The order inside a bucket is the
+// query order, whatever the number of threads.
+constexpr int kBuckets = 3 * 8 * 7 * 2;  // strategy x K x LDS class x 24-bit strides
+
+static inline int bucket_of(int st, int K, int cls, bool small) {
+    return (((st - 1) * 8 + (K - 1)) * 7 + cls) * 2 + (small ? 1 : 0);
+}
+
+namespace {
+struct RangeStat {
+    int64_t lo = 0, hi = 0;
+    int64_t err_q = -1;
+    int err_code = FC_OK;
+    std::string err;
+    int64_t cells_sum = 0;
+    bool windows = false;
+    std::vector<int64_t> cnt, cur;
+    std::vector<double> bytes;
+    std::vector<int32_t> maxc;
+};
+
+// Strategy of one query (validated), and its window size for partitions.
+inline int choose(const fc_db *db, uint32_t forced, int64_t k, int64_t c, int64_t &win) {
+    int st;
+    if (forced == FC_STRAT_BITMAP)
+        st = c <= 128 ? S_BITMAP : (c <= kHistMaxCells ? S_HIST : S_PART);
+    else if (forced == FC_STRAT_HIST)
+        st = c <= kHistMaxCells ? S_HIST : S_PART;
+    else if (forced == FC_STRAT_PARTITION)
+        st = S_PART;
+    else if (db->d_bits && db->tune.bitmap_for((int)k, c))
+        st = S_BITMAP;
+    else
+        st = c <= kHistMaxCells ? S_HIST : S_PART;
+    win = c;
+    if (st == S_PART) {
+        // windows over the top key digits: at least two when forced
+        win = kHistMaxCells;
+        if (forced == FC_STRAT_PARTITION && c <= kHistMaxCells) win = (c + 1) / 2;
+        if (win < 1) win = 1;
+    }
+    return st;
+}
+
+// Validates query i; returns its cells (> 0) or 0 with the error filled in.
+inline int64_t check_one(const fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
+                         int64_t i, RangeStat &R) {
+    const int64_t k = var_off[i + 1] - var_off[i];
+    char buf[160];
+    if (k < 1 || k > FC_MAX_VARS) {
+        snprintf(buf, sizeof buf, "query %lld has %lld variables (need 1..%d)", (long long)i,
+                 (long long)k, FC_MAX_VARS);
+        R.err = buf;
+        R.err_code = FC_ERR_INVALID;
+        return 0;
+    }
+    const int32_t *v = vars_flat + var_off[i];
+    int64_t c = 1;
+    for (int64_t t = 0; t < k; ++t) {
+        if (v[t] < 0 || v[t] >= db->n) {
+            snprintf(buf, sizeof buf, "query %lld: variable %d out of range [0, %d)", (long long)i,
+                     v[t], db->n);
+            R.err = buf;
+            R.err_code = FC_ERR_INVALID;
+            return 0;
+        }
+        for (int64_t u = 0; u < t; ++u)
+            if (v[u] == v[t]) {
+                snprintf(buf, sizeof buf, "query %lld: variable %d appears twice", (long long)i,
+                         v[t]);
+                R.err = buf;
+                R.err_code = FC_ERR_INVALID;
+                return 0;
+            }
+        c *= db->arity[v[t]];
+        if (c > INT32_MAX) {
+            snprintf(buf, sizeof buf, "query %lld: table exceeds int32 indexing (use the sparse "
+                     "path)", (long long)i);
+            R.err = buf;
+            R.err_code = FC_ERR_RANGE;
+            return 0;
+        }
+    }
+    return c;
+}
+
+template <typename F>
+void parallel_ranges(std::vector<RangeStat> &R, F f) {
+    if (R.size() == 1) {
+        f(R[0]);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(R.size());
+    for (auto &r : R) th.emplace_back([&f, &r] { f(r); });
+    for (auto &t : th) t.join();
+}
+}  // namespace
+
 static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
-                      int64_t nq, const int64_t *table_off, uint32_t flags,
-                      const std::vector<int64_t> &cells, Plan &P) {
+                      int64_t nq, const int64_t *table_off, uint32_t flags, bool reducers,
+                      Plan &P) {
+    if (!db) {
+        set_error("NULL database handle");
+        return FC_ERR_INVALID;
+    }
+    if (nq < 0 || (nq > 0 && (!vars_flat || !var_off))) {
+        set_error("need nq >= 0, vars_flat and var_off");
+        return FC_ERR_INVALID;
+    }
+    if (nq > (int64_t)INT32_MAX / 2) {
+        set_error("batch of %lld queries is too large", (long long)nq);
+        return FC_ERR_RANGE;
+    }
+    if (nq > 0 && var_off[0] != 0) {
+        set_error("var_off[0] must be 0");
+        return FC_ERR_INVALID;
+    }
     const uint32_t forced = flags & FC_STRAT_MASK;
     if (forced > FC_STRAT_PARTITION) {
         set_error("unknown strategy %u", forced);
@@ -642,81 +764,139 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
         return FC_ERR_INVALID;
     }
     P.packed = table_off == nullptr;
-    P.query.resize((size_t)nq);
-    int64_t off = 0;
-    // buckets: strat(3) x K(8) x class(7) x small(2)
-    std::vector<std::vector<QDesc>> bucket(3 * 8 * 7 * 2);
-    auto bidx = [](int st, int K, int cls, bool small) {
-        return (((st - 1) * 8 + (K - 1)) * 7 + cls) * 2 + (small ? 1 : 0);
-    };
-    for (int64_t i = 0; i < nq; ++i) {
-        QDesc d;
-        std::memset(&d, 0, sizeof d);
-        const int64_t k = var_off[i + 1] - var_off[i];
-        const int64_t c = cells[(size_t)i];
-        d.k = (int32_t)k;
-        for (int64_t t = 0; t < k; ++t) d.var[t] = vars_flat[var_off[i] + t];
-        d.cells = (int32_t)c;
-        d.qid = (int32_t)i;
-        d.table_off = table_off ? table_off[i] : off;
-        off += c;
-        d.win_base = 0;
-        d.win_cells = (int32_t)c;
-        P.query[(size_t)i] = d;
-
-        int st;
-        if (forced == FC_STRAT_BITMAP)
-            st = c <= 128 ? S_BITMAP : (c <= kHistMaxCells ? S_HIST : S_PART);
-        else if (forced == FC_STRAT_HIST)
-            st = c <= kHistMaxCells ? S_HIST : S_PART;
-        else if (forced == FC_STRAT_PARTITION)
-            st = S_PART;
-        else if (db->d_bits && db->tune.bitmap_for((int)k, c))
-            st = S_BITMAP;
-        else
-            st = c <= kHistMaxCells ? S_HIST : S_PART;
-        const bool small = c < (int64_t(1) << 24);
-        if (st == S_BITMAP) {
-            bucket[bidx(S_BITMAP, (int)k, 0, false)].push_back(d);
-        } else if (st == S_HIST) {
-            bucket[bidx(S_HIST, (int)k, hist_class(c), small)].push_back(d);
-        } else {
-            // windows over the top key digits: at least two when forced
-            int64_t win = kHistMaxCells;
-            if (forced == FC_STRAT_PARTITION && c <= kHistMaxCells) win = (c + 1) / 2;
-            if (win < 1) win = 1;
+    P.nq = nq;
+    const int64_t total_cells_in = table_off ? table_off[nq] : 0;
+    unsigned hw = std::thread::hardware_concurrency();
+    int64_t T = std::min<int64_t>(std::max<unsigned>(1u, std::min(16u, hw ? hw : 1u)),
+                                  std::max<int64_t>(1, nq / 32768));
+    std::vector<RangeStat> R((size_t)T);
+    for (int64_t t = 0; t < T; ++t) {
+        R[(size_t)t].lo = nq * t / T;
+        R[(size_t)t].hi = nq * (t + 1) / T;
+        R[(size_t)t].cnt.assign(kBuckets, 0);
+        R[(size_t)t].bytes.assign(kBuckets, 0.0);
+        R[(size_t)t].maxc.assign(kBuckets, 0);
+    }
+    // pass 1: validate, count descriptors per bucket
+    parallel_ranges(R, [&](RangeStat &r) {
+        for (int64_t i = r.lo; i < r.hi; ++i) {
+            const int64_t c = check_one(db, vars_flat, var_off, i, r);
+            if (!c) {
+                r.err_q = i;
+                return;
+            }
+            if (table_off && (table_off[i] < 0 || table_off[i] + c > total_cells_in)) {
+                char buf[160];
+                snprintf(buf, sizeof buf, "query %lld: table_off places its %lld cells outside "
+                         "[0, %lld)", (long long)i, (long long)c, (long long)total_cells_in);
+                r.err = buf;
+                r.err_code = FC_ERR_INVALID;
+                r.err_q = i;
+                return;
+            }
+            const int64_t k = var_off[i + 1] - var_off[i];
+            int64_t win;
+            const int st = choose(db, forced, k, c, win);
+            const bool small = c < (int64_t(1) << 24);
+            r.cells_sum += c;
             for (int64_t b0 = 0; b0 < c; b0 += win) {
-                QDesc w = d;
-                w.win_base = (int32_t)b0;
-                w.win_cells = (int32_t)std::min<int64_t>(win, c - b0);
-                bucket[bidx(S_PART, (int)k, hist_class(w.win_cells), small)].push_back(w);
+                const int64_t wc = std::min<int64_t>(win, c - b0);
+                const int b = st == S_BITMAP ? bucket_of(S_BITMAP, (int)k, 0, false)
+                                             : bucket_of(st, (int)k, hist_class(wc), small);
+                r.cnt[(size_t)b] += 1;
+                r.bytes[(size_t)b] += (double)k * (double)db->m * ((double)wc / (double)c);
+                r.maxc[(size_t)b] = std::max<int32_t>(r.maxc[(size_t)b], (int32_t)wc);
+                if (st == S_PART) r.windows = true;
+            }
+        }
+    });
+    for (auto &r : R)
+        if (r.err_q >= 0) {
+            set_error("%s", r.err.c_str());
+            return r.err_code;
+        }
+    P.windows = false;
+    for (auto &r : R) P.windows = P.windows || r.windows;
+    // bucket starts (launch order) and per-range cursors
+    std::vector<int64_t> start(kBuckets + 1, 0);
+    for (int b = 0; b < kBuckets; ++b) {
+        int64_t tot = 0;
+        for (auto &r : R) tot += r.cnt[(size_t)b];
+        start[(size_t)b + 1] = start[(size_t)b] + tot;
+    }
+    {
+        std::vector<int64_t> run(start.begin(), start.end() - 1);
+        for (auto &r : R) {
+            r.cur.assign(kBuckets, 0);
+            for (int b = 0; b < kBuckets; ++b) {
+                r.cur[(size_t)b] = run[(size_t)b];
+                run[(size_t)b] += r.cnt[(size_t)b];
             }
         }
     }
-    P.total_cells = table_off ? table_off[nq] : off;
+    const bool need_query = !P.packed || (reducers && P.windows);
+    P.work.resize((size_t)start[kBuckets]);
+    if (need_query) P.query.resize((size_t)nq);
+    std::vector<int64_t> base((size_t)T, 0);
+    for (int64_t t = 1; t < T; ++t) base[(size_t)t] = base[(size_t)t - 1] + R[(size_t)t - 1].cells_sum;
+    P.total_cells = table_off ? total_cells_in : (T ? base[(size_t)T - 1] + R[(size_t)T - 1].cells_sum : 0);
+    // pass 2: write every descriptor into its slot
+    for (int64_t t = 0; t < T; ++t) R[(size_t)t].cells_sum = base[(size_t)t];  // reuse as offset
+    parallel_ranges(R, [&](RangeStat &r) {
+        int64_t off = r.cells_sum;
+        for (int64_t i = r.lo; i < r.hi; ++i) {
+            const int64_t k = var_off[i + 1] - var_off[i];
+            int64_t c = 1;
+            QDesc d;
+            std::memset(&d, 0, sizeof d);
+            for (int64_t t = 0; t < k; ++t) {
+                d.var[t] = vars_flat[var_off[i] + t];
+                c *= db->arity[d.var[t]];
+            }
+            d.k = (int32_t)k;
+            d.cells = (int32_t)c;
+            d.qid = (int32_t)i;
+            d.table_off = table_off ? table_off[i] : off;
+            off += c;
+            d.win_base = 0;
+            d.win_cells = (int32_t)c;
+            if (need_query) P.query[(size_t)i] = d;
+            int64_t win;
+            const int st = choose(db, forced, k, c, win);
+            const bool small = c < (int64_t(1) << 24);
+            for (int64_t b0 = 0; b0 < c; b0 += win) {
+                const int64_t wc = std::min<int64_t>(win, c - b0);
+                const int b = st == S_BITMAP ? bucket_of(S_BITMAP, (int)k, 0, false)
+                                             : bucket_of(st, (int)k, hist_class(wc), small);
+                QDesc w = d;
+                w.win_base = (int32_t)b0;
+                w.win_cells = (int32_t)wc;
+                P.work[(size_t)r.cur[(size_t)b]++] = w;
+            }
+        }
+    });
     for (int st = 1; st <= 3; ++st)
         for (int K = 1; K <= 8; ++K)
             for (int cls = 0; cls < 7; ++cls)
                 for (int sm = 0; sm < 2; ++sm) {
-                    auto &b = bucket[bidx(st, K, cls, sm != 0)];
-                    if (b.empty()) continue;
+                    const int b = bucket_of(st, K, cls, sm != 0);
+                    const int64_t cnt = start[(size_t)b + 1] - start[(size_t)b];
+                    if (!cnt) continue;
                     Launch L;
                     L.strat = st;
                     L.K = K;
                     L.small = sm != 0;
-                    L.first = (int64_t)P.work.size();
-                    L.count = (int32_t)b.size();
+                    L.first = start[(size_t)b];
+                    L.count = (int32_t)cnt;
                     int64_t maxc = 0;
-                    for (auto &d : b) maxc = std::max<int64_t>(maxc, d.win_cells);
+                    double bytes = 0.0;
+                    for (auto &r : R) {
+                        maxc = std::max<int64_t>(maxc, r.maxc[(size_t)b]);
+                        bytes += r.bytes[(size_t)b];
+                    }
                     L.chunks = pick_chunks(db, L.count, maxc, st);
                     L.packed16 = st == S_HIST && cls < kHist16Classes;
-                    if (st == S_BITMAP)
-                        L.lds_bytes = (int32_t)(maxc * kBlock * 4);
-                    else
-                        L.lds_bytes = kClassLds[cls];
-                    double bytes = 0.0;
-                    for (auto &d : b)
-                        bytes += (double)d.k * (double)db->m * ((double)d.win_cells / (double)d.cells);
+                    L.lds_bytes = st == S_BITMAP ? (int32_t)(maxc * kBlock * 4) : kClassLds[cls];
                     L.alg_bytes = bytes;
                     if (st == S_BITMAP)
                         snprintf(L.name, sizeof L.name, "k_bitmap<%d,%d>", K,
@@ -725,7 +905,6 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
                         snprintf(L.name, sizeof L.name, "k_hist16<%d>", K);
                     else
                         snprintf(L.name, sizeof L.name, "k_hist<%d,%d>", K, sm);
-                    P.work.insert(P.work.end(), b.begin(), b.end());
                     P.launches.push_back(L);
                 }
     return FC_OK;
@@ -864,7 +1043,7 @@ struct Image {
 
 static void make_image(const fc_db *db, const Plan &P, uint32_t reducers, Image &I) {
     for (const Launch &L : P.launches) {
-        if ((int64_t)P.query.size() <= db->tune.persistent_max_queries &&
+        if (P.nq <= db->tune.persistent_max_queries &&
             L.lds_bytes <= kPersistentLds) {
             PGroup g;
             g.vbase = I.vtotal;
@@ -883,7 +1062,7 @@ static void make_image(const fc_db *db, const Plan &P, uint32_t reducers, Image 
             I.solo.push_back(&L);
         }
     }
-    I.with_query = reducers != 0 || !P.packed;
+    I.with_query = !P.query.empty();
     size_t b = sizeof(QDesc) * P.work.size();
     I.off_query = b;
     if (I.with_query) b += sizeof(QDesc) * P.query.size();
@@ -944,9 +1123,13 @@ static int enqueue_batch(fc_db *db, const Plan &P, const Image &I, void *dimg, i
             ps.end(s);
         }
     }
-    if (reducers && !P.query.empty()) {
+    if (reducers && P.nq > 0) {
+        // one descriptor per query: the per-query list when windows split a
+        // query, else the counting descriptors themselves (scores go by qid)
+        const QDesc *rd = I.with_query ? dq : dw;
+        const int64_t nrd = I.with_query ? (int64_t)P.query.size() : (int64_t)P.work.size();
         ProfScope ps("k_reduce", s, 0.0, 0.0);
-        FC_HIP(launch_reduce(db, dq, (int64_t)P.query.size(), tables, reducers, ess, scores, err, s));
+        FC_HIP(launch_reduce(db, rd, nrd, P.nq, tables, reducers, ess, scores, err, s));
         ps.end(s);
     }
     return FC_OK;
@@ -996,15 +1179,13 @@ extern "C" int fc_count_batch(fc_db *db, const int32_t *vars_flat, const int64_t
                               int64_t nq, int32_t *tables, const int64_t *table_off,
                               uint32_t flags, void *stream) {
     clear_error();
-    std::vector<int64_t> cells;
-    int rc = validate(db, vars_flat, var_off, nq, table_off, cells);
-    if (rc) return rc;
+    int rc = FC_OK;
     if (nq > 0 && !tables) {
         set_error("fc_count_batch: tables is NULL");
         return FC_ERR_INVALID;
     }
     Plan P;
-    if ((rc = build_plan(db, vars_flat, var_off, nq, table_off, flags, cells, P))) return rc;
+    if ((rc = build_plan(db, vars_flat, var_off, nq, table_off, flags, false, P))) return rc;
     if (nq == 0) return FC_OK;
     hipStream_t s = (hipStream_t)stream;
     FC_HIP(hipSetDevice(db->device));
@@ -1046,9 +1227,7 @@ extern "C" int fc_count_reduce(fc_db *db, const int32_t *vars_flat, const int64_
                                float *scores, float *err, int32_t *tables,
                                const int64_t *table_off, uint32_t flags, void *stream) {
     clear_error();
-    std::vector<int64_t> cells;
-    int rc = validate(db, vars_flat, var_off, nq, table_off, cells);
-    if (rc) return rc;
+    int rc = FC_OK;
     if (reducers == 0 || (reducers & ~(uint32_t)(FC_RED_LL | FC_RED_MDL | FC_RED_BDEU | FC_RED_MI))) {
         set_error("fc_count_reduce: reducer mask %#x is empty or unknown", reducers);
         return FC_ERR_INVALID;
@@ -1067,7 +1246,7 @@ extern "C" int fc_count_reduce(fc_db *db, const int32_t *vars_flat, const int64_
         return FC_ERR_INVALID;
     }
     Plan P;
-    if ((rc = build_plan(db, vars_flat, var_off, nq, table_off, flags, cells, P))) return rc;
+    if ((rc = build_plan(db, vars_flat, var_off, nq, table_off, flags, true, P))) return rc;
     if (nq == 0) return FC_OK;
     hipStream_t s = (hipStream_t)stream;
     FC_HIP(hipSetDevice(db->device));
@@ -1170,11 +1349,9 @@ extern "C" int fc_batch_footprint(const fc_db *db, const int32_t *vars_flat,
         set_error("fc_batch_footprint: bytes is NULL");
         return FC_ERR_INVALID;
     }
-    std::vector<int64_t> cells;
-    int rc = validate(db, vars_flat, var_off, nq, nullptr, cells);
-    if (rc) return rc;
+    int rc = FC_OK;
     Plan P;
-    if ((rc = build_plan(db, vars_flat, var_off, nq, nullptr, flags, cells, P))) return rc;
+    if ((rc = build_plan(db, vars_flat, var_off, nq, nullptr, flags, true, P))) return rc;
     *bytes = (int64_t)sizeof(int32_t) * P.total_cells +
              (int64_t)sizeof(QDesc) * (int64_t)(P.work.size() + P.query.size()) +
              (int64_t)sizeof(float) * 2 * 4 * nq;
@@ -1409,9 +1586,7 @@ extern "C" int fc_graph_create(fc_db *db, const int32_t *vars_flat, const int64_
         return FC_ERR_INVALID;
     }
     *out = nullptr;
-    std::vector<int64_t> cells;
-    int rc = validate(db, vars_flat, var_off, nq, table_off, cells);
-    if (rc) return rc;
+    int rc = FC_OK;
     if (nq < 1) {
         set_error("fc_graph_create: empty batch");
         return FC_ERR_INVALID;
@@ -1450,7 +1625,7 @@ extern "C" int fc_graph_create(fc_db *db, const int32_t *vars_flat, const int64_
         fc_graph *g;
         ~Guard() { if (g) fc_graph_destroy(g); }
     } guard{g};
-    if ((rc = build_plan(db, vars_flat, var_off, nq, table_off, flags, cells, g->P))) return rc;
+    if ((rc = build_plan(db, vars_flat, var_off, nq, table_off, flags, reducers != 0, g->P))) return rc;
     make_image(db, g->P, reducers, g->I);
     FC_HIP(hipMalloc(&g->dimg, g->I.bytes));
     std::vector<char> host(g->I.bytes);

@@ -57,17 +57,35 @@ hipError_t fill_zero_i32(int32_t *p, int64_t n, hipStream_t s) {
 static std::mutex g_stage_mu;
 static std::vector<Staging *> g_stage_free;
 
+static size_t g_stage_count = 0;
+constexpr size_t kStageMax = 8;
+
 Staging *staging_acquire(size_t bytes) {
+    // Prefer a free buffer whose last copy has completed and that is large
+    // enough, then any completed one, then a new buffer (up to kStageMax), and
+    // only then wait for the oldest: the host can plan ahead of the device.
     Staging *st = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_stage_mu);
-        for (size_t i = 0; i < g_stage_free.size(); ++i)
-            if (g_stage_free[i]->cap >= bytes || i + 1 == g_stage_free.size()) {
-                st = g_stage_free[i];
-                g_stage_free.erase(g_stage_free.begin() + (long)i);
-                break;
+        int pick = -1;
+        for (int pass = 0; pass < 2 && pick < 0; ++pass)
+            for (size_t i = 0; i < g_stage_free.size(); ++i) {
+                Staging *c = g_stage_free[i];
+                const bool idle = !c->done || hipEventQuery(c->done) == hipSuccess;
+                if (idle && (pass == 1 || c->cap >= bytes)) {
+                    pick = (int)i;
+                    break;
+                }
             }
+        if (pick < 0 && g_stage_count >= kStageMax && !g_stage_free.empty()) pick = 0;
+        if (pick >= 0) {
+            st = g_stage_free[(size_t)pick];
+            g_stage_free.erase(g_stage_free.begin() + pick);
+        } else {
+            ++g_stage_count;
+        }
     }
+    (void)hipGetLastError();  // hipEventQuery reports "not ready" as an error code
     if (!st) st = new (std::nothrow) Staging();
     if (!st) return nullptr;
     if (st->done) (void)hipEventSynchronize(st->done);  // previous copy out of it

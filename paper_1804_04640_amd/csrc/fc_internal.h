@@ -128,8 +128,9 @@ struct ProfScope {
     void end(hipStream_t s);
 };
 
-// Reducer launch (fc_reduce.hip).  descs: one QDesc per query (device).
-hipError_t launch_reduce(const fc_db *db, const QDesc *descs, int64_t nq,
+// Reducer launch (fc_reduce.hip).  descs: exactly one QDesc per query
+// (device, any order); scores[slot * nq + qid].
+hipError_t launch_reduce(const fc_db *db, const QDesc *descs, int64_t nd, int64_t nq,
                          const int32_t *tables, uint32_t reducers, double ess,
                          float *scores, float *err, hipStream_t s);
 

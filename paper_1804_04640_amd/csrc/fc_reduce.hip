@@ -119,7 +119,8 @@ __device__ __forceinline__ float g_fun(float d) {
     return (1.0f + d) * log1pf(d) - d;
 }
 
-__global__ __launch_bounds__(256) void k_reduce(const QDesc *__restrict__ descs, int64_t nq,
+__global__ __launch_bounds__(256) void k_reduce(const QDesc *__restrict__ descs, int64_t nd,
+                                                int64_t nq,
                                                 const int32_t *__restrict__ tables,
                                                 const uint8_t *__restrict__ arity,
                                                 const int32_t *__restrict__ soff,
@@ -128,9 +129,9 @@ __global__ __launch_bounds__(256) void k_reduce(const QDesc *__restrict__ descs,
                                                 float *__restrict__ scores,
                                                 float *__restrict__ err) {
     const int lane = threadIdx.x & 63;
-    const int64_t qi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (qi >= nq) return;
-    const QDesc &d = descs[qi];
+    const int64_t di = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (di >= nd) return;
+    const QDesc &d = descs[di];
     const int32_t child = d.var[d.k - 1];
     const int32_t r = arity[child];
     const int64_t q = (int64_t)d.cells / r;
@@ -213,7 +214,7 @@ __global__ __launch_bounds__(256) void k_reduce(const QDesc *__restrict__ descs,
         }
     }
     int slot = 0;
-    const int64_t base = qi;
+    const int64_t base = d.qid;
     if (want_ll) wave_reduce(ll);
     if (want_bd) wave_reduce(bd);
     if (want_mi) wave_reduce(mi);
@@ -251,12 +252,12 @@ __global__ __launch_bounds__(256) void k_reduce(const QDesc *__restrict__ descs,
 
 }  // namespace
 
-hipError_t launch_reduce(const fc_db *db, const QDesc *descs, int64_t nq, const int32_t *tables,
-                         uint32_t reducers, double ess, float *scores, float *err,
-                         hipStream_t s) {
-    if (nq <= 0) return hipSuccess;
-    int64_t blocks = (nq + 3) / 4;
-    hipLaunchKernelGGL(k_reduce, dim3((unsigned)blocks), dim3(256), 0, s, descs, nq, tables,
+hipError_t launch_reduce(const fc_db *db, const QDesc *descs, int64_t nd, int64_t nq,
+                         const int32_t *tables, uint32_t reducers, double ess, float *scores,
+                         float *err, hipStream_t s) {
+    if (nd <= 0) return hipSuccess;
+    int64_t blocks = (nd + 3) / 4;
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)blocks), dim3(256), 0, s, descs, nd, nq, tables,
                        db->d_arity, db->d_soff, db->d_marg, db->m, reducers, (float)ess, scores,
                        err);
     return hipGetLastError();

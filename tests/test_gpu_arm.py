@@ -79,3 +79,28 @@ def test_sparse_tables():
         np.testing.assert_array_equal(cnt, dense[nz])
         keys, cnt, nnz = db.count_sparse([0, 1, 2], cap=5)
         assert len(keys) == 5 and nnz > 5
+
+
+@pytest.mark.parametrize("score", ["mdl", "bdeu"])
+def test_parent_set_assignment_is_exact(score):
+    import itertools
+    from paper_1804_04640_amd import parents
+    w = synth.cfg2(m=4000, nq=1)
+    D, ar = w.D[:7].copy(), w.arity[:7].copy()       # 7 variables of the DAG sample
+    n = 7
+    with Database(D, ar) as db:
+        best, stats = parents.best_parents(db, max_pa=3, score=score)
+    for c in range(n):
+        others = [v for v in range(n) if v != c]
+        ref = {}
+        for k in range(0, 4):
+            for pa in itertools.combinations(others, k):
+                T = orc.count(D, ar, list(pa) + [c])
+                ref[pa] = orc.score(score, T, int(ar[c]), 1.0)
+        opt = min(ref.values()) if score == "mdl" else max(ref.values())
+        got_pa, got_s = best[c]
+        # the chosen set is optimal up to the float32 tolerance of the scores
+        assert abs(ref[tuple(sorted(got_pa))] - opt) <= 2e-6 * abs(opt) + 1e-9, (c, got_pa)
+        assert abs(got_s - ref[tuple(sorted(got_pa))]) <= 1e-6 * abs(opt) + 1e-9
+    if score == "mdl":
+        assert stats["scored"] + stats["pruned"] == n * (1 + 6 + 15 + 20)
