@@ -113,6 +113,20 @@ int fc_db_create(const uint8_t *data, int64_t m, int32_t n,
                  const uint8_t *arity, int32_t layout, uint32_t flags,
                  void *stream, fc_db **out);
 
+/*
+ * Append m_new instances to a database (the extension noted in Section 6:
+ * the bitmaps are updated, a column scan needs nothing else).  data, layout
+ * and FC_DB_DATA_ON_DEVICE are as in fc_db_create; the new states are
+ * validated before anything changes, so a rejected append leaves the handle
+ * as it was.  Columns, marginals, entropies and bit-vectors are updated in
+ * place (columns grow when the padded size changes).  Graphs captured before
+ * the append are invalidated: fc_graph_launch then fails with
+ * FC_ERR_INVALID.  Must not run concurrently with other calls on the handle;
+ * synchronises the device.
+ */
+int fc_db_append(fc_db *db, const uint8_t *data, int64_t m_new, int32_t layout,
+                 uint32_t flags, void *stream);
+
 /* Free every device and host resource of the handle (NULL is a no-op). */
 void fc_db_destroy(fc_db *db);
 

@@ -31,7 +31,7 @@ FC_RED_BDEU = 4
 FC_RED_MI = 8
 
 # every symbol the header declares
-EXPORTS = ("fc_db_create", "fc_db_destroy", "fc_db_info", "fc_db_marginals", "fc_table_cells",
+EXPORTS = ("fc_db_create", "fc_db_append", "fc_db_destroy", "fc_db_info", "fc_db_marginals", "fc_table_cells",
            "fc_count", "fc_count_assignment", "fc_count_assignments", "fc_count_sparse", "fc_count_batch", "fc_count_reduce", "fc_pairs",
            "fc_batch_footprint", "fc_graph_create", "fc_graph_launch", "fc_graph_destroy",
            "fc_db_get_tuning", "fc_db_set_tuning", "fc_autotune",
@@ -101,6 +101,7 @@ def load():
         P, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
         sig = {
             "fc_db_create": (ctypes.c_int, [P, i64, i32, P, i32, u32, P, P]),
+            "fc_db_append": (ctypes.c_int, [P, P, i64, i32, u32, P]),
             "fc_db_destroy": (None, [P]),
             "fc_db_info": (ctypes.c_int, [P, P, P, P, P]),
             "fc_db_marginals": (ctypes.c_int, [P, P, P]),
@@ -146,6 +147,10 @@ def fc_db_create(data, m, n, arity, layout, flags, stream):
     h = ctypes.c_void_p()
     check(load().fc_db_create(data, m, n, arity, layout, flags, stream, ctypes.byref(h)))
     return h.value
+
+
+def fc_db_append(db, data, m_new, layout, flags, stream):
+    return check(load().fc_db_append(db, data, m_new, layout, flags, stream))
 
 
 def fc_db_destroy(db):

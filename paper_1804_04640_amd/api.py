@@ -83,6 +83,25 @@ class Database:
         self.arity = arity.copy()
         self.bitvectors = bitvectors
 
+    def append(self, D, layout: str = "col", stream=None) -> None:
+        """Append instances (uint8 [n][m_new] column-major, or [m_new][n] with
+        layout="row"); counts, marginals and bit-vectors cover them at once."""
+        lay = L.FC_COL_MAJOR if layout == "col" else L.FC_ROW_MAJOR
+        flags = 0
+        if isinstance(D, torch.Tensor):
+            Dt = D.contiguous()
+            if Dt.is_cuda:
+                flags |= L.FC_DB_DATA_ON_DEVICE
+            ptr, shape = (Dt.data_ptr() if Dt.numel() else 0), tuple(Dt.shape)
+        else:
+            Dt = np.ascontiguousarray(np.asarray(D, dtype=np.uint8))
+            ptr, shape = _np_ptr(Dt), Dt.shape
+        n, m_new = (shape[0], shape[1]) if lay == L.FC_COL_MAJOR else (shape[1], shape[0])
+        if n != self.n:
+            raise ValueError("appended data has %d variables, the database %d" % (n, self.n))
+        L.fc_db_append(self.handle, ptr, m_new, lay, flags, _stream(stream))
+        self.m += int(m_new)
+
     # ----------------------------------------------------------- lifecycle
     def close(self):
         if getattr(self, "_h", None):

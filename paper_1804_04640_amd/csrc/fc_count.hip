@@ -1553,6 +1553,7 @@ extern "C" int fc_autotune(fc_db *db, const int32_t *vars_flat, const int64_t *v
 // ------------------------------------------------------------------ graphs
 struct fc_graph {
     fc_db *db = nullptr;
+    uint64_t epoch = 0;  // database epoch at capture
     fc::Plan P;
     fc::Image I;
     void *dimg = nullptr;
@@ -1621,6 +1622,7 @@ extern "C" int fc_graph_create(fc_db *db, const int32_t *vars_flat, const int64_
         return FC_ERR_NOMEM;
     }
     g->db = db;
+    g->epoch = db->epoch;
     struct Guard {
         fc_graph *g;
         ~Guard() { if (g) fc_graph_destroy(g); }
@@ -1657,6 +1659,10 @@ extern "C" int fc_graph_launch(fc_graph *g, void *stream) {
     clear_error();
     if (!g || !g->exec) {
         set_error("fc_graph_launch: NULL graph");
+        return FC_ERR_INVALID;
+    }
+    if (g->epoch != g->db->epoch) {
+        set_error("fc_graph_launch: the database changed since the batch was captured");
         return FC_ERR_INVALID;
     }
     FC_HIP(hipSetDevice(g->db->device));

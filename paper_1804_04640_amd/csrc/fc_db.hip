@@ -6,6 +6,7 @@
 // words, one row of words per (variable, state).  Per-variable marginal
 // counts (the precomputed first partition level of Section 3.3) and
 // entropies (the Bitmap traversal order of Section 3.2) are computed once.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -165,12 +166,13 @@ __global__ void k_check_marg(const uint8_t *__restrict__ cols, int64_t m, int64_
 // instance p of variable v is in state s.  One wave per 64-row word; padding
 // rows (p >= m) contribute no bits.
 __global__ void k_bitvectors(const uint8_t *__restrict__ cols, int64_t m, int64_t m_pad,
-                             int64_t words, const uint8_t *__restrict__ arity,
+                             int64_t words, int64_t w_lo, int64_t w_hi,
+                             const uint8_t *__restrict__ arity,
                              const int32_t *__restrict__ soff, uint64_t *__restrict__ bits) {
     int32_t v = blockIdx.y;
     int lane = threadIdx.x & 63;
-    int64_t w = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-    if (w >= words) return;
+    int64_t w = w_lo + (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    if (w >= w_hi) return;
     int64_t p = w * 64 + lane;
     int s = (p < m) ? cols[(int64_t)v * m_pad + p] : 255;
     int r = arity[v];
@@ -341,7 +343,7 @@ extern "C" int fc_db_create(const uint8_t *data, int64_t m, int32_t n, const uin
         if ((rc = db_alloc((void **)&db->d_bits, bytes, db))) return rc;
         dim3 grid((unsigned)((db->words + 3) / 4), (unsigned)n);
         hipLaunchKernelGGL(k_bitvectors, grid, dim3(256), 0, s, db->d_cols, m, db->m_pad,
-                           db->words, db->d_arity, db->d_soff, db->d_bits);
+                           db->words, (int64_t)0, db->words, db->d_arity, db->d_soff, db->d_bits);
         FC_HIP(hipGetLastError());
         FC_HIP(hipStreamSynchronize(s));
     }
@@ -370,5 +372,138 @@ extern "C" int fc_db_marginals(const fc_db *db, int64_t *counts, float *entropy_
     }
     if (counts) std::memcpy(counts, db->marg.data(), sizeof(int64_t) * db->marg.size());
     if (entropy_bits) std::memcpy(entropy_bits, db->entropy.data(), sizeof(float) * db->n);
+    return FC_OK;
+}
+
+extern "C" int fc_db_append(fc_db *db, const uint8_t *data, int64_t m_new, int32_t layout,
+                            uint32_t flags, void *stream) {
+    clear_error();
+    if (!db || m_new < 0 || (m_new > 0 && !data)) {
+        set_error("fc_db_append: need a database, m_new >= 0 and data");
+        return FC_ERR_INVALID;
+    }
+    if (layout != FC_COL_MAJOR && layout != FC_ROW_MAJOR) {
+        set_error("fc_db_append: unknown layout %d", layout);
+        return FC_ERR_INVALID;
+    }
+    if (m_new == 0) return FC_OK;
+    const int64_t m_old = db->m, m = m_old + m_new;
+    if (m >= (int64_t(1) << 31)) {
+        set_error("fc_db_append: %lld instances do not fit int32 counts", (long long)m);
+        return FC_ERR_RANGE;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    FC_HIP(hipSetDevice(db->device));
+    const int32_t n = db->n, sum_r = db->state_off[n];
+    const bool on_dev = (flags & FC_DB_DATA_ON_DEVICE) != 0;
+    // 1. the new instances, column-major [n][m_new], validated and counted
+    DevBuf tmp, raw, bad, cnt;
+    FC_HIP(tmp.alloc((size_t)n * (size_t)m_new, s));
+    if (layout == FC_COL_MAJOR) {
+        FC_HIP(hipMemcpyAsync(tmp.p, data, (size_t)n * (size_t)m_new,
+                              on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    } else {
+        const uint8_t *src = data;
+        if (!on_dev) {
+            FC_HIP(raw.alloc((size_t)n * (size_t)m_new, s));
+            FC_HIP(hipMemcpyAsync(raw.p, data, (size_t)n * (size_t)m_new, hipMemcpyHostToDevice, s));
+            src = (const uint8_t *)raw.p;
+        }
+        dim3 grid((unsigned)((m_new + 63) / 64), (unsigned)((n + 63) / 64));
+        hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, s, src, m_new, n, (uint8_t *)tmp.p,
+                           m_new);
+        FC_HIP(hipGetLastError());
+    }
+    FC_HIP(bad.alloc(sizeof(int32_t), s));
+    FC_HIP(cnt.alloc(sizeof(int32_t) * (size_t)sum_r, s));
+    FC_HIP(fill_zero_i32((int32_t *)bad.p, 1, s));
+    FC_HIP(fill_zero_i32((int32_t *)cnt.p, sum_r, s));
+    {
+        int64_t slabs = std::min<int64_t>((m_new + 65535) / 65536, 64);
+        hipLaunchKernelGGL(k_check_marg, dim3((unsigned)slabs, (unsigned)n), dim3(256), 0, s,
+                           (const uint8_t *)tmp.p, m_new, m_new, db->d_arity, db->d_soff,
+                           (int32_t *)cnt.p, (int32_t *)bad.p);
+        FC_HIP(hipGetLastError());
+    }
+    int32_t nbad = 0;
+    std::vector<int32_t> add((size_t)sum_r);
+    FC_HIP(hipMemcpyAsync(&nbad, bad.p, sizeof nbad, hipMemcpyDeviceToHost, s));
+    FC_HIP(hipMemcpyAsync(add.data(), cnt.p, sizeof(int32_t) * (size_t)sum_r,
+                          hipMemcpyDeviceToHost, s));
+    FC_HIP(hipStreamSynchronize(s));
+    if (nbad) {
+        set_error("fc_db_append: %d new states are not below their variable's arity "
+                  "(nothing was appended)", nbad);
+        return FC_ERR_INVALID;
+    }
+    // 2. grow the padded columns and bit-vectors when the tile count changes
+    FC_HIP(hipDeviceSynchronize());  // no launch may still read the old buffers
+    const int64_t m_pad = ((m + kTileRows - 1) / kTileRows) * kTileRows;
+    const int64_t words = m_pad / 64;
+    if (m_pad != db->m_pad) {
+        uint8_t *cols = nullptr;
+        if (hipMalloc(&cols, (size_t)n * (size_t)m_pad) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("fc_db_append: device allocation failed");
+            return FC_ERR_NOMEM;
+        }
+        uint64_t *bits = nullptr;
+        if (db->d_bits &&
+            hipMalloc(&bits, sizeof(uint64_t) * (size_t)sum_r * (size_t)words) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFree(cols);
+            set_error("fc_db_append: device allocation failed");
+            return FC_ERR_NOMEM;
+        }
+        FC_HIP(fill_zero_i32((int32_t *)cols, (int64_t)n * m_pad / 4, s));
+        FC_HIP(hipMemcpy2DAsync(cols, (size_t)m_pad, db->d_cols, (size_t)db->m_pad,
+                                (size_t)db->m_pad, (size_t)n, hipMemcpyDeviceToDevice, s));
+        if (bits) {
+            FC_HIP(fill_zero_i32((int32_t *)bits, 2 * (int64_t)sum_r * words, s));
+            FC_HIP(hipMemcpy2DAsync(bits, sizeof(uint64_t) * (size_t)words, db->d_bits,
+                                    sizeof(uint64_t) * (size_t)db->words,
+                                    sizeof(uint64_t) * (size_t)db->words, (size_t)sum_r,
+                                    hipMemcpyDeviceToDevice, s));
+        }
+        FC_HIP(hipStreamSynchronize(s));
+        (void)hipFree(db->d_cols);
+        db->device_bytes += (int64_t)n * (m_pad - db->m_pad);
+        db->d_cols = cols;
+        if (bits) {
+            (void)hipFree(db->d_bits);
+            db->device_bytes += (int64_t)sizeof(uint64_t) * sum_r * (words - db->words);
+            db->d_bits = bits;
+        }
+        db->m_pad = m_pad;
+        db->words = words;
+    }
+    // 3. the new instances into the columns, then the bit-vector words they touch
+    FC_HIP(hipMemcpy2DAsync(db->d_cols + m_old, (size_t)db->m_pad, tmp.p, (size_t)m_new,
+                            (size_t)m_new, (size_t)n, hipMemcpyDeviceToDevice, s));
+    if (db->d_bits) {
+        const int64_t w_lo = m_old / 64, w_hi = (m + 63) / 64;
+        dim3 grid((unsigned)((w_hi - w_lo + 3) / 4), (unsigned)n);
+        hipLaunchKernelGGL(k_bitvectors, grid, dim3(256), 0, s, db->d_cols, m, db->m_pad,
+                           db->words, w_lo, w_hi, db->d_arity, db->d_soff, db->d_bits);
+        FC_HIP(hipGetLastError());
+    }
+    std::vector<int32_t> marg32((size_t)sum_r);
+    for (int32_t i = 0; i < sum_r; ++i) {
+        db->marg[(size_t)i] += add[(size_t)i];
+        marg32[(size_t)i] = (int32_t)db->marg[(size_t)i];
+    }
+    FC_HIP(hipMemcpyAsync(db->d_marg, marg32.data(), sizeof(int32_t) * (size_t)sum_r,
+                          hipMemcpyHostToDevice, s));
+    FC_HIP(hipStreamSynchronize(s));
+    db->m = m;
+    for (int32_t v = 0; v < n; ++v) {
+        double h = 0.0;
+        for (int st = 0; st < db->arity[v]; ++st) {
+            const double pr = (double)db->marg[db->state_off[v] + st] / (double)m;
+            if (pr > 0) h -= pr * std::log2(pr);
+        }
+        db->entropy[v] = (float)h;
+    }
+    db->epoch += 1;
     return FC_OK;
 }

@@ -71,6 +71,7 @@ struct fc_db {
     int32_t *d_soff = nullptr;       // [n+1]
     int32_t *d_marg = nullptr;       // [sum r]
     int64_t device_bytes = 0;
+    uint64_t epoch = 0;              // bumped by every append
     fc::Tuning tune;
 };
 

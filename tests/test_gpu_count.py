@@ -146,9 +146,9 @@ def test_marginals_and_assignment():
         cnt, ent = db.marginals()
         off = 0
         for v in range(w.n):
-            np.testing.assert_array_equal(cnt[off:off + w.arity[v]],
+            np.testing.assert_array_equal(cnt[off:off + int(w.arity[v])],
                                           np.bincount(w.D[v], minlength=w.arity[v]))
-            off += w.arity[v]
+            off += int(w.arity[v])
         rng = np.random.default_rng(0)
         for _ in range(20):
             k = int(rng.integers(1, 6))
@@ -203,3 +203,46 @@ def test_tuning_roundtrip_and_validation():
         t["bitmap_words"] = 3
         with pytest.raises(_lib.FastcountError):
             db.set_tuning(t)
+
+
+def test_incremental_appends():
+    w = synth.cfg3(m=30_011, nq=120)
+    parts = [(0, 4000), (4000, 4100), (4100, 9000), (9000, 30_011)]   # in-tile and tile-crossing
+    qs = (w.vars_flat, w.var_off)
+    with Database(np.ascontiguousarray(w.D[:, :4000]), w.arity) as db:
+        for lo, hi in parts[1:]:
+            piece = np.ascontiguousarray(w.D[:, lo:hi])
+            if hi - lo > 1000:
+                db.append(np.ascontiguousarray(piece.T), layout="row")
+            else:
+                db.append(piece)
+        assert db.info()[0] == w.m
+        for strategy in ("auto", "bitmap", "hist"):
+            tables, toff = db.count_batch(qs, strategy=strategy)
+            check_tables(w, tables, toff)
+        cnt, _ = db.marginals()
+        off = 0
+        for v in range(w.n):
+            ref = np.bincount(w.D[v], minlength=w.arity[v])
+            got = cnt[off:off + int(w.arity[v])]
+            assert np.array_equal(got, ref), (v, got.tolist(), ref.tolist())
+            off += int(w.arity[v])
+        assert db.count_assignment([0, 1], [1, 0]) == orc.count_assignment(w.D, w.arity, [0, 1], [1, 0])
+
+
+def test_rejected_append_changes_nothing_and_graphs_expire():
+    w = synth.cfg1(m=6000, nq=60)
+    with Database(w.D, w.arity) as db:
+        g = db.graph((w.vars_flat, w.var_off), ("mdl",))
+        bad = np.zeros((w.n, 10), np.uint8)
+        bad[0, 3] = w.arity[0]                                # state == arity
+        with pytest.raises(_lib.FastcountError):
+            db.append(bad)
+        assert db.info()[0] == w.m
+        tables, toff = db.count_batch((w.vars_flat, w.var_off))
+        check_tables(w, tables, toff)
+        g.replay()                                            # still valid
+        db.append(np.zeros((w.n, 5), np.uint8))
+        with pytest.raises(_lib.FastcountError):
+            g.replay()                                        # captured before the append
+        g.close()
