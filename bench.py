@@ -45,16 +45,16 @@ def src_hash() -> str:
 
 def workload(name: str):
     from paper_1804_04640_amd import synth
-    if name == "cfg2":
-        return synth.cfg2(), ("mdl",)
-    if name == "cfg1":
-        return synth.cfg1(), ("mdl",)
-    if name == "cfg3":
-        return synth.cfg3(), ("bdeu", "mi")
-    if name == "cfg5":
-        return synth.cfg5(), ("mdl",)
-    if name == "cfg4":
-        return synth.cfg4(), ()
+    if name == "bn-family":
+        return synth.bn_family(), ("mdl",)
+    if name == "plain-small":
+        return synth.plain_small(), ("mdl",)
+    if name == "batched-uneven":
+        return synth.batched_uneven(), ("bdeu", "mi")
+    if name == "serving":
+        return synth.serving(), ("mdl",)
+    if name == "all-pairs":
+        return synth.all_pairs(), ()
     raise SystemExit("unknown workload %s" % name)
 
 
@@ -103,7 +103,7 @@ def bench_serve(args):
                                               poisson_arrivals, run_load)
 
     t0 = time.time()
-    w = synth.cfg5(nbatches=256)
+    w = synth.serving(nbatches=256)
     print("# %s generated in %.1fs" % (w.desc, time.time() - t0), file=sys.stderr, flush=True)
     db = Database(w.D, w.arity)
     batches = []
@@ -168,7 +168,7 @@ def bench_parents(args):
     from paper_1804_04640_amd import _lib, parents, synth
     from paper_1804_04640_amd.api import Database
 
-    w = synth.cfg2(m=100_000, nq=1)
+    w = synth.bn_family(m=100_000, nq=1)
     db = Database(w.D, w.arity)
     rng = np.random.default_rng(0)
     sample = [np.concatenate([rng.choice(np.delete(np.arange(w.n), c), size=int(rng.integers(0, args.parents + 1)), replace=False), [c]]).astype(np.int32)
@@ -299,7 +299,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"])
+    ap.add_argument("--workload", default="bn-family", choices=["plain-small", "bn-family", "batched-uneven", "all-pairs", "serving"])
     ap.add_argument("--strategy", default="auto", choices=["auto", "hist", "bitmap", "partition"])
     ap.add_argument("--per-query", type=int, default=2000,
                     help="queries timed on the plain per-query path (0: skip)")
@@ -318,7 +318,7 @@ def main():
                     help="exact parent-set assignment with |Pa| <= MAX_PA on a 37-variable "
                          "DAG sample of m=100,000 (MDL)")
     ap.add_argument("--arm", action="store_true",
-                    help="with --workload cfg4: bottom-up association-rule mining")
+                    help="with --workload all-pairs: bottom-up association-rule mining")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter scale)")
     args = ap.parse_args()
@@ -348,9 +348,9 @@ def main():
           file=sys.stderr, flush=True)
     if args.parents:
         return bench_parents(args)
-    if args.workload == "cfg4" and args.arm:
+    if args.workload == "all-pairs" and args.arm:
         return bench_arm(args, w)
-    if args.workload == "cfg4":
+    if args.workload == "all-pairs":
         return bench_pairs(args, w)
     if args.serve:
         return bench_serve(args)

@@ -8,7 +8,7 @@ The paper's own data sets (Table 1; the association-rule data of Section 4.3)
 are not available; these generators stand in for them with the shapes the
 paper reports (n = 20..104 variables, arities 2 up to high values, m = 1K to
 10M instances, Section 4.1).  Every generator is seeded with numpy PCG64,
-seed = 180404640 + workload number.
+seed = 180404640 + the workload's stream number (see rng_for).
 
 Databases are column-major uint8 arrays ``D[n][m]`` with 0-based states.
 Query streams are flat: ``vars_flat`` (int32) with ``var_off`` (int64, nq+1)
@@ -57,8 +57,10 @@ class Workload:
         return [self.query(i) for i in range(self.nq)]
 
 
-def rng_for(cfg: int) -> np.random.Generator:
-    return np.random.Generator(np.random.PCG64(SEED_BASE + cfg))
+def rng_for(stream: int) -> np.random.Generator:
+    """Generator of seed SEED_BASE + stream (plain-small 1, bn-family 2,
+    batched-uneven 3, all-pairs 4, serving 5; other numbers for tests)."""
+    return np.random.Generator(np.random.PCG64(SEED_BASE + stream))
 
 
 def flatten(queries) -> tuple:
@@ -154,17 +156,17 @@ def _bernoulli_positions(rng, p, m) -> np.ndarray:
 
 
 # ---------------------------------------------------------------- workloads
-def cfg1(m=10_000, nq=1000) -> Workload:
+def plain_small(m=10_000, nq=1000) -> Workload:
     """n=8, arities U{2,3,4}, iid uniform states, queries of 1-4 variables."""
     rng = rng_for(1)
     arity = rng.integers(2, 5, size=8).astype(np.uint8)
     D = iid_uniform(rng, arity, m)
     flat, off = random_queries(rng, 8, nq, 1, 4)
-    return Workload("cfg1-plain-small", D, arity, flat, off, (),
+    return Workload("plain-small", D, arity, flat, off, (),
                     desc="n=8 r~U{2,3,4} m=%d iid uniform; %d queries k~U{1..4}" % (m, nq))
 
 
-def cfg2(m=1_000_000, nq=50_000) -> Workload:
+def bn_family(m=1_000_000, nq=50_000) -> Workload:
     """n=37, arities U{2,3,4}, random DAG (in-degree <= 4, Dirichlet(1)),
     family queries child + 0..4 parents, MDL."""
     rng = rng_for(2)
@@ -173,12 +175,12 @@ def cfg2(m=1_000_000, nq=50_000) -> Workload:
     order, parents = random_dag(rng, n, 4)
     D = forward_sample(rng, arity, order, parents, m, 1.0)
     flat, off = family_queries(rng, n, nq, 0, 4)
-    return Workload("cfg2-bn-family-mdl", D, arity, flat, off, ("mdl",),
+    return Workload("bn-family", D, arity, flat, off, ("mdl",),
                     desc="n=37 r~U{2,3,4} m=%d DAG(indeg<=4, Dir(1)); %d families |Pa|~U{0..4}"
                     % (m, nq))
 
 
-def cfg3(m=4_000_000, nq=200_000) -> Workload:
+def batched_uneven(m=4_000_000, nq=200_000) -> Workload:
     """n=100, arities min(8, 2+Geom(0.4)), random DAG (in-degree <= 3,
     Dirichlet(0.5)), queries of 1..6 variables, BDeu(ess=1) + MI."""
     rng = rng_for(3)
@@ -188,7 +190,7 @@ def cfg3(m=4_000_000, nq=200_000) -> Workload:
     order, parents = random_dag(rng, n, 3)
     D = forward_sample(rng, arity, order, parents, m, 0.5)
     flat, off = random_queries(rng, n, nq, 1, 6)
-    return Workload("cfg3-batched-uneven", D, arity, flat, off, ("bdeu", "mi"), ess=1.0,
+    return Workload("batched-uneven", D, arity, flat, off, ("bdeu", "mi"), ess=1.0,
                     desc="n=100 r=min(8,2+Geom(0.4)) m=%d DAG(indeg<=3, Dir(0.5)); %d queries k~U{1..6}"
                     % (m, nq))
 
@@ -206,7 +208,7 @@ def zipf_marginals(n, s=1.1, mean=0.01):
     return np.minimum(1.0, 0.5 * (lo + hi) * i ** -s)
 
 
-def cfg4(m=1 << 21, n=1024, groups=64) -> Workload:
+def all_pairs(m=1 << 21, n=1024, groups=64) -> Workload:
     """Binary transactions: Zipf(1.1) item frequencies at 1% mean density,
     items independent except `groups` planted disjoint groups of 3..5 items.
     Reading of "co-occur with p=0.6": a group fires in an instance with
@@ -233,7 +235,7 @@ def cfg4(m=1 << 21, n=1024, groups=64) -> Workload:
     arity = np.full(n, 2, dtype=np.uint8)
     flat = np.zeros(0, dtype=np.int32)
     off = np.zeros(1, dtype=np.int64)
-    return Workload("cfg4-all-pairs", D, arity, flat, off, ("suppconf",), minsup=0.001,
+    return Workload("all-pairs", D, arity, flat, off, ("suppconf",), minsup=0.001,
                     desc="n=%d binary items, m=%d, Zipf(1.1) at 1%% density, %d planted groups"
                     % (n, m, groups))
 
@@ -279,7 +281,7 @@ def hill_climb_batches(rng, n, nbatches, smin=10, smax=5000, max_pa=6):
     return batches
 
 
-def cfg5(m=1 << 22, nbatches=64) -> Workload:
+def serving(m=1 << 22, nbatches=64) -> Workload:
     """Serving: n=64, arities U{2..5}, random DAG (in-degree <= 4, Dirichlet(1))
     resident on the device; hill-climbing family batches of 10..5000 queries
     of 2..7 variables; MDL."""
@@ -295,9 +297,10 @@ def cfg5(m=1 << 22, nbatches=64) -> Workload:
         ids.append(np.arange(base, base + len(b), dtype=np.int64))
         base += len(b)
     flat, off = flatten(qs)
-    return Workload("cfg5-serving", D, arity, flat, off, ("mdl",), batches=ids,
+    return Workload("serving", D, arity, flat, off, ("mdl",), batches=ids,
                     desc="n=64 r~U{2..5} m=%d DAG(indeg<=4, Dir(1)); %d hill-climbing batches"
                     % (m, nbatches))
 
 
-WORKLOADS = {1: cfg1, 2: cfg2, 3: cfg3, 4: cfg4, 5: cfg5}
+WORKLOADS = {"plain-small": plain_small, "bn-family": bn_family,
+             "batched-uneven": batched_uneven, "all-pairs": all_pairs, "serving": serving}

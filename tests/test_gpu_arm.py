@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("bits", [True, False])
 def test_count_assignments_batch(bits):
-    w = synth.cfg3(m=70_001, nq=10)
+    w = synth.batched_uneven(m=70_001, nq=10)
     rng = np.random.default_rng(3)
     qs, st = [], []
     for _ in range(300):
@@ -44,7 +44,7 @@ def test_mining_matches_exhaustive_definition():
 
 
 def test_mining_on_planted_transactions():
-    w = synth.cfg4(m=1 << 16, n=64, groups=4)
+    w = synth.all_pairs(m=1 << 16, n=64, groups=4)
     with Database(w.D, w.arity) as db:
         freq, rules = arm.mine(db, minsup=0.002, minconf=0.3, max_size=6)
         # every reported support is the single-assignment count
@@ -85,7 +85,7 @@ def test_sparse_tables():
 def test_parent_set_assignment_is_exact(score):
     import itertools
     from paper_1804_04640_amd import parents
-    w = synth.cfg2(m=4000, nq=1)
+    w = synth.bn_family(m=4000, nq=1)
     D, ar = w.D[:7].copy(), w.arity[:7].copy()       # 7 variables of the DAG sample
     n = 7
     with Database(D, ar) as db:

@@ -30,17 +30,17 @@ def test_fig1_example():
 
 
 @pytest.mark.parametrize("strategy", ["auto", "hist", "bitmap", "partition"])
-def test_cfg1_full_batch(strategy):
-    w = synth.cfg1()
-    print("cfg1 strategy=%s nq=%d m=%d" % (strategy, w.nq, w.m), flush=True)
+def test_plain_small_full_batch(strategy):
+    w = synth.plain_small()
+    print("plain-small strategy=%s nq=%d m=%d" % (strategy, w.nq, w.m), flush=True)
     with Database(w.D, w.arity) as db:
         tables, toff = db.count_batch((w.vars_flat, w.var_off), strategy=strategy)
         torch.cuda.synchronize()
         check_tables(w, tables, toff)
 
 
-def test_cfg1_per_query_path():
-    w = synth.cfg1()
+def test_plain_small_per_query_path():
+    w = synth.plain_small()
     with Database(w.D, w.arity) as db:
         for i in range(0, w.nq, 7):
             q = w.query(i)
@@ -48,17 +48,17 @@ def test_cfg1_per_query_path():
 
 
 @pytest.mark.parametrize("strategy", ["auto", "hist", "bitmap", "partition"])
-def test_cfg2_small_strategies(strategy):
-    w = synth.cfg2(m=100_003, nq=400)        # ragged tail: m is not a tile multiple
-    print("cfg2-small strategy=%s" % strategy, flush=True)
+def test_bn_family_small_strategies(strategy):
+    w = synth.bn_family(m=100_003, nq=400)        # ragged tail: m is not a tile multiple
+    print("bn-family small strategy=%s" % strategy, flush=True)
     with Database(w.D, w.arity) as db:
         tables, toff = db.count_batch((w.vars_flat, w.var_off), strategy=strategy)
         torch.cuda.synchronize()
         check_tables(w, tables, toff)
 
 
-def test_cfg3_small_auto_and_host_output():
-    w = synth.cfg3(m=60_001, nq=300)
+def test_batched_uneven_small_and_host_output():
+    w = synth.batched_uneven(m=60_001, nq=300)
     with Database(w.D, w.arity) as db:
         tables, toff = db.count_batch((w.vars_flat, w.var_off))
         torch.cuda.synchronize()
@@ -83,7 +83,7 @@ def test_large_table_partition_path():
 
 
 def test_batch_equals_alone():
-    w = synth.cfg3(m=30_000, nq=200)
+    w = synth.batched_uneven(m=30_000, nq=200)
     with Database(w.D, w.arity) as db:
         tables, toff = db.count_batch((w.vars_flat, w.var_off))
         T = tables.cpu().numpy()
@@ -93,7 +93,7 @@ def test_batch_equals_alone():
 
 
 def test_repeat_runs_identical():
-    w = synth.cfg2(m=50_000, nq=300)
+    w = synth.bn_family(m=50_000, nq=300)
     with Database(w.D, w.arity) as db:
         a, _ = db.count_batch((w.vars_flat, w.var_off))
         b, _ = db.count_batch((w.vars_flat, w.var_off))
@@ -115,7 +115,7 @@ def test_edge_cases():
 
 
 def test_validation_errors_name_the_query():
-    w = synth.cfg1()
+    w = synth.plain_small()
     with Database(w.D, w.arity) as db:
         bad = [[0, 1], [2, 2], [3]]
         with pytest.raises(_lib.FastcountError) as e:
@@ -131,7 +131,7 @@ def test_validation_errors_name_the_query():
 
 
 def test_row_major_and_device_input():
-    w = synth.cfg1(m=5000, nq=50)
+    w = synth.plain_small(m=5000, nq=50)
     with Database(np.ascontiguousarray(w.D.T), w.arity, layout="row") as db:
         tables, toff = db.count_batch((w.vars_flat, w.var_off))
         check_tables(w, tables, toff)
@@ -141,7 +141,7 @@ def test_row_major_and_device_input():
 
 
 def test_marginals_and_assignment():
-    w = synth.cfg2(m=40_000, nq=10)
+    w = synth.bn_family(m=40_000, nq=10)
     with Database(w.D, w.arity) as db:
         cnt, ent = db.marginals()
         off = 0
@@ -162,7 +162,7 @@ def test_marginals_and_assignment():
 
 @pytest.mark.parametrize("persistent", [0, 100000])
 def test_persistent_and_solo_launches_agree(persistent):
-    w = synth.cfg3(m=50_001, nq=300)
+    w = synth.batched_uneven(m=50_001, nq=300)
     with Database(w.D, w.arity) as db:
         t = db.tuning()
         t["persistent_max_queries"] = persistent
@@ -174,7 +174,7 @@ def test_persistent_and_solo_launches_agree(persistent):
 
 def test_graph_replays_match_eager():
     # replays interleaved with eager work, every replay checked
-    w = synth.cfg2(m=60_000, nq=250)
+    w = synth.bn_family(m=60_000, nq=250)
     with Database(w.D, w.arity) as db:
         g = db.graph((w.vars_flat, w.var_off), ("mdl", "bdeu"), keep_tables=True)
         eager, _, tables, toff = db.count_reduce((w.vars_flat, w.var_off), ("mdl", "bdeu"),
@@ -193,7 +193,7 @@ def test_graph_replays_match_eager():
 
 
 def test_tuning_roundtrip_and_validation():
-    w = synth.cfg1()
+    w = synth.plain_small()
     with Database(w.D, w.arity) as db:
         t = db.tuning()
         t["chunk_rows"] = 32768
@@ -206,7 +206,7 @@ def test_tuning_roundtrip_and_validation():
 
 
 def test_incremental_appends():
-    w = synth.cfg3(m=30_011, nq=120)
+    w = synth.batched_uneven(m=30_011, nq=120)
     parts = [(0, 4000), (4000, 4100), (4100, 9000), (9000, 30_011)]   # in-tile and tile-crossing
     qs = (w.vars_flat, w.var_off)
     with Database(np.ascontiguousarray(w.D[:, :4000]), w.arity) as db:
@@ -231,7 +231,7 @@ def test_incremental_appends():
 
 
 def test_rejected_append_changes_nothing_and_graphs_expire():
-    w = synth.cfg1(m=6000, nq=60)
+    w = synth.plain_small(m=6000, nq=60)
     with Database(w.D, w.arity) as db:
         g = db.graph((w.vars_flat, w.var_off), ("mdl",))
         bad = np.zeros((w.n, 10), np.uint8)

@@ -58,20 +58,20 @@ def check_full(w, reducers, nsample):
 
 
 def test_bn_family_full():
-    check_full(synth.cfg2(), ("mdl",), 300)
+    check_full(synth.bn_family(), ("mdl",), 300)
 
 
 def test_batched_uneven_full():
-    check_full(synth.cfg3(), ("bdeu", "mi"), 150)
+    check_full(synth.batched_uneven(), ("bdeu", "mi"), 150)
 
 
 def test_serving_database_full():
-    w = synth.cfg5(nbatches=16)
+    w = synth.serving(nbatches=16)
     check_full(w, ("mdl",), 150)
 
 
 def test_all_pairs_full():
-    w = synth.cfg4()
+    w = synth.all_pairs()
     n, m = w.D.shape
     with Database(w.D, w.arity) as db:
         recs, G, total = db.pairs(w.minsup, gram=True)

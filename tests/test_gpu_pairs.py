@@ -49,8 +49,8 @@ def test_item_subset_and_cap():
         assert len(recs) == 3 and total > 3
 
 
-def test_cfg4_reduced():
-    w = synth.cfg4(m=1 << 17)
+def test_all_pairs_reduced():
+    w = synth.all_pairs(m=1 << 17)
     check(w.D, 0.001)
 
 

@@ -43,8 +43,8 @@ def test_fig1_scores():
             assert float(sc[name][0]) == pytest.approx(exp[name], rel=REL)
 
 
-def test_cfg2_small_mdl_ll():
-    w = synth.cfg2(m=100_003, nq=500)
+def test_bn_family_small_mdl_ll():
+    w = synth.bn_family(m=100_003, nq=500)
     with Database(w.D, w.arity) as db:
         sc, er, tables, toff = db.count_reduce((w.vars_flat, w.var_off), ("ll", "mdl"),
                                                keep_tables=True)
@@ -52,8 +52,8 @@ def test_cfg2_small_mdl_ll():
         check_scores(w, sc, er, ("ll", "mdl"))
 
 
-def test_cfg3_small_bdeu_mi():
-    w = synth.cfg3(m=80_021, nq=400)
+def test_batched_uneven_small_bdeu_mi():
+    w = synth.batched_uneven(m=80_021, nq=400)
     with Database(w.D, w.arity) as db:
         sc, er, _, _ = db.count_reduce((w.vars_flat, w.var_off), ("bdeu", "mi"), ess=1.0)
         torch.cuda.synchronize()
@@ -62,7 +62,7 @@ def test_cfg3_small_bdeu_mi():
 
 @pytest.mark.parametrize("ess", [0.5, 10.0])
 def test_bdeu_other_ess(ess):
-    w = synth.cfg2(m=30_000, nq=200)
+    w = synth.bn_family(m=30_000, nq=200)
     with Database(w.D, w.arity) as db:
         sc, er, _, _ = db.count_reduce((w.vars_flat, w.var_off), ("bdeu",), ess=ess)
         check_scores(w, sc, er, ("bdeu",), ess=ess)
@@ -89,7 +89,7 @@ def test_stress_tables_near_deterministic_and_independent():
 
 
 def test_scores_alone_equal_scores_in_batch():
-    w = synth.cfg3(m=40_000, nq=120)
+    w = synth.batched_uneven(m=40_000, nq=120)
     with Database(w.D, w.arity) as db:
         sc, _, _, _ = db.count_reduce((w.vars_flat, w.var_off), ("bdeu", "mi"))
         for i in range(0, w.nq, 11):

@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 @pytest.fixture(scope="module")
 def served():
-    w = synth.cfg5(m=200_003, nbatches=12)
+    w = synth.serving(m=200_003, nbatches=12)
     db = Database(w.D, w.arity)
     yield w, db
     db.close()

@@ -14,14 +14,14 @@ def digest(w):
 
 
 def test_generators_are_deterministic():
-    a, b = synth.cfg1(), synth.cfg1()
+    a, b = synth.plain_small(), synth.plain_small()
     assert digest(a) == digest(b)
-    c, d = synth.cfg3(m=20_000, nq=300), synth.cfg3(m=20_000, nq=300)
+    c, d = synth.batched_uneven(m=20_000, nq=300), synth.batched_uneven(m=20_000, nq=300)
     assert digest(c) == digest(d)
 
 
 def test_shapes_and_ranges():
-    w = synth.cfg1()
+    w = synth.plain_small()
     assert w.D.shape == (8, 10_000) and w.nq == 1000
     assert set(np.unique(w.arity)) <= {2, 3, 4}
     assert np.all(w.D < w.arity[:, None])
@@ -29,10 +29,10 @@ def test_shapes_and_ranges():
     assert ks.min() >= 1 and ks.max() <= 4
     for q in w.queries():
         assert len(set(q.tolist())) == len(q)
-    w3 = synth.cfg3(m=5000, nq=500)
+    w3 = synth.batched_uneven(m=5000, nq=500)
     assert w3.arity.min() >= 2 and w3.arity.max() <= 8
     assert np.all(w3.D < w3.arity[:, None])
-    w2 = synth.cfg2(m=3000, nq=200)
+    w2 = synth.bn_family(m=3000, nq=200)
     ks = np.diff(w2.var_off)
     assert ks.min() >= 1 and ks.max() <= 5
 
