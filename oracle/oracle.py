@@ -43,32 +43,36 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def _bind(lib):
+    """Declares the C signatures on a loaded oracle library."""
+    P = ctypes.c_void_p
+    i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    lib.orc_table_cells.argtypes = [P, i32, P, i32]
+    lib.orc_table_cells.restype = i64
+    lib.orc_count.argtypes = [P, i64, i32, P, P, i32, P, i64]
+    lib.orc_count.restype = ctypes.c_int
+    lib.orc_count_assignment.argtypes = [P, i64, i32, P, P, P, i32]
+    lib.orc_count_assignment.restype = i64
+    for name in ("orc_ll", "orc_mdl", "orc_mi"):
+        f = getattr(lib, name)
+        f.argtypes = [P, i64, i32]
+        f.restype = f64
+    lib.orc_bdeu.argtypes = [P, i64, i32, f64]
+    lib.orc_bdeu.restype = f64
+    lib.orc_count_sparse.argtypes = [P, i64, i32, P, P, i32, P, P]
+    lib.orc_count_sparse.restype = i64
+    lib.orc_gram.argtypes = [P, i64, i32, P]
+    lib.orc_gram.restype = ctypes.c_int
+    return lib
+
+
 def _load():
     global _lib
     with _lock:
         if _lib is None:
             if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
                 build(force=True)
-            lib = ctypes.CDLL(_LIB)
-            P = ctypes.c_void_p
-            i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
-            lib.orc_table_cells.argtypes = [P, i32, P, i32]
-            lib.orc_table_cells.restype = i64
-            lib.orc_count.argtypes = [P, i64, i32, P, P, i32, P, i64]
-            lib.orc_count.restype = ctypes.c_int
-            lib.orc_count_assignment.argtypes = [P, i64, i32, P, P, P, i32]
-            lib.orc_count_assignment.restype = i64
-            for name in ("orc_ll", "orc_mdl", "orc_mi"):
-                f = getattr(lib, name)
-                f.argtypes = [P, i64, i32]
-                f.restype = f64
-            lib.orc_bdeu.argtypes = [P, i64, i32, f64]
-            lib.orc_bdeu.restype = f64
-            lib.orc_count_sparse.argtypes = [P, i64, i32, P, P, i32, P, P]
-            lib.orc_count_sparse.restype = i64
-            lib.orc_gram.argtypes = [P, i64, i32, P]
-            lib.orc_gram.restype = ctypes.c_int
-            _lib = lib
+            _lib = _bind(ctypes.CDLL(_LIB))
     return _lib
 
 
