@@ -4,9 +4,9 @@
 // Section 2 definition):
 //  * HIST: every instance's states form one mixed-radix key (the digits of
 //    the MSD radix of Section 3.3, child least significant) and the key's
-//    cell is incremented in an LDS histogram.  Small tables keep up to 64
-//    copies of the histogram (one per lane slot, odd row stride) so lanes of
-//    a wave rarely hit the same address.
+//    cell is incremented in an LDS histogram.  Each cell owns up to 64
+//    consecutive words (one per lane slot, as many as the LDS allows), so
+//    lanes of a wave add into different banks whatever their keys.
 //  * BITMAP: the per-state bit-vectors of the query's variables are ANDed
 //    down the configuration tree of Alg. 1 and the leaves are popcounted; a
 //    subtree whose prefix is empty in every lane of the wave is pruned, as
@@ -27,8 +27,7 @@
 namespace fc {
 
 constexpr int kHistMaxCells = 40000;  // odd row stride * 4 B <= 160 KiB
-constexpr int kLaneCols = 64;         // cells * 64 lanes * 4 B = 16 KiB at most
-constexpr int32_t kPersistentLds = 64 * 65 * 4;  // groups up to this LDS share one launch
+constexpr int32_t kPersistentLds = 64 * 64 * 4;  // groups up to this LDS share one launch
 
 __device__ __forceinline__ void map_block(int64_t b, int32_t nd, int32_t chunks, int32_t &d,
                                           int32_t &c) {
@@ -157,27 +156,22 @@ __device__ __forceinline__ void hist16_body(const uint8_t *__restrict__ cols, in
             colp[t] = cols + (int64_t)v * m_pad;
         }
     }
-    // Two layouts.  Tables up to kLaneCols cells: cell x of lane l lives at
-    // word x*64 + l, so a lane always hits its own bank and no ds_add of a
-    // wave conflicts, whatever the keys.  Larger tables: `copies` histograms
-    // with an odd row stride, lanes spread over the copies.
-    const bool lanecols = cells <= kLaneCols;
-    const int32_t cs = cells | 1;
-    int32_t copies = lds_words / cs;
-    copies = copies >= 64 ? 64 : copies >= 32 ? 32 : copies >= 16 ? 16 : copies >= 8 ? 8
-           : copies >= 4 ? 4 : copies >= 2 ? 2 : 1;
-    const int32_t used = lanecols ? cells * 64 : copies * cs;
+    // Lane columns: each cell owns B consecutive words (B = 64, 32, ..., 1,
+    // as many as the LDS allows) and lane l adds into word x*B + l mod B, so
+    // with B = 64 (or 32: a wave's halves go to the banks separately) no two
+    // lanes of a ds_add share a bank whatever the keys, and smaller B only
+    // ever shares a bank between lanes l and l + B.
+    int32_t B = lds_words / cells;
+    B = B >= 64 ? 64 : B >= 32 ? 32 : B >= 16 ? 16 : B >= 8 ? 8 : B >= 4 ? 4 : B >= 2 ? 2 : 1;
+    const int32_t used = cells * B;
     for (int32_t i = threadIdx.x; i < used; i += kBlock) lds[i] = 0;
     __syncthreads();
-    if (lanecols) {
 #pragma unroll
-        for (int t = 0; t < K; ++t) sb[t] *= 64u;
-    }
+    for (int t = 0; t < K; ++t) sb[t] *= (uint32_t)B;
     const int64_t tiles = m_pad / kTileRows;
     const int64_t r0 = (int64_t)c * tiles / chunks * kTileRows;
     const int64_t r1 = (int64_t)(c + 1) * tiles / chunks * kTileRows;
-    const uint32_t slot = lanecols ? (threadIdx.x & 63u) : (threadIdx.x & (copies - 1)) * (uint32_t)cs;
-    const uint32_t init = (slot * 4u) * 0x00010001u;
+    const uint32_t init = ((threadIdx.x & (uint32_t)(B - 1)) * 4u) * 0x00010001u;
     char *base = reinterpret_cast<char *>(lds);
 
     for (int64_t row = r0 + (int64_t)threadIdx.x * 16; row < r1; row += kBlock * 16) {
@@ -204,12 +198,9 @@ __device__ __forceinline__ void hist16_body(const uint8_t *__restrict__ cols, in
     int32_t *out = tables + q.table_off;
     for (int32_t cell = threadIdx.x; cell < cells; cell += kBlock) {
         uint32_t sum = 0;
-        if (lanecols) {
-            const uint32_t lane = threadIdx.x & 63u;  // staggered: no two lanes share a bank
-            for (uint32_t j = 0; j < 64; ++j) sum += lds[cell * 64 + ((j + lane) & 63u)];
-        } else {
-            for (int32_t p = 0; p < copies; ++p) sum += lds[p * cs + cell];
-        }
+        const uint32_t lane = threadIdx.x & 63u;  // staggered reads: spread over banks
+        for (int32_t j = 0; j < B; ++j)
+            sum += lds[cell * B + (int32_t)((j + lane) & (uint32_t)(B - 1))];
         if (cell == 0 && has_pad) sum -= (uint32_t)pad_rows;  // padding rows are key 0
         if (sum) atomicAdd(&out[cell], (int32_t)sum);
     }
@@ -543,8 +534,8 @@ struct Plan {
 // LDS size classes; every class but the last keeps its byte addresses below
 // 2^16 (the packed 16-bit key path).
 static const int32_t kClassCap[] = {16, 64, 256, 1024, 4096, 16383, kHistMaxCells};
-static const int32_t kClassLds[] = {64 * 17 * 4,  64 * 65 * 4,   16 * 257 * 4, 4 * 1025 * 4,
-                                    4097 * 4,     16383 * 4,     kHistMaxCells * 4 + 4};
+static const int32_t kClassLds[] = {16 * 64 * 4, 64 * 64 * 4, 256 * 32 * 4, 1024 * 8 * 4,
+                                    4096 * 2 * 4, 16383 * 4,  kHistMaxCells * 4 + 4};
 constexpr int kHist16Classes = 6;
 
 static int hist_class(int64_t cells) {
