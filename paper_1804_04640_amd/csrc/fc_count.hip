@@ -47,6 +47,18 @@ __device__ __forceinline__ void map_block(int64_t b, int32_t nd, int32_t chunks,
     }
 }
 
+// A state column as a buffer resource: the loads of all K columns share one
+// 32-bit vector offset (m_pad <= 2^31) and differ only in scalar registers,
+// and a load past the column's end returns zeros instead of faulting.
+typedef __amdgpu_buffer_rsrc_t Col;
+__device__ __forceinline__ Col make_col(const uint8_t *p, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(p), (short)0, (int)bytes,
+                                             0x00020000 /* 32-bit data format */);
+}
+__device__ __forceinline__ uint4 load16(Col c, uint32_t off) {
+    return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(c, off, 0, 0));
+}
+
 __device__ __forceinline__ uint32_t byte_of(const uint4 &v, int i) {
     uint32_t w = (i < 4) ? v.x : (i < 8) ? v.y : (i < 12) ? v.z : v.w;
     return (w >> ((i & 3) * 8)) & 0xFFu;
@@ -64,7 +76,7 @@ __device__ __forceinline__ void hist_body(const uint8_t *__restrict__ cols, int6
     const uint32_t win = (uint32_t)q.win_cells;
 
     uint32_t stride[K];
-    const uint8_t *colp[K];
+    Col colp[K];
     {
         uint32_t s = 1;
 #pragma unroll
@@ -72,7 +84,7 @@ __device__ __forceinline__ void hist_body(const uint8_t *__restrict__ cols, int6
             int32_t v = q.var[t];
             stride[t] = s;
             s *= arity[v];
-            colp[t] = cols + (int64_t)v * m_pad;
+            colp[t] = make_col(cols + (int64_t)v * m_pad, m_pad);
         }
     }
     const int32_t cs = (int32_t)(win | 1u);
@@ -87,10 +99,10 @@ __device__ __forceinline__ void hist_body(const uint8_t *__restrict__ cols, int6
     const int64_t r1 = (int64_t)(c + 1) * tiles / chunks * kTileRows;
     uint32_t *h = lds + (threadIdx.x & (copies - 1)) * cs;
 
-    for (int64_t row = r0 + (int64_t)threadIdx.x * 16; row < r1; row += kBlock * 16) {
+    for (uint32_t row = (uint32_t)r0 + threadIdx.x * 16u; row < (uint32_t)r1; row += kBlock * 16u) {
         uint4 v[K];
 #pragma unroll
-        for (int t = 0; t < K; ++t) v[t] = *reinterpret_cast<const uint4 *>(colp[t] + row);
+        for (int t = 0; t < K; ++t) v[t] = load16(colp[t], row);
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             uint32_t key = 0;
@@ -120,10 +132,53 @@ __global__ __launch_bounds__(kBlock) void k_hist(const uint8_t *__restrict__ col
                                                  const QDesc *__restrict__ descs, int32_t nd,
                                                  int32_t chunks, int32_t lds_words,
                                                  int32_t pad_rows, int32_t *__restrict__ tables) {
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     int32_t di, c;
     map_block(blockIdx.x, nd, chunks, di, c);
     hist_body<K, SMALL>(cols, m_pad, arity, descs[di], c, chunks, lds_words, pad_rows, tables, lds);
+}
+
+// Lane-column histograms: every cell owns B consecutive LDS words (B a power
+// of two).  Zeroing and the flush use all threads and 16-byte accesses when
+// B >= 4: B/4 consecutive threads read one cell's words, combine their sums
+// with lane shuffles, and the first adds the cell's count to the table.
+__device__ __forceinline__ void zero_cols(uint32_t *lds, int32_t words) {
+    if ((words & 3) == 0) {
+        uint4 *l4 = reinterpret_cast<uint4 *>(lds);
+        for (int32_t i = threadIdx.x; i < words / 4; i += kBlock) l4[i] = make_uint4(0u, 0u, 0u, 0u);
+    } else {
+        for (int32_t i = threadIdx.x; i < words; i += kBlock) lds[i] = 0;
+    }
+}
+
+__device__ __forceinline__ void flush_cols(const uint32_t *lds, int32_t cells, int32_t B,
+                                           bool has_pad, int32_t pad_rows, int32_t *out) {
+    if (B >= 4) {
+        const int32_t per = B / 4;  // threads per cell: 1, 2, 4, 8 or 16
+        const int32_t total = cells * per;
+        const uint4 *l4 = reinterpret_cast<const uint4 *>(lds);
+        for (int32_t b0 = 0; b0 < total; b0 += kBlock) {  // uniform trip count
+            const int32_t i = b0 + (int32_t)threadIdx.x;
+            uint32_t sum = 0;
+            if (i < total) {
+                const uint4 v = l4[i];
+                sum = (v.x + v.y) + (v.z + v.w);
+            }
+            for (int32_t off = per / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+            if (i < total && (i & (per - 1)) == 0) {
+                const int32_t cell = i / per;
+                if (cell == 0 && has_pad) sum -= (uint32_t)pad_rows;  // padding rows are key 0
+                if (sum) atomicAdd(&out[cell], (int32_t)sum);
+            }
+        }
+    } else {
+        for (int32_t cell = threadIdx.x; cell < cells; cell += kBlock) {
+            uint32_t sum = 0;
+            for (int32_t j = 0; j < B; ++j) sum += lds[cell * B + j];
+            if (cell == 0 && has_pad) sum -= (uint32_t)pad_rows;
+            if (sum) atomicAdd(&out[cell], (int32_t)sum);
+        }
+    }
 }
 
 // LDS histogram for tables whose copies fit 64 KiB (no key window): the key
@@ -145,7 +200,7 @@ __device__ __forceinline__ void hist16_body(const uint8_t *__restrict__ cols, in
                                             uint32_t *lds) {
     const int32_t cells = q.cells;
     uint32_t sb[K];
-    const uint8_t *colp[K];
+    Col colp[K];
     {
         uint32_t s = 1;
 #pragma unroll
@@ -153,7 +208,7 @@ __device__ __forceinline__ void hist16_body(const uint8_t *__restrict__ cols, in
             const int32_t v = q.var[t];
             sb[t] = (s * 4u) * 0x00010001u;  // byte stride in both halves
             s *= arity[v];
-            colp[t] = cols + (int64_t)v * m_pad;
+            colp[t] = make_col(cols + (int64_t)v * m_pad, m_pad);
         }
     }
     // Lane columns: each cell owns B consecutive words (B = 64, 32, ..., 1,
@@ -163,8 +218,7 @@ __device__ __forceinline__ void hist16_body(const uint8_t *__restrict__ cols, in
     // ever shares a bank between lanes l and l + B.
     int32_t B = lds_words / cells;
     B = B >= 64 ? 64 : B >= 32 ? 32 : B >= 16 ? 16 : B >= 8 ? 8 : B >= 4 ? 4 : B >= 2 ? 2 : 1;
-    const int32_t used = cells * B;
-    for (int32_t i = threadIdx.x; i < used; i += kBlock) lds[i] = 0;
+    zero_cols(lds, cells * B);
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < K; ++t) sb[t] *= (uint32_t)B;
@@ -174,10 +228,10 @@ __device__ __forceinline__ void hist16_body(const uint8_t *__restrict__ cols, in
     const uint32_t init = ((threadIdx.x & (uint32_t)(B - 1)) * 4u) * 0x00010001u;
     char *base = reinterpret_cast<char *>(lds);
 
-    for (int64_t row = r0 + (int64_t)threadIdx.x * 16; row < r1; row += kBlock * 16) {
+    for (uint32_t row = (uint32_t)r0 + threadIdx.x * 16u; row < (uint32_t)r1; row += kBlock * 16u) {
         uint4 v[K];
 #pragma unroll
-        for (int t = 0; t < K; ++t) v[t] = *reinterpret_cast<const uint4 *>(colp[t] + row);
+        for (int t = 0; t < K; ++t) v[t] = load16(colp[t], row);
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
             uint32_t alo = init, ahi = init;  // instances (0,2) and (1,3) of this dword
@@ -194,16 +248,81 @@ __device__ __forceinline__ void hist16_body(const uint8_t *__restrict__ cols, in
         }
     }
     __syncthreads();
-    const bool has_pad = (r1 == m_pad) && (r0 < r1);
-    int32_t *out = tables + q.table_off;
-    for (int32_t cell = threadIdx.x; cell < cells; cell += kBlock) {
-        uint32_t sum = 0;
-        const uint32_t lane = threadIdx.x & 63u;  // staggered reads: spread over banks
-        for (int32_t j = 0; j < B; ++j)
-            sum += lds[cell * B + (int32_t)((j + lane) & (uint32_t)(B - 1))];
-        if (cell == 0 && has_pad) sum -= (uint32_t)pad_rows;  // padding rows are key 0
-        if (sum) atomicAdd(&out[cell], (int32_t)sum);
+    flush_cols(lds, cells, B, (r1 == m_pad) && (r0 < r1), pad_rows, tables + q.table_off);
+}
+
+// LDS histogram for tables of at most 256 cells.  A column word holds four
+// instances as bytes, so its low 16-bit half is b1*256 + b0; summed over the
+// query's columns with packed multiply-adds, (b1*256 + b0) * stride gives
+// key1*256 + key0 exactly, because every key is below 256 and no carry
+// crosses the byte boundary (key3, key2 likewise in the high half).  One
+// packed multiply-add per column thus forms four keys, and one byte permute
+// per instance turns a key into the LDS byte address key*256 + lane*4: every
+// cell owns 64 words, one per lane, so no ds_add of a wave has a bank
+// conflict whatever the keys.
+template <int K>
+__device__ __forceinline__ void hist8_body(const uint8_t *__restrict__ cols, int64_t m_pad,
+                                           const uint8_t *__restrict__ arity, const QDesc &q,
+                                           int32_t c, int32_t chunks, int32_t pad_rows,
+                                           int32_t *__restrict__ tables, uint32_t *lds) {
+    const int32_t cells = q.cells;
+    uint32_t sb[K];
+    Col colp[K];
+    {
+        uint32_t s = 1;
+#pragma unroll
+        for (int t = K - 1; t >= 0; --t) {
+            const int32_t v = q.var[t];
+            sb[t] = s * 0x00010001u;  // the stride in both halves
+            s *= arity[v];
+            colp[t] = make_col(cols + (int64_t)v * m_pad, m_pad);
+        }
     }
+    zero_cols(lds, cells * 64);
+    __syncthreads();
+    const int64_t tiles = m_pad / kTileRows;
+    const int64_t r0 = (int64_t)c * tiles / chunks * kTileRows;
+    const int64_t r1 = (int64_t)(c + 1) * tiles / chunks * kTileRows;
+    const uint32_t slot = (threadIdx.x & 63u) * 4u;
+    char *base = reinterpret_cast<char *>(lds);
+
+    for (uint32_t row = (uint32_t)r0 + threadIdx.x * 16u; row < (uint32_t)r1; row += kBlock * 16u) {
+        uint4 v[K];
+#pragma unroll
+        for (int t = 0; t < K; ++t) v[t] = load16(colp[t], row);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            uint32_t key = 0;  // bytes: keys of instances 0..3 of this word
+#pragma unroll
+            for (int t = 0; t < K; ++t) {
+                const uint32_t w = d == 0 ? v[t].x : d == 1 ? v[t].y : d == 2 ? v[t].z : v[t].w;
+                key = pk_mad_u16(w, sb[t], key);
+            }
+            // byte 0 of the address from `slot`, byte 1 from key byte i
+            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(key, slot, 0x0c0c0400u)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(key, slot, 0x0c0c0500u)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(key, slot, 0x0c0c0600u)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(key, slot, 0x0c0c0700u)), 1u);
+        }
+    }
+    __syncthreads();
+    flush_cols(lds, cells, 64, (r1 == m_pad) && (r0 < r1), pad_rows, tables + q.table_off);
+}
+
+// CAP: the launch group's largest table.  The histogram is a static LDS
+// array so its address is a compile-time constant and no add is spent per
+// instance on the LDS base.
+template <int K, int CAP>
+__global__ __launch_bounds__(kBlock) void k_hist8(const uint8_t *__restrict__ cols,
+                                                  int64_t m_pad,
+                                                  const uint8_t *__restrict__ arity,
+                                                  const QDesc *__restrict__ descs, int32_t nd,
+                                                  int32_t chunks, int32_t pad_rows,
+                                                  int32_t *__restrict__ tables) {
+    __shared__ __attribute__((aligned(16))) uint32_t lds[CAP * 64];
+    int32_t di, c;
+    map_block(blockIdx.x, nd, chunks, di, c);
+    hist8_body<K>(cols, m_pad, arity, descs[di], c, chunks, pad_rows, tables, lds);
 }
 
 template <int K>
@@ -214,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void k_hist16(const uint8_t *__restrict__ c
                                                    int32_t chunks, int32_t lds_words,
                                                    int32_t pad_rows,
                                                    int32_t *__restrict__ tables) {
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     int32_t di, c;
     map_block(blockIdx.x, nd, chunks, di, c);
     hist16_body<K>(cols, m_pad, arity, descs[di], c, chunks, lds_words, pad_rows, tables, lds);
@@ -313,7 +432,7 @@ struct PGroup {
     int32_t chunks;
     int32_t kind;     // PK_* << 4 | K
 };
-enum { PK_HIST16 = 1, PK_HIST_S = 2, PK_HIST_B = 3, PK_BITMAP = 4 };
+enum { PK_HIST16 = 1, PK_HIST_S = 2, PK_HIST_B = 3, PK_BITMAP = 4, PK_HIST8 = 5 };
 
 template <int K, int W>
 __device__ __forceinline__ void persistent_case(int type, const uint8_t *cols, int64_t m_pad,
@@ -323,6 +442,9 @@ __device__ __forceinline__ void persistent_case(int type, const uint8_t *cols, i
                                                 int32_t lds_words, int32_t pad, int32_t *tables,
                                                 uint32_t *lds) {
     switch (type) {
+        case PK_HIST8:
+            hist8_body<K>(cols, m_pad, arity, q, c, chunks, pad, tables, lds);
+            break;
         case PK_HIST16:
             hist16_body<K>(cols, m_pad, arity, q, c, chunks, lds_words, pad, tables, lds);
             break;
@@ -345,7 +467,7 @@ __global__ __launch_bounds__(kBlock) void k_count_persistent(
     const QDesc *__restrict__ descs, const PGroup *__restrict__ groups, int32_t ngroups,
     int64_t total_v, uint32_t *__restrict__ heads, int32_t lds_words, int32_t pad_rows,
     int32_t *__restrict__ tables) {
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     __shared__ int64_t s_v;
     const uint32_t xcc = __builtin_amdgcn_s_getreg((3 << 11) | 20) & 7u;  // HW_REG_XCC_ID
     for (;;) {
@@ -514,7 +636,7 @@ struct Launch {
     int strat;
     int K;
     bool small;
-    bool packed16;    // k_hist16: whole table, 16-bit byte-address keys
+    int32_t hk;       // histogram kernel: HK_HIST8, HK_HIST16 or HK_GENERIC
     int64_t first;    // first descriptor
     int32_t count;    // descriptors
     int32_t chunks;
@@ -533,10 +655,14 @@ struct Plan {
 
 // LDS size classes; every class but the last keeps its byte addresses below
 // 2^16 (the packed 16-bit key path).
+// Classes up to 64 cells use the byte-key kernel (64 words per cell; at
+// 256 cells its 64 KiB of LDS would halve the resident workgroups).
 static const int32_t kClassCap[] = {16, 64, 256, 1024, 4096, 16383, kHistMaxCells};
 static const int32_t kClassLds[] = {16 * 64 * 4, 64 * 64 * 4, 256 * 32 * 4, 1024 * 8 * 4,
                                     4096 * 2 * 4, 16383 * 4,  kHistMaxCells * 4 + 4};
+constexpr int kHist8Classes = 2;
 constexpr int kHist16Classes = 6;
+enum { HK_GENERIC = 0, HK_HIST16 = 1, HK_HIST8 = 2 };
 
 static int hist_class(int64_t cells) {
     for (int i = 0; i < 7; ++i)
@@ -886,13 +1012,18 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
                         bytes += r.bytes[(size_t)b];
                     }
                     L.chunks = pick_chunks(db, L.count, maxc, st);
-                    L.packed16 = st == S_HIST && cls < kHist16Classes;
+                    L.hk = st != S_HIST            ? HK_GENERIC
+                           : cls < kHist8Classes  ? HK_HIST8
+                           : cls < kHist16Classes ? HK_HIST16
+                                                  : HK_GENERIC;
                     L.lds_bytes = st == S_BITMAP ? (int32_t)(maxc * kBlock * 4) : kClassLds[cls];
                     L.alg_bytes = bytes;
                     if (st == S_BITMAP)
                         snprintf(L.name, sizeof L.name, "k_bitmap<%d,%d>", K,
                                  db->tune.bitmap_words >= 4 ? 4 : db->tune.bitmap_words == 2 ? 2 : 1);
-                    else if (L.packed16)
+                    else if (L.hk == HK_HIST8)
+                        snprintf(L.name, sizeof L.name, "k_hist8<%d>", K);
+                    else if (L.hk == HK_HIST16)
                         snprintf(L.name, sizeof L.name, "k_hist16<%d>", K);
                     else
                         snprintf(L.name, sizeof L.name, "k_hist<%d,%d>", K, sm);
@@ -907,7 +1038,13 @@ static hipError_t launch_hist_k(const fc_db *db, const Launch &L, const QDesc *d
                                 int32_t *tables, hipStream_t s) {
     const int64_t blocks = (int64_t)L.count * L.chunks;
     const int32_t pad = (int32_t)(db->m_pad - db->m);
-    if (L.packed16)
+    if (L.hk == HK_HIST8 && L.lds_bytes <= 16 * 64 * 4)
+        hipLaunchKernelGGL((k_hist8<K, 16>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                           db->d_cols, db->m_pad, db->d_arity, d, L.count, L.chunks, pad, tables);
+    else if (L.hk == HK_HIST8)
+        hipLaunchKernelGGL((k_hist8<K, 64>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                           db->d_cols, db->m_pad, db->d_arity, d, L.count, L.chunks, pad, tables);
+    else if (L.hk == HK_HIST16)
         hipLaunchKernelGGL((k_hist16<K>), dim3((unsigned)blocks), dim3(kBlock), L.lds_bytes, s,
                            db->d_cols, db->m_pad, db->d_arity, d, L.count, L.chunks,
                            L.lds_bytes / 4, pad, tables);
@@ -1043,7 +1180,8 @@ static void make_image(const fc_db *db, const Plan &P, uint32_t reducers, Image 
             g.nd = L.count;
             g.chunks = L.chunks;
             const int type = L.strat == S_BITMAP ? PK_BITMAP
-                           : L.packed16 ? PK_HIST16 : L.small ? PK_HIST_S : PK_HIST_B;
+                           : L.hk == HK_HIST8 ? PK_HIST8 : L.hk == HK_HIST16 ? PK_HIST16
+                           : L.small ? PK_HIST_S : PK_HIST_B;
             g.kind = (type << 4) | L.K;
             I.vtotal += g.nv;
             I.groups.push_back(g);
