@@ -5,15 +5,24 @@
 // Gram matrix A^T A of the m x n one-hot {0,1} instance-by-item matrix, a
 // dense contraction over the instances.  It runs on int8 MFMA with exact
 // int32 accumulation (counts < 2^31): the item bit-vectors of state 1 are
-// expanded to one byte per instance on chip, never materialised in HBM.
-//  * tiles of 128 x 128 items, upper block triangle only (the matrix is
-//    symmetric); split-K over the instances, partial tiles summed with int32
-//    atomics;
-//  * per K step each workgroup expands 4 words (256 instances) of its 2 x 128
-//    items into LDS panels, 4 waves each run a 4 x 4 grid of
-//    16x16x64 i8 MFMAs on their 64 x 64 quarter of the tile;
-//  * the (tile, split) order is XCD aware: one XCD works through one row
-//    range of every tile pair, so a split's bit-vectors stay in its L2.
+// expanded to one byte per instance in registers, never materialised.
+//  * a workgroup of 4 waves owns a 128 x 256 block of items (the blocks
+//    that reach the upper triangle; the matrix is symmetric) over one range
+//    of instances (split K); each wave holds a 128 x 64 part as an 8 x 4 grid
+//    of 16x16x64 i8 MFMA accumulators; partial blocks are summed into the
+//    output with int32 atomics;
+//  * the instances are taken 512 at a time (8 words of every item): a lane
+//    of K group g loads words 2g and 2g+1 of each of its items with one
+//    16-byte load (the 4 groups of an item read 64 contiguous bytes), and
+//    MFMA step h of the 8 feeds it the 16 bits h % 4 of word 2g + h / 4.
+//    Every instance is used exactly once, and A and B fragments come from
+//    the same function over the same instance groups, so their K order
+//    agrees whatever the hardware's order is;
+//  * a lane expands its 16 bits of an item to 16 bytes, the operand layout
+//    of the MFMA.  The 128 row items are shared by the 4 waves: each
+//    expands 2 of the 8 row fragments into an LDS panel (double buffered,
+//    one barrier per step); the 64 column items of a wave stay in registers;
+//  * the words of the next 512 instances load during the current ones.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -26,129 +35,166 @@ namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-constexpr int kGT = 128;                 // items per tile side
-constexpr int kGW = 2;                   // 64-instance words per K step
-constexpr int kPanel = kGW * 4 * kGT * 16;  // bytes: [word][group][item][16]
-
-__device__ __forceinline__ void map_pair(int64_t b, int32_t npairs, int32_t splits, int32_t &p,
-                                         int32_t &sp) {
-    if (splits % kXcds == 0) {
-        int32_t x = (int32_t)(b % kXcds);
-        int64_t t = b / kXcds;
-        p = (int32_t)(t % npairs);
-        sp = (int32_t)(t / npairs) * kXcds + x;
-    } else {
-        p = (int32_t)(b / splits);
-        sp = (int32_t)(b % splits);
-    }
-}
+constexpr int kGT = 128;  // row items per block
+constexpr int kGC = 256;  // column items per block (64 per wave)
+constexpr int kGR = kGT / 16;  // row fragments
+constexpr int kGK = 4;         // column fragments per wave
+constexpr int kGS = 8;         // words per load step
 
 // 16 instance bits -> 16 bytes of 0/1 (instance order = byte order).
-__device__ __forceinline__ uint4 expand16(uint32_t b) {
-    uint4 r;
-    r.x = ((b & 0xFu) * 0x00204081u) & 0x01010101u;
-    r.y = (((b >> 4) & 0xFu) * 0x00204081u) & 0x01010101u;
-    r.z = (((b >> 8) & 0xFu) * 0x00204081u) & 0x01010101u;
-    r.w = (((b >> 12) & 0xFu) * 0x00204081u) & 0x01010101u;
+__device__ __forceinline__ v4i expand16(uint32_t b) {
+    v4i r;
+    r[0] = (int)(((b & 0xFu) * 0x00204081u) & 0x01010101u);
+    r[1] = (int)((((b >> 4) & 0xFu) * 0x00204081u) & 0x01010101u);
+    r[2] = (int)((((b >> 8) & 0xFu) * 0x00204081u) & 0x01010101u);
+    r[3] = (int)((((b >> 12) & 0xFu) * 0x00204081u) & 0x01010101u);
     return r;
 }
 
-__global__ __launch_bounds__(256) void k_gram(const uint64_t *__restrict__ bits, int64_t words,
-                                              const int32_t *__restrict__ rowidx, int32_t ntiles,
-                                              int32_t npairs, int32_t splits,
-                                              int32_t *__restrict__ C, int32_t ldc) {
-    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-    int32_t p, sp;
-    map_pair(blockIdx.x, npairs, splits, p, sp);
-    int32_t I = 0, J = 0;
-    {  // pair index -> (I, J) with I <= J
-        int32_t rem = p;
-        while (rem >= ntiles - I) {
-            rem -= ntiles - I;
-            ++I;
-        }
-        J = I + rem;
-    }
-    const bool diag = I == J;
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int item = t >> 1, half = t & 1;
-    const int32_t ra = rowidx[I * kGT + item];
-    const int32_t rb = rowidx[J * kGT + item];
-    const uint64_t *pa = bits + (int64_t)(ra < 0 ? 0 : ra) * words;
-    const uint64_t *pb = bits + (int64_t)(rb < 0 ? 0 : rb) * words;
+// The 16 bits of MFMA step h in a lane's two words (x, y: low/high halves
+// of word 2g; z, w: of word 2g + 1).
+template <int H>
+__device__ __forceinline__ uint32_t bits_of(const uint4 &v) {
+    const uint32_t d = H < 2 ? v.x : H < 4 ? v.y : H < 6 ? v.z : v.w;
+    return (H & 1) ? d >> 16 : d & 0xFFFFu;
+}
 
+// A lane's 2 row items (its share of the panel) and 4 column items.
+struct Words {
+    uint4 a[2], b[kGK];
+};
+
+__device__ __forceinline__ Words load_words(const uint64_t *const (&pa)[2],
+                                            const uint64_t *const (&pb)[kGK], int64_t w) {
+    Words x;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) x.a[i] = *reinterpret_cast<const uint4 *>(pa[i] + w);
+#pragma unroll
+    for (int j = 0; j < kGK; ++j) x.b[j] = *reinterpret_cast<const uint4 *>(pb[j] + w);
+    return x;
+}
+
+// Expansion of one step's operands: this wave's 2 row fragments into the
+// panel, its 4 column fragments into registers.
+template <int H>
+__device__ __forceinline__ void expand_step(const Words &x, const uint4 (&ma)[2],
+                                            const uint4 (&mb)[kGK], v4i (*panel)[64], int wave,
+                                            int lane, v4i (&b)[kGK]) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+        panel[2 * wave + i][lane] = expand16(bits_of<H>(x.a[i]) & bits_of<H>(ma[i]));
+#pragma unroll
+    for (int j = 0; j < kGK; ++j) b[j] = expand16(bits_of<H>(x.b[j]) & bits_of<H>(mb[j]));
+}
+
+// One step: the 8 x 4 MFMAs of the current operands (row fragments from
+// `cur_panel`, column fragments `b`) with the next step's expansions
+// (operands of step HN of the words `xn`) interleaved between the MFMA rows,
+// so a wave's VALU work overlaps its own matrix-core work; then the barrier
+// that publishes the next panel.
+template <int HN>
+__device__ __forceinline__ void gram_step(const Words &xn, const uint4 (&ma)[2],
+                                          const uint4 (&mb)[kGK], v4i (*cur_panel)[64],
+                                          v4i (*next_panel)[64], int wave, int lane,
+                                          bool active, const v4i (&b)[kGK], v4i (&nb)[kGK],
+                                          v4i (&acc)[kGR][kGK]) {
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < kGR; ++i) {
+            const v4i a = cur_panel[i][lane];
+#pragma unroll
+            for (int j = 0; j < kGK; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b[j], acc[i][j], 0, 0, 0);
+            if (i < 2)
+                next_panel[2 * wave + i][lane] =
+                    expand16(bits_of<HN>(xn.a[i]) & bits_of<HN>(ma[i]));
+            else if (i < 2 + kGK)
+                nb[i - 2] = expand16(bits_of<HN>(xn.b[i - 2]) & bits_of<HN>(mb[i - 2]));
+        }
+    } else {
+        expand_step<HN>(xn, ma, mb, next_panel, wave, lane, nb);
+    }
+    __syncthreads();  // the next panel is complete; the current one is free
+}
+
+__global__ __launch_bounds__(256, 2) void k_gram(const uint64_t *__restrict__ bits, int64_t words,
+                                                 const int32_t *__restrict__ rowidx, int32_t nrb,
+                                                 int32_t ncb, int32_t npairs, int32_t splits,
+                                                 int32_t *__restrict__ C, int32_t ldc) {
+    __shared__ v4i panel[2][kGR][64];  // row fragments of two steps, lane-major
+    const int32_t p = (int32_t)(blockIdx.x % (uint32_t)npairs);
+    const int32_t sp = (int32_t)(blockIdx.x / (uint32_t)npairs);
+    // pair index -> (I, J): row block I meets the upper triangle from column
+    // block I / 2 on
+    int32_t I = 0, rem = p;
+    while (rem >= ncb - I / 2) {
+        rem -= ncb - I / 2;
+        ++I;
+    }
+    const int32_t J = I / 2 + rem;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane >> 4, col = lane & 15;
+    const int32_t col0 = J * kGC + wave * 64;  // this wave's first column item
+    // a wave whose columns all lie left of the block's first row adds nothing
+    const bool active = col0 + 63 >= I * kGT;
+    // this lane's words 2g, 2g + 1 of every 8; padding items read row 0, masked
+    const uint64_t *pa[2], *pb[kGK];
+    uint4 ma[2], mb[kGK];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int32_t r = rowidx[I * kGT + (2 * wave + i) * 16 + col];
+        pa[i] = bits + (int64_t)(r < 0 ? 0 : r) * words + 2 * grp;
+        const uint32_t m = r < 0 ? 0u : 0xFFFFFFFFu;
+        ma[i] = make_uint4(m, m, m, m);
+    }
+#pragma unroll
+    for (int j = 0; j < kGK; ++j) {
+        const int32_t r = rowidx[col0 + j * 16 + col];
+        pb[j] = bits + (int64_t)(r < 0 ? 0 : r) * words + 2 * grp;
+        const uint32_t m = r < 0 ? 0u : 0xFFFFFFFFu;
+        mb[j] = make_uint4(m, m, m, m);
+    }
     const int64_t tiles = words / (kTileRows / 64);
     const int64_t w0 = (int64_t)sp * tiles / splits * (kTileRows / 64);
     const int64_t w1 = (int64_t)(sp + 1) * tiles / splits * (kTileRows / 64);
 
-    v4i acc[4][4];
+    v4i acc[kGR][kGK];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < kGR; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = v4i{0, 0, 0, 0};
-
-    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
-    const int grp = lane >> 4, col = lane & 15;
-    // Double-buffered panels (A and B of buffer `cur` at lds + cur * 2 * kPanel)
-    // and register prefetch of the next step's words: one barrier per step.
-    uint64_t xa[kGW], xb[kGW];
-#pragma unroll
-    for (int g = 0; g < kGW; ++g) {
-        xa[g] = (ra >= 0 && w0 < w1) ? pa[w0 + g] : 0ull;
-        xb[g] = (rb >= 0 && w0 < w1 && !diag) ? pb[w0 + g] : 0ull;
+        for (int j = 0; j < kGK; ++j) acc[i][j] = v4i{0, 0, 0, 0};
+    if (w0 < w1) {
+        // (w1 - w0) is a multiple of 64 words; past the range the loads
+        // repeat the last step's words (expanded, never multiplied)
+        const int64_t last = w1 - kGS;
+        Words cur = load_words(pa, pb, w0);
+        v4i b[kGK], nb[kGK];
+        expand_step<0>(cur, ma, mb, panel[0], wave, lane, b);
+        __syncthreads();
+        for (int64_t w = w0; w < w1; w += kGS) {
+            const Words nxt = load_words(pa, pb, w + kGS < last ? w + kGS : last);
+            gram_step<1>(cur, ma, mb, panel[0], panel[1], wave, lane, active, b, nb, acc);
+            gram_step<2>(cur, ma, mb, panel[1], panel[0], wave, lane, active, nb, b, acc);
+            gram_step<3>(cur, ma, mb, panel[0], panel[1], wave, lane, active, b, nb, acc);
+            gram_step<4>(cur, ma, mb, panel[1], panel[0], wave, lane, active, nb, b, acc);
+            gram_step<5>(cur, ma, mb, panel[0], panel[1], wave, lane, active, b, nb, acc);
+            gram_step<6>(cur, ma, mb, panel[1], panel[0], wave, lane, active, nb, b, acc);
+            gram_step<7>(cur, ma, mb, panel[0], panel[1], wave, lane, active, b, nb, acc);
+            gram_step<0>(nxt, ma, mb, panel[1], panel[0], wave, lane, active, nb, b, acc);
+            cur = nxt;
+        }
     }
-    int cur = 0;
-    for (int64_t w = w0; w < w1; w += kGW) {  // (w1 - w0) is a multiple of 64 words
-        uint8_t *PA = lds + cur * 2 * kPanel;
-        uint8_t *PB = diag ? PA : PA + kPanel;
-#pragma unroll
-        for (int g = 0; g < kGW; ++g) {
-            const uint32_t va = (uint32_t)(xa[g] >> (32 * half));
-            const uint32_t vb = (uint32_t)(xb[g] >> (32 * half));
-#pragma unroll
-            for (int gg = 0; gg < 2; ++gg) {
-                const int group = 2 * half + gg;
-                const int off = ((g * 4 + group) * kGT + item) * 16;
-                *reinterpret_cast<uint4 *>(PA + off) = expand16((va >> (16 * gg)) & 0xFFFFu);
-                if (!diag)
-                    *reinterpret_cast<uint4 *>(PB + off) = expand16((vb >> (16 * gg)) & 0xFFFFu);
-            }
-        }
-        if (w + kGW < w1) {  // next step's words, in flight during the MFMAs
-#pragma unroll
-            for (int g = 0; g < kGW; ++g) {
-                xa[g] = ra >= 0 ? pa[w + kGW + g] : 0ull;
-                xb[g] = (rb >= 0 && !diag) ? pb[w + kGW + g] : 0ull;
-            }
-        }
-        __syncthreads();  // panels of `cur` complete; the other buffer is free
-#pragma unroll
-        for (int g = 0; g < kGW; ++g) {
-            v4i a[4], b[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                a[i] = *reinterpret_cast<const v4i *>(PA + ((g * 4 + grp) * kGT + wr + i * 16 + col) * 16);
-                b[i] = *reinterpret_cast<const v4i *>(PB + ((g * 4 + grp) * kGT + wc + i * 16 + col) * 16);
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], b[j], acc[i][j], 0, 0, 0);
-        }
-        cur ^= 1;
-    }
+    if (!active) return;
     // D layout of a 16x16 MFMA tile: lane l, element e -> row 4*(l/16)+e, column l%16
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < kGR; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < kGK; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int32_t v = acc[i][j][e];
                 if (v) {
-                    const int64_t row = (int64_t)I * kGT + wr + i * 16 + 4 * grp + e;
-                    const int64_t cc = (int64_t)J * kGT + wc + j * 16 + col;
+                    const int64_t row = (int64_t)I * kGT + i * 16 + 4 * grp + e;
+                    const int64_t cc = (int64_t)col0 + j * 16 + col;
                     atomicAdd(&C[row * ldc + cc], v);
                 }
             }
@@ -233,8 +279,9 @@ extern "C" int fc_pairs(fc_db *db, const int32_t *items, int32_t ni, double mins
         set_error("fc_pairs: items is NULL but ni=%d != n=%d", ni, db->n);
         return FC_ERR_INVALID;
     }
-    const int32_t ntiles = (ni + kGT - 1) / kGT;
-    const int32_t np = ntiles * kGT;
+    const int32_t ncb = (ni + kGC - 1) / kGC;  // column blocks
+    const int32_t np = ncb * kGC;              // items padded to whole blocks
+    const int32_t nrb = np / kGT;              // row blocks
     std::vector<int32_t> rowidx((size_t)np, -1);
     std::vector<uint8_t> seen((size_t)db->n, 0);
     for (int32_t i = 0; i < ni; ++i) {
@@ -262,13 +309,6 @@ extern "C" int fc_pairs(fc_db *db, const int32_t *items, int32_t ni, double mins
     if (db->m == 0) nmin = 1;  // no instance: no pair has support
     hipStream_t s = (hipStream_t)stream;
     FC_HIP(hipSetDevice(db->device));
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute((const void *)k_gram, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  4 * kPanel);
-        (void)hipGetLastError();
-        attr = true;
-    }
     DevBuf dC, dRow, dCnt, dOff, dRec, dG;
     const int64_t ldc = np;
     FC_HIP(dC.alloc(sizeof(int32_t) * (size_t)np * (size_t)np, s));
@@ -277,18 +317,19 @@ extern "C" int fc_pairs(fc_db *db, const int32_t *items, int32_t ni, double mins
                           hipMemcpyHostToDevice, s));
     int32_t *C = (int32_t *)dC.p;
     FC_HIP(fill_zero_i32(C, (int64_t)np * np, s));
-    const int32_t npairs = ntiles * (ntiles + 1) / 2;
+    int32_t npairs = 0;  // (row block, column block) pairs reaching the upper triangle
+    for (int32_t I = 0; I < nrb; ++I) npairs += ncb - I / 2;
     const int64_t tiles = db->words / (kTileRows / 64);
-    int64_t splits = (4 * (int64_t)db->cu_count + npairs - 1) / npairs;
-    splits = std::max<int64_t>(splits, 64);
+    // two workgroups per CU are resident: as many splits as fill them once,
+    // whole 64-word tiles each
+    int64_t splits = 2 * (int64_t)db->cu_count / npairs;
     splits = std::min<int64_t>(splits, tiles);
-    if (splits >= kXcds) splits -= splits % kXcds;
     if (splits < 1) splits = 1;
     if (db->m > 0) {
         const double ops = 2.0 * (double)db->m * (double)ni * (double)(ni + 1) / 2.0;
         ProfScope ps("k_gram", s, 0.0, ops);
-        hipLaunchKernelGGL(k_gram, dim3((unsigned)(npairs * splits)), dim3(256), 4 * kPanel, s,
-                           db->d_bits, db->words, (const int32_t *)dRow.p, ntiles, npairs,
+        hipLaunchKernelGGL(k_gram, dim3((unsigned)(npairs * splits)), dim3(256), 0, s,
+                           db->d_bits, db->words, (const int32_t *)dRow.p, nrb, ncb, npairs,
                            (int32_t)splits, C, (int32_t)ldc);
         FC_HIP(hipGetLastError());
         ps.end(s);
