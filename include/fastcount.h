@@ -288,6 +288,9 @@ typedef struct fc_tuning {
      * the Bitmap strategy when its table has at most 2^(b+2) cells and this
      * entry is non-zero (b = 0..5: up to 4, 8, 16, 32, 64, 128 cells).      */
     uint8_t bitmap_cells[FC_MAX_VARS][6];
+    int32_t packed_columns;    /* 1: histogram kernels read the 4-bit packed
+                                  columns when the database has them, 0: the
+                                  byte columns                            */
 } fc_tuning;
 
 int fc_db_get_tuning(const fc_db *db, fc_tuning *t);

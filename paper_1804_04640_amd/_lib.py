@@ -51,13 +51,15 @@ class fc_reduce_params(ctypes.Structure):
 class fc_tuning(ctypes.Structure):
     _fields_ = [("chunk_rows", ctypes.c_int64), ("bitmap_chunk_rows", ctypes.c_int64),
                 ("bitmap_words", ctypes.c_int32), ("persistent_max_queries", ctypes.c_int32),
-                ("bitmap_cells", (ctypes.c_uint8 * 6) * FC_MAX_VARS)]
+                ("bitmap_cells", (ctypes.c_uint8 * 6) * FC_MAX_VARS),
+                ("packed_columns", ctypes.c_int32)]
 
     def to_dict(self):
         return {"chunk_rows": int(self.chunk_rows), "bitmap_chunk_rows": int(self.bitmap_chunk_rows),
                 "bitmap_words": int(self.bitmap_words),
                 "persistent_max_queries": int(self.persistent_max_queries),
-                "bitmap_cells": [[int(x) for x in row] for row in self.bitmap_cells]}
+                "bitmap_cells": [[int(x) for x in row] for row in self.bitmap_cells],
+                "packed_columns": int(self.packed_columns)}
 
     @classmethod
     def from_dict(cls, d):
@@ -69,6 +71,7 @@ class fc_tuning(ctypes.Structure):
         for k, row in enumerate(d["bitmap_cells"]):
             for b, x in enumerate(row):
                 t.bitmap_cells[k][b] = int(x)
+        t.packed_columns = int(d.get("packed_columns", 1))
         return t
 
 

@@ -339,6 +339,159 @@ __global__ __launch_bounds__(kBlock) void k_hist16(const uint8_t *__restrict__ c
     hist16_body<K>(cols, m_pad, arity, descs[di], c, chunks, lds_words, pad_rows, tables, lds);
 }
 
+// The same two histograms over the 4-bit packed columns (all arities at most
+// 16): half the bytes per instance.  A packed word holds 8 instances, two
+// per byte (low nibble first); each thread reads 32 instances per column.
+//
+// Byte keys (tables of at most 64 cells): the even and the odd nibbles of a
+// word, masked into bytes, give two chains of packed multiply-adds, four
+// keys each.
+template <int K>
+__device__ __forceinline__ void hist8n_body(const uint8_t *__restrict__ nib, int64_t m_pad,
+                                            const uint8_t *__restrict__ arity, const QDesc &q,
+                                            int32_t c, int32_t chunks, int32_t pad_rows,
+                                            int32_t *__restrict__ tables, uint32_t *lds) {
+    const int32_t cells = q.cells;
+    uint32_t sb[K];
+    Col colp[K];
+    {
+        uint32_t s = 1;
+#pragma unroll
+        for (int t = K - 1; t >= 0; --t) {
+            const int32_t v = q.var[t];
+            sb[t] = s * 0x00010001u;
+            s *= arity[v];
+            colp[t] = make_col(nib + (int64_t)v * (m_pad / 2), m_pad / 2);
+        }
+    }
+    zero_cols(lds, cells * 64);
+    __syncthreads();
+    const int64_t tiles = m_pad / kTileRows;
+    const int64_t r0 = (int64_t)c * tiles / chunks * kTileRows;
+    const int64_t r1 = (int64_t)(c + 1) * tiles / chunks * kTileRows;
+    const uint32_t slot = (threadIdx.x & 63u) * 4u;
+    char *base = reinterpret_cast<char *>(lds);
+
+    for (uint32_t row = (uint32_t)r0 + threadIdx.x * 32u; row < (uint32_t)r1; row += kBlock * 32u) {
+        uint4 v[K];
+#pragma unroll
+        for (int t = 0; t < K; ++t) v[t] = load16(colp[t], row >> 1);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            uint32_t ke = 0, ko = 0;  // bytes: keys of the even / odd instances
+#pragma unroll
+            for (int t = 0; t < K; ++t) {
+                const uint32_t w = d == 0 ? v[t].x : d == 1 ? v[t].y : d == 2 ? v[t].z : v[t].w;
+                ke = pk_mad_u16(w & 0x0F0F0F0Fu, sb[t], ke);
+                ko = pk_mad_u16((w >> 4) & 0x0F0F0F0Fu, sb[t], ko);
+            }
+            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(ke, slot, 0x0c0c0400u)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(ke, slot, 0x0c0c0500u)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(ke, slot, 0x0c0c0600u)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(ke, slot, 0x0c0c0700u)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(ko, slot, 0x0c0c0400u)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(ko, slot, 0x0c0c0500u)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(ko, slot, 0x0c0c0600u)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(ko, slot, 0x0c0c0700u)), 1u);
+        }
+    }
+    __syncthreads();
+    flush_cols(lds, cells, 64, (r1 == m_pad) && (r0 < r1), pad_rows, tables + q.table_off);
+}
+
+template <int K, int CAP>
+__global__ __launch_bounds__(kBlock) void k_hist8n(const uint8_t *__restrict__ nib,
+                                                   int64_t m_pad,
+                                                   const uint8_t *__restrict__ arity,
+                                                   const QDesc *__restrict__ descs, int32_t nd,
+                                                   int32_t chunks, int32_t pad_rows,
+                                                   int32_t *__restrict__ tables) {
+    __shared__ __attribute__((aligned(16))) uint32_t lds[CAP * 64];
+    int32_t di, c;
+    map_block(blockIdx.x, nd, chunks, di, c);
+    hist8n_body<K>(nib, m_pad, arity, descs[di], c, chunks, pad_rows, tables, lds);
+}
+
+// Address keys (lane columns of B >= 4 words per cell): the key of two
+// instances (nibbles i and i + 4 of a word) forms in the 16-bit halves of a
+// register.  Nibble positions 1 and 3 of a half are masked in place, worth
+// 16 times their state, and use strides pre-divided by 16, which is exact
+// because a cell is 4 B >= 16 bytes wide; positions 2 and 3 come from the
+// word shifted by 8.
+template <int K>
+__device__ __forceinline__ void hist16n_body(const uint8_t *__restrict__ nib, int64_t m_pad,
+                                             const uint8_t *__restrict__ arity, const QDesc &q,
+                                             int32_t c, int32_t chunks, int32_t lds_words,
+                                             int32_t pad_rows, int32_t *__restrict__ tables,
+                                             uint32_t *lds) {
+    const int32_t cells = q.cells;
+    int32_t B = lds_words / cells;
+    B = B >= 64 ? 64 : B >= 32 ? 32 : B >= 16 ? 16 : B >= 8 ? 8 : 4;  // >= 4 by the class
+    uint32_t sa[K], sq[K];
+    Col colp[K];
+    {
+        uint32_t s = 1;
+#pragma unroll
+        for (int t = K - 1; t >= 0; --t) {
+            const int32_t v = q.var[t];
+            sa[t] = (s * 4u * (uint32_t)B) * 0x00010001u;  // byte stride of a state
+            sq[t] = (s * (uint32_t)B / 4u) * 0x00010001u;  // the same for 16 x state
+            s *= arity[v];
+            colp[t] = make_col(nib + (int64_t)v * (m_pad / 2), m_pad / 2);
+        }
+    }
+    zero_cols(lds, cells * B);
+    __syncthreads();
+    const int64_t tiles = m_pad / kTileRows;
+    const int64_t r0 = (int64_t)c * tiles / chunks * kTileRows;
+    const int64_t r1 = (int64_t)(c + 1) * tiles / chunks * kTileRows;
+    const uint32_t init = ((threadIdx.x & (uint32_t)(B - 1)) * 4u) * 0x00010001u;
+    char *base = reinterpret_cast<char *>(lds);
+
+    for (uint32_t row = (uint32_t)r0 + threadIdx.x * 32u; row < (uint32_t)r1; row += kBlock * 32u) {
+        uint4 v[K];
+#pragma unroll
+        for (int t = 0; t < K; ++t) v[t] = load16(colp[t], row >> 1);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            uint32_t a0 = init, a1 = init, a2 = init, a3 = init;  // instances (0,4) .. (3,7)
+#pragma unroll
+            for (int t = 0; t < K; ++t) {
+                const uint32_t w = d == 0 ? v[t].x : d == 1 ? v[t].y : d == 2 ? v[t].z : v[t].w;
+                const uint32_t w8 = w >> 8;
+                a0 = pk_mad_u16(w & 0x000F000Fu, sa[t], a0);
+                a1 = pk_mad_u16(w & 0x00F000F0u, sq[t], a1);
+                a2 = pk_mad_u16(w8 & 0x000F000Fu, sa[t], a2);
+                a3 = pk_mad_u16(w8 & 0x00F000F0u, sq[t], a3);
+            }
+            atomicAdd(reinterpret_cast<uint32_t *>(base + (a0 & 0xFFFFu)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + (a1 & 0xFFFFu)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + (a2 & 0xFFFFu)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + (a3 & 0xFFFFu)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + (a0 >> 16)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + (a1 >> 16)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + (a2 >> 16)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + (a3 >> 16)), 1u);
+        }
+    }
+    __syncthreads();
+    flush_cols(lds, cells, B, (r1 == m_pad) && (r0 < r1), pad_rows, tables + q.table_off);
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_hist16n(const uint8_t *__restrict__ nib,
+                                                    int64_t m_pad,
+                                                    const uint8_t *__restrict__ arity,
+                                                    const QDesc *__restrict__ descs, int32_t nd,
+                                                    int32_t chunks, int32_t lds_words,
+                                                    int32_t pad_rows,
+                                                    int32_t *__restrict__ tables) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    int32_t di, c;
+    map_block(blockIdx.x, nd, chunks, di, c);
+    hist16n_body<K>(nib, m_pad, arity, descs[di], c, chunks, lds_words, pad_rows, tables, lds);
+}
+
 // Bitmap count (Alg. 1) of one descriptor over one chunk of 64-row words.
 template <int L, int K, int W>
 struct Walk {
@@ -662,7 +815,8 @@ static const int32_t kClassLds[] = {16 * 64 * 4, 64 * 64 * 4, 256 * 32 * 4, 1024
                                     4096 * 2 * 4, 16383 * 4,  kHistMaxCells * 4 + 4};
 constexpr int kHist8Classes = 2;
 constexpr int kHist16Classes = 6;
-enum { HK_GENERIC = 0, HK_HIST16 = 1, HK_HIST8 = 2 };
+constexpr int kHist16nClasses = 4;  // lane columns of at least 4 words per cell
+enum { HK_GENERIC = 0, HK_HIST16 = 1, HK_HIST8 = 2, HK_HIST16N = 3, HK_HIST8N = 4 };
 
 static int hist_class(int64_t cells) {
     for (int i = 0; i < 7; ++i)
@@ -1012,10 +1166,14 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
                         bytes += r.bytes[(size_t)b];
                     }
                     L.chunks = pick_chunks(db, L.count, maxc, st);
-                    L.hk = st != S_HIST            ? HK_GENERIC
-                           : cls < kHist8Classes  ? HK_HIST8
-                           : cls < kHist16Classes ? HK_HIST16
-                                                  : HK_GENERIC;
+                    const bool nib = db->d_nib && db->tune.packed_columns;
+                    L.hk = st != S_HIST                    ? HK_GENERIC
+                           : cls < kHist8Classes            ? (nib ? HK_HIST8N : HK_HIST8)
+                           : nib && cls < kHist16nClasses   ? HK_HIST16N
+                           : cls < kHist16Classes           ? HK_HIST16
+                                                            : HK_GENERIC;
+                    if (L.hk == HK_HIST8N || L.hk == HK_HIST16N)
+                        bytes *= 0.5;  // half a byte per state
                     L.lds_bytes = st == S_BITMAP ? (int32_t)(maxc * kBlock * 4) : kClassLds[cls];
                     L.alg_bytes = bytes;
                     if (st == S_BITMAP)
@@ -1023,6 +1181,10 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
                                  db->tune.bitmap_words >= 4 ? 4 : db->tune.bitmap_words == 2 ? 2 : 1);
                     else if (L.hk == HK_HIST8)
                         snprintf(L.name, sizeof L.name, "k_hist8<%d>", K);
+                    else if (L.hk == HK_HIST8N)
+                        snprintf(L.name, sizeof L.name, "k_hist8n<%d>", K);
+                    else if (L.hk == HK_HIST16N)
+                        snprintf(L.name, sizeof L.name, "k_hist16n<%d>", K);
                     else if (L.hk == HK_HIST16)
                         snprintf(L.name, sizeof L.name, "k_hist16<%d>", K);
                     else
@@ -1038,7 +1200,17 @@ static hipError_t launch_hist_k(const fc_db *db, const Launch &L, const QDesc *d
                                 int32_t *tables, hipStream_t s) {
     const int64_t blocks = (int64_t)L.count * L.chunks;
     const int32_t pad = (int32_t)(db->m_pad - db->m);
-    if (L.hk == HK_HIST8 && L.lds_bytes <= 16 * 64 * 4)
+    if (L.hk == HK_HIST8N && L.lds_bytes <= 16 * 64 * 4)
+        hipLaunchKernelGGL((k_hist8n<K, 16>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                           db->d_nib, db->m_pad, db->d_arity, d, L.count, L.chunks, pad, tables);
+    else if (L.hk == HK_HIST8N)
+        hipLaunchKernelGGL((k_hist8n<K, 64>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                           db->d_nib, db->m_pad, db->d_arity, d, L.count, L.chunks, pad, tables);
+    else if (L.hk == HK_HIST16N)
+        hipLaunchKernelGGL((k_hist16n<K>), dim3((unsigned)blocks), dim3(kBlock), L.lds_bytes, s,
+                           db->d_nib, db->m_pad, db->d_arity, d, L.count, L.chunks,
+                           L.lds_bytes / 4, pad, tables);
+    else if (L.hk == HK_HIST8 && L.lds_bytes <= 16 * 64 * 4)
         hipLaunchKernelGGL((k_hist8<K, 16>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
                            db->d_cols, db->m_pad, db->d_arity, d, L.count, L.chunks, pad, tables);
     else if (L.hk == HK_HIST8)
@@ -1111,6 +1283,8 @@ static void set_attrs_k() {
                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
     (void)hipFuncSetAttribute((const void *)k_hist16<K>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
+    (void)hipFuncSetAttribute((const void *)k_hist16n<K>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
     (void)hipFuncSetAttribute((const void *)k_bitmap<K, 1>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
     (void)hipFuncSetAttribute((const void *)k_bitmap<K, 2>,
@@ -1180,7 +1354,8 @@ static void make_image(const fc_db *db, const Plan &P, uint32_t reducers, Image 
             g.nd = L.count;
             g.chunks = L.chunks;
             const int type = L.strat == S_BITMAP ? PK_BITMAP
-                           : L.hk == HK_HIST8 ? PK_HIST8 : L.hk == HK_HIST16 ? PK_HIST16
+                           : (L.hk == HK_HIST8 || L.hk == HK_HIST8N) ? PK_HIST8
+                           : (L.hk == HK_HIST16 || L.hk == HK_HIST16N) ? PK_HIST16
                            : L.small ? PK_HIST_S : PK_HIST_B;
             g.kind = (type << 4) | L.K;
             I.vtotal += g.nv;
@@ -1499,6 +1674,7 @@ extern "C" int fc_db_get_tuning(const fc_db *db, fc_tuning *t) {
     t->bitmap_words = db->tune.bitmap_words;
     t->persistent_max_queries = db->tune.persistent_max_queries;
     std::memcpy(t->bitmap_cells, db->tune.bitmap_cells, sizeof t->bitmap_cells);
+    t->packed_columns = db->tune.packed_columns;
     return FC_OK;
 }
 
@@ -1509,9 +1685,10 @@ extern "C" int fc_db_set_tuning(fc_db *db, const fc_tuning *t) {
         return FC_ERR_INVALID;
     }
     if (t->chunk_rows < kTileRows || t->bitmap_chunk_rows < kTileRows ||
-        (t->bitmap_words != 1 && t->bitmap_words != 2 && t->bitmap_words != 4)) {
-        set_error("fc_db_set_tuning: chunk rows must be >= %lld and bitmap_words 1, 2 or 4",
-                  (long long)kTileRows);
+        (t->bitmap_words != 1 && t->bitmap_words != 2 && t->bitmap_words != 4) ||
+        (t->packed_columns != 0 && t->packed_columns != 1)) {
+        set_error("fc_db_set_tuning: chunk rows must be >= %lld, bitmap_words 1, 2 or 4, "
+                  "packed_columns 0 or 1", (long long)kTileRows);
         return FC_ERR_INVALID;
     }
     db->tune.chunk_rows = t->chunk_rows;
@@ -1519,6 +1696,7 @@ extern "C" int fc_db_set_tuning(fc_db *db, const fc_tuning *t) {
     db->tune.bitmap_words = t->bitmap_words;
     db->tune.persistent_max_queries = t->persistent_max_queries < 0 ? 0 : t->persistent_max_queries;
     std::memcpy(db->tune.bitmap_cells, t->bitmap_cells, sizeof t->bitmap_cells);
+    db->tune.packed_columns = t->packed_columns;
     return FC_OK;
 }
 
@@ -1612,7 +1790,16 @@ extern "C" int fc_autotune(fc_db *db, const int32_t *vars_flat, const int64_t *v
         }
         db->tune.persistent_max_queries = thr;
     }
-    // 1. Histogram chunk size with the current strategy choice.
+    // 1. Packed 4-bit columns against byte columns for the histograms (when
+    //    the database has them), then the histogram chunk size.
+    if (db->d_nib) {
+        const int cur = db->tune.packed_columns;
+        float ms_cur = 0.f, ms_alt = 0.f;
+        if ((rc = time_batch(db, flat, off, FC_STRAT_AUTO, tables, s, 5, ms_cur))) return rc;
+        db->tune.packed_columns = 1 - cur;
+        if ((rc = time_batch(db, flat, off, FC_STRAT_AUTO, tables, s, 5, ms_alt))) return rc;
+        db->tune.packed_columns = ms_alt < 0.97f * ms_cur ? 1 - cur : cur;
+    }
     if ((rc = sweep_chunks(0))) return rc;
     // 2. Bitmap against histogram per (k, size bucket), on the sample's own
     //    queries of that shape, repeated to at least 1024 queries so the

@@ -165,6 +165,33 @@ __global__ void k_check_marg(const uint8_t *__restrict__ cols, int64_t m, int64_
 // Per-state bit-vectors: bit (p mod 64) of word p/64 of row (v, s) is set when
 // instance p of variable v is in state s.  One wave per 64-row word; padding
 // rows (p >= m) contribute no bits.
+// 4-bit copy of the columns for databases whose arities are all at most 16:
+// byte b of a column holds instance 2b in its low and 2b + 1 in its high
+// nibble.  Each thread packs 8 instances (two input words -> one word) of
+// the word range [d_lo, d_hi) of every column.
+__global__ void k_pack_nib(const uint8_t *__restrict__ cols, int64_t m_pad, int32_t n,
+                           int64_t d_lo, int64_t d_hi, uint8_t *__restrict__ nib) {
+    const int64_t per = d_hi - d_lo;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < per * n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = (int32_t)(i / per);
+        const int64_t d = d_lo + i % per;
+        const uint2 x = *reinterpret_cast<const uint2 *>(cols + (int64_t)v * m_pad + 8 * d);
+        const uint32_t even = __builtin_amdgcn_perm(x.y, x.x, 0x06040200u);  // instances 0,2,4,6
+        const uint32_t odd = __builtin_amdgcn_perm(x.y, x.x, 0x07050301u);   // instances 1,3,5,7
+        reinterpret_cast<uint32_t *>(nib + (int64_t)v * (m_pad / 2))[d] = even | (odd << 4);
+    }
+}
+
+static hipError_t pack_nib(fc_db *db, int64_t d_lo, int64_t d_hi, hipStream_t s) {
+    if (!db->d_nib || d_hi <= d_lo) return hipSuccess;
+    const int64_t total = (d_hi - d_lo) * db->n;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_pack_nib, dim3((unsigned)blocks), dim3(256), 0, s, db->d_cols, db->m_pad,
+                       db->n, d_lo, d_hi, db->d_nib);
+    return hipGetLastError();
+}
+
 __global__ void k_bitvectors(const uint8_t *__restrict__ cols, int64_t m, int64_t m_pad,
                              int64_t words, int64_t w_lo, int64_t w_hi,
                              const uint8_t *__restrict__ arity,
@@ -196,6 +223,7 @@ extern "C" void fc_db_destroy(fc_db *db) {
     (void)hipSetDevice(db->device);
     (void)hipDeviceSynchronize();
     if (db->d_cols) (void)hipFree(db->d_cols);
+    if (db->d_nib) (void)hipFree(db->d_nib);
     if (db->d_bits) (void)hipFree(db->d_bits);
     if (db->d_arity) (void)hipFree(db->d_arity);
     if (db->d_soff) (void)hipFree(db->d_soff);
@@ -338,6 +366,13 @@ extern "C" int fc_db_create(const uint8_t *data, int64_t m, int32_t n, const uin
         }
         db->entropy[v] = (float)h;
     }
+    bool small_arity = true;
+    for (int32_t v = 0; v < n; ++v) small_arity = small_arity && arity[v] <= 16;
+    if (small_arity) {
+        if ((rc = db_alloc((void **)&db->d_nib, (size_t)n * (size_t)(db->m_pad / 2), db)))
+            return rc;
+        FC_HIP(pack_nib(db, 0, db->m_pad / 8, s));
+    }
     if (flags & FC_DB_BITVECTORS) {
         size_t bytes = sizeof(uint64_t) * (size_t)sum_r * (size_t)db->words;
         if ((rc = db_alloc((void **)&db->d_bits, bytes, db))) return rc;
@@ -438,6 +473,7 @@ extern "C" int fc_db_append(fc_db *db, const uint8_t *data, int64_t m_new, int32
     }
     // 2. grow the padded columns and bit-vectors when the tile count changes
     FC_HIP(hipDeviceSynchronize());  // no launch may still read the old buffers
+    const int64_t m_pad_before = db->m_pad;
     const int64_t m_pad = ((m + kTileRows - 1) / kTileRows) * kTileRows;
     const int64_t words = m_pad / 64;
     if (m_pad != db->m_pad) {
@@ -455,6 +491,14 @@ extern "C" int fc_db_append(fc_db *db, const uint8_t *data, int64_t m_new, int32
             set_error("fc_db_append: device allocation failed");
             return FC_ERR_NOMEM;
         }
+        uint8_t *nib = nullptr;
+        if (db->d_nib && hipMalloc(&nib, (size_t)n * (size_t)(m_pad / 2)) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFree(cols);
+            if (bits) (void)hipFree(bits);
+            set_error("fc_db_append: device allocation failed");
+            return FC_ERR_NOMEM;
+        }
         FC_HIP(fill_zero_i32((int32_t *)cols, (int64_t)n * m_pad / 4, s));
         FC_HIP(hipMemcpy2DAsync(cols, (size_t)m_pad, db->d_cols, (size_t)db->m_pad,
                                 (size_t)db->m_pad, (size_t)n, hipMemcpyDeviceToDevice, s));
@@ -469,6 +513,11 @@ extern "C" int fc_db_append(fc_db *db, const uint8_t *data, int64_t m_new, int32
         (void)hipFree(db->d_cols);
         db->device_bytes += (int64_t)n * (m_pad - db->m_pad);
         db->d_cols = cols;
+        if (nib) {  // repacked whole below
+            (void)hipFree(db->d_nib);
+            db->device_bytes += (int64_t)n * (m_pad - db->m_pad) / 2;
+            db->d_nib = nib;
+        }
         if (bits) {
             (void)hipFree(db->d_bits);
             db->device_bytes += (int64_t)sizeof(uint64_t) * sum_r * (words - db->words);
@@ -477,9 +526,12 @@ extern "C" int fc_db_append(fc_db *db, const uint8_t *data, int64_t m_new, int32
         db->m_pad = m_pad;
         db->words = words;
     }
-    // 3. the new instances into the columns, then the bit-vector words they touch
+    // 3. the new instances into the columns, then the packed words and the
+    //    bit-vector words they touch (all packed words after a regrowth)
+    const bool regrown = db->m_pad != m_pad_before;
     FC_HIP(hipMemcpy2DAsync(db->d_cols + m_old, (size_t)db->m_pad, tmp.p, (size_t)m_new,
                             (size_t)m_new, (size_t)n, hipMemcpyDeviceToDevice, s));
+    FC_HIP(pack_nib(db, regrown ? 0 : m_old / 8, regrown ? db->m_pad / 8 : (m + 7) / 8, s));
     if (db->d_bits) {
         const int64_t w_lo = m_old / 64, w_hi = (m + 63) / 64;
         dim3 grid((unsigned)((w_hi - w_lo + 3) / 4), (unsigned)n);

@@ -41,6 +41,7 @@ struct Tuning {
     int64_t bitmap_chunk_rows = 65536;  // bitmap rows per workgroup (at least)
     int bitmap_words = 2;               // 64-row words per thread per tree walk
     int persistent_max_queries = 256;   // small batches: one persistent launch
+    int packed_columns = 1;             // histograms read the 4-bit columns when present
     // bitmap_cells[k-1][b]: bitmap for k variables and <= 2^(b+2) cells
     uint8_t bitmap_cells[FC_MAX_VARS][6] = {};
     Tuning() {
@@ -66,6 +67,7 @@ struct fc_db {
     std::vector<int64_t> marg;       // sum of arities
     std::vector<float> entropy;      // n, bits
     uint8_t *d_cols = nullptr;       // [n][m_pad] states
+    uint8_t *d_nib = nullptr;        // [n][m_pad/2] states, 4 bits each (all arities <= 16)
     uint64_t *d_bits = nullptr;      // [sum r][words] per-state bit-vectors
     uint8_t *d_arity = nullptr;      // [n]
     int32_t *d_soff = nullptr;       // [n+1]

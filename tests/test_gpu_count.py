@@ -192,6 +192,41 @@ def test_graph_replays_match_eager():
         g.close()
 
 
+@pytest.mark.parametrize("packed", [0, 1])
+def test_packed_and_byte_columns_agree(packed):
+    # arities up to 16 (packed columns exist); tables of every histogram class
+    rng = synth.rng_for(91)
+    n, m = 12, 70_001                                   # ragged tail
+    ar = rng.integers(2, 17, size=n).astype(np.uint8)
+    ar[0] = 16
+    D = np.stack([rng.integers(0, a, size=m) for a in ar]).astype(np.uint8)
+    qs = [rng.choice(n, size=k, replace=False).astype(np.int32)
+          for k in (1, 2, 2, 3, 3, 3, 4, 4, 5, 6) for _ in range(6)]
+    w = synth.Workload("packed-check", D, ar, *synth.flatten(qs), ())
+    print("packed=%d cells=%s" % (packed, sorted(int(np.prod(ar[q].astype(np.int64))) for q in qs)[-5:]),
+          flush=True)
+    with Database(D, ar) as db:
+        t = db.tuning()
+        t["packed_columns"] = packed
+        t["persistent_max_queries"] = 0
+        db.set_tuning(t)
+        tables, toff = db.count_batch((w.vars_flat, w.var_off), strategy="hist")
+        check_tables(w, tables, toff)
+        tables, toff = db.count_batch((w.vars_flat, w.var_off), strategy="auto")
+        check_tables(w, tables, toff)
+
+
+def test_arity_above_16_uses_byte_columns():
+    rng = synth.rng_for(92)
+    ar = np.array([17, 3, 20, 2, 5], np.uint8)
+    D = np.stack([rng.integers(0, a, size=20_000) for a in ar]).astype(np.uint8)
+    qs = [np.array(q, np.int32) for q in ([0], [0, 1], [2, 3, 4], [1, 2], [4, 3, 1, 0])]
+    w = synth.Workload("byte-check", D, ar, *synth.flatten(qs), ())
+    with Database(D, ar) as db:
+        tables, toff = db.count_batch((w.vars_flat, w.var_off), strategy="hist")
+        check_tables(w, tables, toff)
+
+
 def test_tuning_roundtrip_and_validation():
     w = synth.plain_small()
     with Database(w.D, w.arity) as db:
@@ -200,7 +235,14 @@ def test_tuning_roundtrip_and_validation():
         t["bitmap_cells"][2][3] = 1
         db.set_tuning(t)
         assert db.tuning() == t
+        t["packed_columns"] = 0
+        db.set_tuning(t)
+        assert db.tuning() == t
         t["bitmap_words"] = 3
+        with pytest.raises(_lib.FastcountError):
+            db.set_tuning(t)
+        t["bitmap_words"] = 2
+        t["packed_columns"] = 2
         with pytest.raises(_lib.FastcountError):
             db.set_tuning(t)
 
