@@ -412,13 +412,13 @@ __global__ __launch_bounds__(kBlock) void k_hist8n(const uint8_t *__restrict__ n
     hist8n_body<K>(nib, m_pad, arity, descs[di], c, chunks, pad_rows, tables, lds);
 }
 
-// Address keys (lane columns of B >= 4 words per cell): the key of two
-// instances (nibbles i and i + 4 of a word) forms in the 16-bit halves of a
-// register.  Nibble positions 1 and 3 of a half are masked in place, worth
-// 16 times their state, and use strides pre-divided by 16, which is exact
-// because a cell is 4 B >= 16 bytes wide; positions 2 and 3 come from the
-// word shifted by 8.
-template <int K>
+// Address keys (lane columns of B words per cell): the key of two instances
+// (nibbles i and i + 4 of a word) forms in the 16-bit halves of a register.
+// WIDE (B >= 4): nibble positions 1 and 3 of a half are masked in place,
+// worth 16 times their state, and use strides pre-divided by 16, which is
+// exact because a cell is 4 B >= 16 bytes wide; positions 2 and 3 come from
+// the word shifted by 8.  Otherwise every position is shifted down first.
+template <int K, bool WIDE>
 __device__ __forceinline__ void hist16n_body(const uint8_t *__restrict__ nib, int64_t m_pad,
                                              const uint8_t *__restrict__ arity, const QDesc &q,
                                              int32_t c, int32_t chunks, int32_t lds_words,
@@ -426,7 +426,7 @@ __device__ __forceinline__ void hist16n_body(const uint8_t *__restrict__ nib, in
                                              uint32_t *lds) {
     const int32_t cells = q.cells;
     int32_t B = lds_words / cells;
-    B = B >= 64 ? 64 : B >= 32 ? 32 : B >= 16 ? 16 : B >= 8 ? 8 : 4;  // >= 4 by the class
+    B = B >= 64 ? 64 : B >= 32 ? 32 : B >= 16 ? 16 : B >= 8 ? 8 : B >= 4 ? 4 : B >= 2 ? 2 : 1;
     uint32_t sa[K], sq[K];
     Col colp[K];
     {
@@ -435,7 +435,8 @@ __device__ __forceinline__ void hist16n_body(const uint8_t *__restrict__ nib, in
         for (int t = K - 1; t >= 0; --t) {
             const int32_t v = q.var[t];
             sa[t] = (s * 4u * (uint32_t)B) * 0x00010001u;  // byte stride of a state
-            sq[t] = (s * (uint32_t)B / 4u) * 0x00010001u;  // the same for 16 x state
+            sq[t] = WIDE ? (s * (uint32_t)B / 4u) * 0x00010001u  // the same for 16 x state
+                         : sa[t];
             s *= arity[v];
             colp[t] = make_col(nib + (int64_t)v * (m_pad / 2), m_pad / 2);
         }
@@ -460,9 +461,14 @@ __device__ __forceinline__ void hist16n_body(const uint8_t *__restrict__ nib, in
                 const uint32_t w = d == 0 ? v[t].x : d == 1 ? v[t].y : d == 2 ? v[t].z : v[t].w;
                 const uint32_t w8 = w >> 8;
                 a0 = pk_mad_u16(w & 0x000F000Fu, sa[t], a0);
-                a1 = pk_mad_u16(w & 0x00F000F0u, sq[t], a1);
                 a2 = pk_mad_u16(w8 & 0x000F000Fu, sa[t], a2);
-                a3 = pk_mad_u16(w8 & 0x00F000F0u, sq[t], a3);
+                if (WIDE) {
+                    a1 = pk_mad_u16(w & 0x00F000F0u, sq[t], a1);
+                    a3 = pk_mad_u16(w8 & 0x00F000F0u, sq[t], a3);
+                } else {
+                    a1 = pk_mad_u16((w >> 4) & 0x000F000Fu, sq[t], a1);
+                    a3 = pk_mad_u16((w >> 12) & 0x000F000Fu, sq[t], a3);
+                }
             }
             atomicAdd(reinterpret_cast<uint32_t *>(base + (a0 & 0xFFFFu)), 1u);
             atomicAdd(reinterpret_cast<uint32_t *>(base + (a1 & 0xFFFFu)), 1u);
@@ -478,7 +484,7 @@ __device__ __forceinline__ void hist16n_body(const uint8_t *__restrict__ nib, in
     flush_cols(lds, cells, B, (r1 == m_pad) && (r0 < r1), pad_rows, tables + q.table_off);
 }
 
-template <int K>
+template <int K, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_hist16n(const uint8_t *__restrict__ nib,
                                                     int64_t m_pad,
                                                     const uint8_t *__restrict__ arity,
@@ -489,7 +495,8 @@ __global__ __launch_bounds__(kBlock) void k_hist16n(const uint8_t *__restrict__ 
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     int32_t di, c;
     map_block(blockIdx.x, nd, chunks, di, c);
-    hist16n_body<K>(nib, m_pad, arity, descs[di], c, chunks, lds_words, pad_rows, tables, lds);
+    hist16n_body<K, WIDE>(nib, m_pad, arity, descs[di], c, chunks, lds_words, pad_rows, tables,
+                          lds);
 }
 
 // Bitmap count (Alg. 1) of one descriptor over one chunk of 64-row words.
@@ -789,7 +796,8 @@ struct Launch {
     int strat;
     int K;
     bool small;
-    int32_t hk;       // histogram kernel: HK_HIST8, HK_HIST16 or HK_GENERIC
+    int32_t hk;       // histogram kernel: HK_HIST8(N), HK_HIST16(N) or HK_GENERIC
+    bool wide;        // every table of the group has lane columns of >= 4 words
     int64_t first;    // first descriptor
     int32_t count;    // descriptors
     int32_t chunks;
@@ -815,7 +823,7 @@ static const int32_t kClassLds[] = {16 * 64 * 4, 64 * 64 * 4, 256 * 32 * 4, 1024
                                     4096 * 2 * 4, 16383 * 4,  kHistMaxCells * 4 + 4};
 constexpr int kHist8Classes = 2;
 constexpr int kHist16Classes = 6;
-constexpr int kHist16nClasses = 4;  // lane columns of at least 4 words per cell
+constexpr int kHist16nWide = 4;     // classes with lane columns of at least 4 words
 enum { HK_GENERIC = 0, HK_HIST16 = 1, HK_HIST8 = 2, HK_HIST16N = 3, HK_HIST8N = 4 };
 
 static int hist_class(int64_t cells) {
@@ -1169,9 +1177,10 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
                     const bool nib = db->d_nib && db->tune.packed_columns;
                     L.hk = st != S_HIST                    ? HK_GENERIC
                            : cls < kHist8Classes            ? (nib ? HK_HIST8N : HK_HIST8)
-                           : nib && cls < kHist16nClasses   ? HK_HIST16N
+                           : nib && cls < kHist16Classes    ? HK_HIST16N
                            : cls < kHist16Classes           ? HK_HIST16
                                                             : HK_GENERIC;
+                    L.wide = cls < kHist16nWide;
                     if (L.hk == HK_HIST8N || L.hk == HK_HIST16N)
                         bytes *= 0.5;  // half a byte per state
                     L.lds_bytes = st == S_BITMAP ? (int32_t)(maxc * kBlock * 4) : kClassLds[cls];
@@ -1206,9 +1215,13 @@ static hipError_t launch_hist_k(const fc_db *db, const Launch &L, const QDesc *d
     else if (L.hk == HK_HIST8N)
         hipLaunchKernelGGL((k_hist8n<K, 64>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
                            db->d_nib, db->m_pad, db->d_arity, d, L.count, L.chunks, pad, tables);
+    else if (L.hk == HK_HIST16N && L.wide)
+        hipLaunchKernelGGL((k_hist16n<K, true>), dim3((unsigned)blocks), dim3(kBlock), L.lds_bytes,
+                           s, db->d_nib, db->m_pad, db->d_arity, d, L.count, L.chunks,
+                           L.lds_bytes / 4, pad, tables);
     else if (L.hk == HK_HIST16N)
-        hipLaunchKernelGGL((k_hist16n<K>), dim3((unsigned)blocks), dim3(kBlock), L.lds_bytes, s,
-                           db->d_nib, db->m_pad, db->d_arity, d, L.count, L.chunks,
+        hipLaunchKernelGGL((k_hist16n<K, false>), dim3((unsigned)blocks), dim3(kBlock),
+                           L.lds_bytes, s, db->d_nib, db->m_pad, db->d_arity, d, L.count, L.chunks,
                            L.lds_bytes / 4, pad, tables);
     else if (L.hk == HK_HIST8 && L.lds_bytes <= 16 * 64 * 4)
         hipLaunchKernelGGL((k_hist8<K, 16>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
@@ -1283,7 +1296,9 @@ static void set_attrs_k() {
                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
     (void)hipFuncSetAttribute((const void *)k_hist16<K>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
-    (void)hipFuncSetAttribute((const void *)k_hist16n<K>,
+    (void)hipFuncSetAttribute((const void *)k_hist16n<K, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
+    (void)hipFuncSetAttribute((const void *)k_hist16n<K, false>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
     (void)hipFuncSetAttribute((const void *)k_bitmap<K, 1>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
