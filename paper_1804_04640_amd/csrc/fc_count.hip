@@ -1188,12 +1188,12 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
                     if (st == S_BITMAP)
                         snprintf(L.name, sizeof L.name, "k_bitmap<%d,%d>", K,
                                  db->tune.bitmap_words >= 4 ? 4 : db->tune.bitmap_words == 2 ? 2 : 1);
-                    else if (L.hk == HK_HIST8)
-                        snprintf(L.name, sizeof L.name, "k_hist8<%d>", K);
-                    else if (L.hk == HK_HIST8N)
-                        snprintf(L.name, sizeof L.name, "k_hist8n<%d>", K);
-                    else if (L.hk == HK_HIST16N)
-                        snprintf(L.name, sizeof L.name, "k_hist16n<%d>", K);
+                    else if (L.hk == HK_HIST8 || L.hk == HK_HIST8N)  // <K, LDS cells>
+                        snprintf(L.name, sizeof L.name, "k_hist8%s<%d,%d>",
+                                 L.hk == HK_HIST8N ? "n" : "", K,
+                                 L.lds_bytes <= 16 * 64 * 4 ? 16 : 64);
+                    else if (L.hk == HK_HIST16N)  // <K, lane columns of >= 4 words>
+                        snprintf(L.name, sizeof L.name, "k_hist16n<%d,%d>", K, L.wide ? 1 : 0);
                     else if (L.hk == HK_HIST16)
                         snprintf(L.name, sizeof L.name, "k_hist16<%d>", K);
                     else
