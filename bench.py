@@ -43,6 +43,21 @@ def src_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def counter_traffic(workload_name: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
+    summary was taken on other kernel sources."""
+    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(tfile) as f:
+            ent = json.load(f).get(workload_name, {}).get(kernel)
+        if ent and ent.get("src_hash") == src_hash():
+            return ent["bytes_per_launch"]
+    except (OSError, ValueError):
+        pass
+    return None
+
+
 def workload(name: str):
     from paper_1804_04640_amd import synth
     if name == "bn-family":
@@ -278,7 +293,8 @@ def bench_pairs(args, w):
         "roofline": {"bound": "mfma", "kernel": "k_gram", "achieved": achieved,
                      "peak": INT8_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / INT8_PEAK_TOPS,
                      "avg_launch_us": 1e3 * g["ms"] / g["launches"],
-                     "alg_ops_per_launch": g["alg_ops"] / g["launches"], "traffic": None},
+                     "alg_ops_per_launch": g["alg_ops"] / g["launches"],
+                     "traffic": counter_traffic(w.name, "k_gram")},
         "cpu_baseline": None,
     }
     if args.cpu_budget > 0:
@@ -437,16 +453,7 @@ def main():
     c_ms = sum(v["ms"] for v in counting.values())
     c_bytes = sum(v["alg_bytes"] for v in counting.values())
     achieved = dom["alg_bytes"] / (dom["ms"] * 1e-3) / 1e9 if dom["ms"] > 0 else 0.0
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tfile):
-        try:
-            tj = json.load(open(tfile))
-            ent = tj.get(args.workload, {}).get(dom_name)
-            if ent and ent.get("src_hash") == src_hash():
-                traffic = ent["bytes_per_launch"]
-        except Exception:
-            traffic = None
+    traffic = counter_traffic(args.workload, dom_name)
     out = {
         "metric": "exact query-rows counted/s + HBM GB/s frac; batched vs per-query; p50/p99 ms",
         "value": value,
