@@ -251,6 +251,15 @@ __device__ __forceinline__ void hist16_body(const uint8_t *__restrict__ cols, in
     flush_cols(lds, cells, B, (r1 == m_pad) && (r0 < r1), pad_rows, tables + q.table_off);
 }
 
+// LDS byte address of byte-key `i` of `key` (selector 0x0c0c0400 + i*256):
+// B = 64: key*256 + slot with slot = lane*4; B = 32: (key*256 + slot) / 2
+// with slot = (lane mod 32)*8.
+template <int B>
+__device__ __forceinline__ uint32_t lds_addr(uint32_t key, uint32_t slot, uint32_t sel) {
+    const uint32_t a = __builtin_amdgcn_perm(key, slot, sel);
+    return B == 64 ? a : a >> 1;
+}
+
 // LDS histogram for tables of at most 256 cells.  A column word holds four
 // instances as bytes, so its low 16-bit half is b1*256 + b0; summed over the
 // query's columns with packed multiply-adds, (b1*256 + b0) * stride gives
@@ -259,8 +268,9 @@ __device__ __forceinline__ void hist16_body(const uint8_t *__restrict__ cols, in
 // packed multiply-add per column thus forms four keys, and one byte permute
 // per instance turns a key into the LDS byte address key*256 + lane*4: every
 // cell owns 64 words, one per lane, so no ds_add of a wave has a bank
-// conflict whatever the keys.
-template <int K>
+// conflict whatever the keys.  B = 32 (tables of up to 256 cells in 32 KiB):
+// the permute builds key*256 + (lane mod 32)*8 and one shift halves it.
+template <int K, int B>
 __device__ __forceinline__ void hist8_body(const uint8_t *__restrict__ cols, int64_t m_pad,
                                            const uint8_t *__restrict__ arity, const QDesc &q,
                                            int32_t c, int32_t chunks, int32_t pad_rows,
@@ -278,12 +288,12 @@ __device__ __forceinline__ void hist8_body(const uint8_t *__restrict__ cols, int
             colp[t] = make_col(cols + (int64_t)v * m_pad, m_pad);
         }
     }
-    zero_cols(lds, cells * 64);
+    zero_cols(lds, cells * B);
     __syncthreads();
     const int64_t tiles = m_pad / kTileRows;
     const int64_t r0 = (int64_t)c * tiles / chunks * kTileRows;
     const int64_t r1 = (int64_t)(c + 1) * tiles / chunks * kTileRows;
-    const uint32_t slot = (threadIdx.x & 63u) * 4u;
+    const uint32_t slot = B == 64 ? (threadIdx.x & 63u) * 4u : (threadIdx.x & 31u) * 8u;
     char *base = reinterpret_cast<char *>(lds);
 
     for (uint32_t row = (uint32_t)r0 + threadIdx.x * 16u; row < (uint32_t)r1; row += kBlock * 16u) {
@@ -299,14 +309,14 @@ __device__ __forceinline__ void hist8_body(const uint8_t *__restrict__ cols, int
                 key = pk_mad_u16(w, sb[t], key);
             }
             // byte 0 of the address from `slot`, byte 1 from key byte i
-            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(key, slot, 0x0c0c0400u)), 1u);
-            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(key, slot, 0x0c0c0500u)), 1u);
-            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(key, slot, 0x0c0c0600u)), 1u);
-            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(key, slot, 0x0c0c0700u)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + lds_addr<B>(key, slot, 0x0c0c0400u)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + lds_addr<B>(key, slot, 0x0c0c0500u)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + lds_addr<B>(key, slot, 0x0c0c0600u)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + lds_addr<B>(key, slot, 0x0c0c0700u)), 1u);
         }
     }
     __syncthreads();
-    flush_cols(lds, cells, 64, (r1 == m_pad) && (r0 < r1), pad_rows, tables + q.table_off);
+    flush_cols(lds, cells, B, (r1 == m_pad) && (r0 < r1), pad_rows, tables + q.table_off);
 }
 
 // CAP: the launch group's largest table.  The histogram is a static LDS
@@ -319,10 +329,11 @@ __global__ __launch_bounds__(kBlock) void k_hist8(const uint8_t *__restrict__ co
                                                   const QDesc *__restrict__ descs, int32_t nd,
                                                   int32_t chunks, int32_t pad_rows,
                                                   int32_t *__restrict__ tables) {
-    __shared__ __attribute__((aligned(16))) uint32_t lds[CAP * 64];
+    constexpr int B = CAP <= 64 ? 64 : 32;
+    __shared__ __attribute__((aligned(16))) uint32_t lds[CAP * B];
     int32_t di, c;
     map_block(blockIdx.x, nd, chunks, di, c);
-    hist8_body<K>(cols, m_pad, arity, descs[di], c, chunks, pad_rows, tables, lds);
+    hist8_body<K, B>(cols, m_pad, arity, descs[di], c, chunks, pad_rows, tables, lds);
 }
 
 template <int K>
@@ -346,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void k_hist16(const uint8_t *__restrict__ c
 // Byte keys (tables of at most 64 cells): the even and the odd nibbles of a
 // word, masked into bytes, give two chains of packed multiply-adds, four
 // keys each.
-template <int K>
+template <int K, int B>
 __device__ __forceinline__ void hist8n_body(const uint8_t *__restrict__ nib, int64_t m_pad,
                                             const uint8_t *__restrict__ arity, const QDesc &q,
                                             int32_t c, int32_t chunks, int32_t pad_rows,
@@ -364,12 +375,12 @@ __device__ __forceinline__ void hist8n_body(const uint8_t *__restrict__ nib, int
             colp[t] = make_col(nib + (int64_t)v * (m_pad / 2), m_pad / 2);
         }
     }
-    zero_cols(lds, cells * 64);
+    zero_cols(lds, cells * B);
     __syncthreads();
     const int64_t tiles = m_pad / kTileRows;
     const int64_t r0 = (int64_t)c * tiles / chunks * kTileRows;
     const int64_t r1 = (int64_t)(c + 1) * tiles / chunks * kTileRows;
-    const uint32_t slot = (threadIdx.x & 63u) * 4u;
+    const uint32_t slot = B == 64 ? (threadIdx.x & 63u) * 4u : (threadIdx.x & 31u) * 8u;
     char *base = reinterpret_cast<char *>(lds);
 
     for (uint32_t row = (uint32_t)r0 + threadIdx.x * 32u; row < (uint32_t)r1; row += kBlock * 32u) {
@@ -385,18 +396,18 @@ __device__ __forceinline__ void hist8n_body(const uint8_t *__restrict__ nib, int
                 ke = pk_mad_u16(w & 0x0F0F0F0Fu, sb[t], ke);
                 ko = pk_mad_u16((w >> 4) & 0x0F0F0F0Fu, sb[t], ko);
             }
-            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(ke, slot, 0x0c0c0400u)), 1u);
-            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(ke, slot, 0x0c0c0500u)), 1u);
-            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(ke, slot, 0x0c0c0600u)), 1u);
-            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(ke, slot, 0x0c0c0700u)), 1u);
-            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(ko, slot, 0x0c0c0400u)), 1u);
-            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(ko, slot, 0x0c0c0500u)), 1u);
-            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(ko, slot, 0x0c0c0600u)), 1u);
-            atomicAdd(reinterpret_cast<uint32_t *>(base + __builtin_amdgcn_perm(ko, slot, 0x0c0c0700u)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + lds_addr<B>(ke, slot, 0x0c0c0400u)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + lds_addr<B>(ke, slot, 0x0c0c0500u)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + lds_addr<B>(ke, slot, 0x0c0c0600u)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + lds_addr<B>(ke, slot, 0x0c0c0700u)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + lds_addr<B>(ko, slot, 0x0c0c0400u)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + lds_addr<B>(ko, slot, 0x0c0c0500u)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + lds_addr<B>(ko, slot, 0x0c0c0600u)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t *>(base + lds_addr<B>(ko, slot, 0x0c0c0700u)), 1u);
         }
     }
     __syncthreads();
-    flush_cols(lds, cells, 64, (r1 == m_pad) && (r0 < r1), pad_rows, tables + q.table_off);
+    flush_cols(lds, cells, B, (r1 == m_pad) && (r0 < r1), pad_rows, tables + q.table_off);
 }
 
 template <int K, int CAP>
@@ -406,10 +417,11 @@ __global__ __launch_bounds__(kBlock) void k_hist8n(const uint8_t *__restrict__ n
                                                    const QDesc *__restrict__ descs, int32_t nd,
                                                    int32_t chunks, int32_t pad_rows,
                                                    int32_t *__restrict__ tables) {
-    __shared__ __attribute__((aligned(16))) uint32_t lds[CAP * 64];
+    constexpr int B = CAP <= 64 ? 64 : 32;
+    __shared__ __attribute__((aligned(16))) uint32_t lds[CAP * B];
     int32_t di, c;
     map_block(blockIdx.x, nd, chunks, di, c);
-    hist8n_body<K>(nib, m_pad, arity, descs[di], c, chunks, pad_rows, tables, lds);
+    hist8n_body<K, B>(nib, m_pad, arity, descs[di], c, chunks, pad_rows, tables, lds);
 }
 
 // Address keys (lane columns of B words per cell): the key of two instances
@@ -603,7 +615,7 @@ __device__ __forceinline__ void persistent_case(int type, const uint8_t *cols, i
                                                 uint32_t *lds) {
     switch (type) {
         case PK_HIST8:
-            hist8_body<K>(cols, m_pad, arity, q, c, chunks, pad, tables, lds);
+            hist8_body<K, 64>(cols, m_pad, arity, q, c, chunks, pad, tables, lds);
             break;
         case PK_HIST16:
             hist16_body<K>(cols, m_pad, arity, q, c, chunks, lds_words, pad, tables, lds);
@@ -816,12 +828,12 @@ struct Plan {
 
 // LDS size classes; every class but the last keeps its byte addresses below
 // 2^16 (the packed 16-bit key path).
-// Classes up to 64 cells use the byte-key kernel (64 words per cell; at
-// 256 cells its 64 KiB of LDS would halve the resident workgroups).
+// Classes up to 256 cells use the byte-key kernels (64 words per cell up to
+// 64 cells, 32 above, so that no class takes more than 32 KiB of LDS).
 static const int32_t kClassCap[] = {16, 64, 256, 1024, 4096, 16383, kHistMaxCells};
 static const int32_t kClassLds[] = {16 * 64 * 4, 64 * 64 * 4, 256 * 32 * 4, 1024 * 8 * 4,
                                     4096 * 2 * 4, 16383 * 4,  kHistMaxCells * 4 + 4};
-constexpr int kHist8Classes = 2;
+constexpr int kHist8Classes = 3;
 constexpr int kHist16Classes = 6;
 constexpr int kHist16nWide = 4;     // classes with lane columns of at least 4 words
 enum { HK_GENERIC = 0, HK_HIST16 = 1, HK_HIST8 = 2, HK_HIST16N = 3, HK_HIST8N = 4 };
@@ -1191,7 +1203,9 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
                     else if (L.hk == HK_HIST8 || L.hk == HK_HIST8N)  // <K, LDS cells>
                         snprintf(L.name, sizeof L.name, "k_hist8%s<%d,%d>",
                                  L.hk == HK_HIST8N ? "n" : "", K,
-                                 L.lds_bytes <= 16 * 64 * 4 ? 16 : 64);
+                                 L.lds_bytes <= 16 * 64 * 4   ? 16
+                                 : L.lds_bytes <= 64 * 64 * 4 ? 64
+                                                              : 256);
                     else if (L.hk == HK_HIST16N)  // <K, lane columns of >= 4 words>
                         snprintf(L.name, sizeof L.name, "k_hist16n<%d,%d>", K, L.wide ? 1 : 0);
                     else if (L.hk == HK_HIST16)
@@ -1212,8 +1226,11 @@ static hipError_t launch_hist_k(const fc_db *db, const Launch &L, const QDesc *d
     if (L.hk == HK_HIST8N && L.lds_bytes <= 16 * 64 * 4)
         hipLaunchKernelGGL((k_hist8n<K, 16>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
                            db->d_nib, db->m_pad, db->d_arity, d, L.count, L.chunks, pad, tables);
-    else if (L.hk == HK_HIST8N)
+    else if (L.hk == HK_HIST8N && L.lds_bytes <= 64 * 64 * 4)
         hipLaunchKernelGGL((k_hist8n<K, 64>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                           db->d_nib, db->m_pad, db->d_arity, d, L.count, L.chunks, pad, tables);
+    else if (L.hk == HK_HIST8N)
+        hipLaunchKernelGGL((k_hist8n<K, 256>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
                            db->d_nib, db->m_pad, db->d_arity, d, L.count, L.chunks, pad, tables);
     else if (L.hk == HK_HIST16N && L.wide)
         hipLaunchKernelGGL((k_hist16n<K, true>), dim3((unsigned)blocks), dim3(kBlock), L.lds_bytes,
@@ -1226,8 +1243,11 @@ static hipError_t launch_hist_k(const fc_db *db, const Launch &L, const QDesc *d
     else if (L.hk == HK_HIST8 && L.lds_bytes <= 16 * 64 * 4)
         hipLaunchKernelGGL((k_hist8<K, 16>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
                            db->d_cols, db->m_pad, db->d_arity, d, L.count, L.chunks, pad, tables);
-    else if (L.hk == HK_HIST8)
+    else if (L.hk == HK_HIST8 && L.lds_bytes <= 64 * 64 * 4)
         hipLaunchKernelGGL((k_hist8<K, 64>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                           db->d_cols, db->m_pad, db->d_arity, d, L.count, L.chunks, pad, tables);
+    else if (L.hk == HK_HIST8)
+        hipLaunchKernelGGL((k_hist8<K, 256>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
                            db->d_cols, db->m_pad, db->d_arity, d, L.count, L.chunks, pad, tables);
     else if (L.hk == HK_HIST16)
         hipLaunchKernelGGL((k_hist16<K>), dim3((unsigned)blocks), dim3(kBlock), L.lds_bytes, s,
