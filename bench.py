@@ -388,11 +388,10 @@ def main():
             tuning = db.tuning()
         elif args.autotune:
             t0 = time.time()
-            rng = np.random.default_rng(0)
-            ids = np.sort(rng.choice(nq, size=min(nq, max(4000, nq // 10)), replace=False))
-            tuning = db.autotune([w.query(int(i)) for i in ids], cache=args.tune_cache,
-                                 stream=stream)
-            print("# autotuned on %d queries in %.1fs: %s" % (len(ids), time.time() - t0,
+            # the batch itself: row-chunk choices depend on how many
+            # workgroups a launch group has, so a smaller sample misleads
+            tuning = db.autotune(q, cache=args.tune_cache, stream=stream)
+            print("# autotuned on %d queries in %.1fs: %s" % (nq, time.time() - t0,
                                                               json.dumps(tuning)),
                   file=sys.stderr, flush=True)
 

@@ -37,7 +37,7 @@ struct alignas(16) QDesc {
 static_assert(sizeof(QDesc) == 64, "QDesc must be 64 bytes");
 
 struct Tuning {
-    int64_t chunk_rows = 65536;         // histogram rows per workgroup (at least)
+    int64_t chunk_rows = 131072;        // histogram rows per workgroup (at least)
     int64_t bitmap_chunk_rows = 65536;  // bitmap rows per workgroup (at least)
     int bitmap_words = 2;               // 64-row words per thread per tree walk
     int persistent_max_queries = 256;   // small batches: one persistent launch
