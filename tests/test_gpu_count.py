@@ -216,6 +216,67 @@ def test_packed_and_byte_columns_agree(packed):
         check_tables(w, tables, toff)
 
 
+# tables whose cell counts sit on both sides of every size-class boundary of
+# the histogram kernels (16, 64, 256, 1024, 4096, 16383, 40000 cells)
+_BOUNDARY_QUERIES = {
+    16: [4, 4], 18: [2, 9], 64: [4, 16], 65: [5, 13], 256: [16, 16], 260: [4, 5, 13],
+    1024: [4, 16, 16], 1050: [2, 3, 5, 5, 7], 4096: [16, 16, 16], 4116: [4, 3, 7, 7, 7],
+    16380: [4, 9, 5, 7, 13], 16384: [4, 16, 16, 16], 40000: [16, 4, 5, 5, 5, 5],
+    40960: [16, 16, 16, 10], 256 * 256: [16, 16, 16, 16],
+}
+
+
+@pytest.mark.parametrize("packed", [0, 1])
+def test_size_class_boundaries(packed):
+    # one variable per needed arity (repeated arities get several variables),
+    # k = 8 queries of binary variables too
+    need = {}
+    for ars in _BOUNDARY_QUERIES.values():
+        for a in set(ars):
+            need[a] = max(need.get(a, 0), ars.count(a))
+    arity = []
+    first = {}
+    for a in sorted(need):
+        first[a] = len(arity)
+        arity += [a] * need[a]
+    arity += [2] * 8
+    ar = np.array(arity, np.uint8)
+    rng = synth.rng_for(93)
+    m = 50_003
+    D = np.stack([rng.integers(0, a, size=m) for a in ar]).astype(np.uint8)
+    qs = []
+    for cells, ars in _BOUNDARY_QUERIES.items():
+        used = {}
+        q = []
+        for a in ars:
+            q.append(first[a] + used.get(a, 0))
+            used[a] = used.get(a, 0) + 1
+        assert int(np.prod(ar[q].astype(np.int64))) == cells
+        qs.append(np.array(q, np.int32))
+        qs.append(np.array(q[::-1], np.int32))
+    nb = len(arity) - 8
+    qs.append(np.arange(nb, nb + 8, dtype=np.int32))            # k = 8, 256 cells
+    qs.append(np.array([first[3], first[5]] + list(range(nb, nb + 6)), np.int32))
+    w = synth.Workload("boundaries", D, ar, *synth.flatten(qs), ())
+    print("packed=%d queries=%d" % (packed, len(qs)), flush=True)
+    with Database(D, ar) as db:
+        t = db.tuning()
+        t["packed_columns"] = packed
+        db.set_tuning(t)
+        for strategy in ("hist", "auto"):
+            tables, toff = db.count_batch((w.vars_flat, w.var_off), strategy=strategy)
+            check_tables(w, tables, toff)
+
+
+def test_empty_batches():
+    w = synth.plain_small(m=2000, nq=5)
+    with Database(w.D, w.arity) as db:
+        tables, toff = db.count_batch([])
+        assert len(toff) == 1 and toff[0] == 0
+        scores, _, _, _ = db.count_reduce([], ("mdl", "mi"))
+        assert all(v.numel() == 0 for v in scores.values())
+
+
 def test_arity_above_16_uses_byte_columns():
     rng = synth.rng_for(92)
     ar = np.array([17, 3, 20, 2, 5], np.uint8)
