@@ -6,7 +6,11 @@
 //    the MSD radix of Section 3.3, child least significant) and the key's
 //    cell is incremented in an LDS histogram.  Each cell owns up to 64
 //    consecutive words (one per lane slot, as many as the LDS allows), so
-//    lanes of a wave add into different banks whatever their keys.
+//    lanes of a wave add into different banks whatever their keys.  Keys of
+//    tables up to 256 cells form as bytes (four instances per packed
+//    multiply-add), up to 16,383 cells as 16-bit LDS addresses (two per
+//    packed multiply-add); databases whose arities are all at most 16 are
+//    also read from a 4-bit packed copy of the columns.
 //  * BITMAP: the per-state bit-vectors of the query's variables are ANDed
 //    down the configuration tree of Alg. 1 and the leaves are popcounted; a
 //    subtree whose prefix is empty in every lane of the wave is pruned, as
@@ -26,7 +30,7 @@
 
 namespace fc {
 
-constexpr int kHistMaxCells = 40000;  // odd row stride * 4 B <= 160 KiB
+constexpr int kHistMaxCells = 40000;  // generic kernel: odd row stride * 4 B <= 160 KiB
 constexpr int32_t kPersistentLds = 64 * 64 * 4;  // groups up to this LDS share one launch
 
 __device__ __forceinline__ void map_block(int64_t b, int32_t nd, int32_t chunks, int32_t &d,
@@ -181,10 +185,11 @@ __device__ __forceinline__ void flush_cols(const uint32_t *lds, int32_t cells, i
     }
 }
 
-// LDS histogram for tables whose copies fit 64 KiB (no key window): the key
-// of two instances at a time is formed in the 16-bit halves of one register
-// with packed multiply-adds, directly as an LDS byte address (strides are
-// pre-scaled by 4 and the lane's copy offset is the accumulator's start).
+// LDS histogram for tables whose lane columns fit 64 KiB (no key window):
+// the key of two instances at a time is formed in the 16-bit halves of one
+// register with packed multiply-adds, directly as an LDS byte address
+// (strides are pre-scaled by 4 B and the lane's word offset is the
+// accumulator's start).
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t pk_mad_u16(uint32_t a, uint32_t b, uint32_t c) {
     const u16x2 x = __builtin_bit_cast(u16x2, a), y = __builtin_bit_cast(u16x2, b),
