@@ -451,6 +451,15 @@ def main():
     counting = {k: v for k, v in prof.items() if v["alg_bytes"] > 0}
     c_ms = sum(v["ms"] for v in counting.values())
     c_bytes = sum(v["alg_bytes"] for v in counting.values())
+    # histogram kernels add one LDS counter per (query, instance): their
+    # algorithmic bytes are K per unit, K/2 for the packed-column kernels
+    h_units, h_ms = 0.0, 0.0
+    for name, v in counting.items():
+        if name.startswith("k_hist"):
+            kk = int(name.split("<")[1].split(",")[0].rstrip(">"))
+            per = kk / 2.0 if name.split("<")[0].endswith("n") else float(kk)
+            h_units += v["alg_bytes"] / per
+            h_ms += v["ms"]
     achieved = dom["alg_bytes"] / (dom["ms"] * 1e-3) / 1e9 if dom["ms"] > 0 else 0.0
     traffic = counter_traffic(args.workload, dom_name)
     out = {
@@ -473,6 +482,7 @@ def main():
                     "effective_GBps": alg_bytes / (ms * 1e-3) / 1e9,
                     "effective_hbm_frac": alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                     "counting_kernels_GBps": c_bytes / (c_ms * 1e-3) / 1e9 if c_ms else None,
+                    "histogram_lds_adds_per_s": h_units / (h_ms * 1e-3) if h_ms else None,
                     "kernels": {k: {"launches": v["launches"], "avg_us": 1e3 * v["ms"] / v["launches"],
                                     "share": v["ms"] / sum(x["ms"] for x in prof.values())}
                                 for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}},
