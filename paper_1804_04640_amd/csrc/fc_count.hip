@@ -517,12 +517,32 @@ __global__ __launch_bounds__(kBlock) void k_hist16n(const uint8_t *__restrict__ 
 }
 
 // Bitmap count (Alg. 1) of one descriptor over one chunk of 64-row words.
+// Leaf rows (the last variable's states) of up to kLeafMax states are loaded
+// once per word group into registers and reused under every prefix.
+constexpr int kLeafMax = 8;
+
 template <int L, int K, int W>
 struct Walk {
     __device__ __forceinline__ static void go(const uint64_t (&pre)[W], uint32_t cell,
                                               const uint64_t *__restrict__ bits, int64_t words,
                                               int64_t w, const int32_t (&base)[K],
-                                              const int32_t (&rad)[K], uint32_t *acc) {
+                                              const int32_t (&rad)[K], bool cached,
+                                              const uint64_t (&leaf)[kLeafMax][W],
+                                              uint32_t *acc) {
+        if constexpr (L == K - 1) {
+            if (cached) {
+#pragma unroll
+                for (int s = 0; s < kLeafMax; ++s) {
+                    if (s < rad[L]) {
+                        uint32_t pc = 0;
+#pragma unroll
+                        for (int i = 0; i < W; ++i) pc += (uint32_t)__popcll(leaf[s][i] & pre[i]);
+                        acc[(cell * (uint32_t)rad[L] + (uint32_t)s) * kBlock] += pc;
+                    }
+                }
+                return;
+            }
+        }
         for (int32_t s = 0; s < rad[L]; ++s) {
             const uint64_t *row = bits + (int64_t)(base[L] + s) * words + w;
             uint64_t x[W];
@@ -538,7 +558,8 @@ struct Walk {
                 uint64_t any = 0;
 #pragma unroll
                 for (int i = 0; i < W; ++i) any |= x[i];
-                if (__any(any != 0)) Walk<L + 1, K, W>::go(x, c2, bits, words, w, base, rad, acc);
+                if (__any(any != 0))
+                    Walk<L + 1, K, W>::go(x, c2, bits, words, w, base, rad, cached, leaf, acc);
             }
         }
     }
@@ -566,8 +587,25 @@ __device__ __forceinline__ void bitmap_body(const uint64_t *__restrict__ bits, i
     uint64_t ones[W];
 #pragma unroll
     for (int i = 0; i < W; ++i) ones[i] = ~0ull;
-    for (int64_t w = w0 + (int64_t)threadIdx.x * W; w < w1; w += kBlock * W)
-        Walk<0, K, W>::go(ones, 0u, bits, words, w, base, rad, acc + threadIdx.x);
+    // K = 1: the root level is the leaf level and every row is read once
+    const bool cached = K > 1 && rad[K - 1] <= kLeafMax;
+    uint64_t leaf[kLeafMax][W];
+    for (int64_t w = w0 + (int64_t)threadIdx.x * W; w < w1; w += kBlock * W) {
+        if (cached) {
+#pragma unroll
+            for (int s = 0; s < kLeafMax; ++s) {
+                if (s < rad[K - 1]) {  // uniform: no load for absent states
+                    const uint64_t *row = bits + (int64_t)(base[K - 1] + s) * words + w;
+#pragma unroll
+                    for (int i = 0; i < W; ++i) leaf[s][i] = row[i];
+                } else {
+#pragma unroll
+                    for (int i = 0; i < W; ++i) leaf[s][i] = 0ull;
+                }
+            }
+        }
+        Walk<0, K, W>::go(ones, 0u, bits, words, w, base, rad, cached, leaf, acc + threadIdx.x);
+    }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int32_t *out = tables + q.table_off;
