@@ -22,6 +22,7 @@
 // Partial tables of row chunks are summed into the output with int32
 // atomics, which is exact and order independent.
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <thread>
@@ -1388,17 +1389,17 @@ template <int W>
 static hipError_t launch_persistent_w(const fc_db *db, const PGroup *d_groups, int32_t ngroups,
                                       int64_t vtotal, uint32_t *heads, int32_t lds,
                                       const QDesc *dw, int32_t *tables, hipStream_t s) {
-    static int per_cu[5] = {0, 0, 0, 0, 0};
-    if (!per_cu[W]) {
-        int nb = 0;
+    static std::atomic<int> per_cu{0};  // resident workgroups per CU (one value per W)
+    int nb = per_cu.load(std::memory_order_relaxed);
+    if (!nb) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_count_persistent<W>, kBlock,
                                                          kPersistentLds) != hipSuccess || nb < 1) {
             (void)hipGetLastError();
             nb = 2;
         }
-        per_cu[W] = nb;
+        per_cu.store(nb, std::memory_order_relaxed);
     }
-    int64_t grid = (int64_t)per_cu[W] * db->cu_count;
+    int64_t grid = (int64_t)nb * db->cu_count;
     grid = std::min<int64_t>(grid, vtotal);
     grid = std::max<int64_t>(grid, 1);
     hipLaunchKernelGGL((k_count_persistent<W>), dim3((unsigned)grid), dim3(kBlock), lds, s,

@@ -349,3 +349,42 @@ def test_rejected_append_changes_nothing_and_graphs_expire():
         with pytest.raises(_lib.FastcountError):
             g.replay()                                        # captured before the append
         g.close()
+
+
+def test_concurrent_host_threads_on_separate_streams():
+    # the ABI allows concurrent calls on one database from several host
+    # threads, each on its own stream; every result equals the serial one
+    import threading
+    w = synth.batched_uneven(m=40_009, nq=600)
+    with Database(w.D, w.arity) as db:
+        parts = [(w.vars_flat[w.var_off[a]:w.var_off[b]], w.var_off[a:b + 1] - w.var_off[a])
+                 for a, b in ((0, 150), (150, 300), (300, 450), (450, 600))]
+        ref = []
+        for flat, off in parts:
+            sc, _, tables, _ = db.count_reduce((flat, off), ("bdeu", "mi"), keep_tables=True)
+            torch.cuda.synchronize()
+            ref.append((sc["bdeu"].cpu(), sc["mi"].cpu(), tables.cpu()))
+        got = [None] * len(parts)
+        errors = []
+
+        def run(i):
+            try:
+                s = torch.cuda.Stream()
+                with torch.cuda.stream(s):
+                    for _ in range(5):
+                        sc, _, tables, _ = db.count_reduce(parts[i], ("bdeu", "mi"),
+                                                           keep_tables=True, stream=s)
+                    s.synchronize()
+                    got[i] = (sc["bdeu"].cpu(), sc["mi"].cpu(), tables.cpu())
+            except Exception as e:      # reported in the main thread
+                errors.append(e)
+
+        th = [threading.Thread(target=run, args=(i,)) for i in range(len(parts))]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        assert not errors, errors
+        for i in range(len(parts)):
+            for a, b in zip(ref[i], got[i]):
+                assert torch.equal(a, b), i
