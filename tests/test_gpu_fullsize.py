@@ -32,6 +32,18 @@ def check_full(w, reducers, nsample):
     sums = np.add.reduceat(T.astype(np.int64), toff[:-1]) if w.nq else []
     assert np.all(sums == w.m)
     assert np.all(T >= 0)
+    # marginalising every table over its child (last) variable reproduces the
+    # table of the remaining variables, counted as queries of their own
+    multi = [i for i in range(w.nq) if w.var_off[i + 1] - w.var_off[i] >= 2]
+    subs = [w.query(i)[:-1] for i in multi]
+    if subs:
+        ST, soff = db.count_batch(subs)
+        ST = ST.cpu().numpy()
+        for j, i in enumerate(multi):
+            q = w.query(i)
+            r = int(w.arity[q[-1]])
+            marg = T[toff[i]:toff[i + 1]].reshape(-1, r).sum(axis=1)
+            assert np.array_equal(marg, ST[soff[j]:soff[j + 1]]), "query %d" % i
     rng = np.random.default_rng(1)
     sample = rng.choice(w.nq, size=min(nsample, w.nq), replace=False)
     # the largest tables are always in the sample
