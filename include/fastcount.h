@@ -225,6 +225,25 @@ int fc_count_reduce(fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
                     const int64_t *table_off, uint32_t flags, void *stream);
 
 /*
+ * Exact parent-set search support (Section 4.2): the scores of every parent
+ * set of `size` variables drawn from cand[0..ncand-1] (distinct, not the
+ * child) for one child, enumerated by the library.  Set i is the i-th
+ * `size`-subset of the positions 0..ncand-1 in lexicographic order; the query
+ * counted for it is the subset's variables (in cand order) followed by the
+ * child.  nsets must equal C(ncand, size), and size + 1 <= FC_MAX_VARS.
+ * scores (device or host) receives, for the j-th set bit of `reducers`,
+ * scores[j*nsets + i], exactly the values fc_count_reduce gives for the same
+ * queries.  prune_mdl > 0 (only with reducers == FC_RED_MDL): a set whose MDL
+ * penalty 1/2 log2(m) q (r-1) alone is >= prune_mdl is not counted and
+ * scores +infinity (its MDL, and every superset's, is at least that bound).
+ * The stream is synchronised when scores is a host pointer.
+ */
+int fc_score_parent_sets(fc_db *db, int32_t child, const int32_t *cand,
+                         int32_t ncand, int32_t size, uint32_t reducers,
+                         const fc_reduce_params *p, double prune_mdl,
+                         float *scores, int64_t nsets, void *stream);
+
+/*
  * All 2-itemset supports of binary items (association rule mining, Section
  * 4.3) from the co-occurrence Gram matrix A^T A of the one-hot instance x item
  * matrix, computed with int8 MFMA and exact int32 accumulation.  items lists

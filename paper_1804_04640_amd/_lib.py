@@ -32,7 +32,8 @@ FC_RED_MI = 8
 
 # every symbol the header declares
 EXPORTS = ("fc_db_create", "fc_db_append", "fc_db_destroy", "fc_db_info", "fc_db_marginals", "fc_table_cells",
-           "fc_count", "fc_count_assignment", "fc_count_assignments", "fc_count_sparse", "fc_count_batch", "fc_count_reduce", "fc_pairs",
+           "fc_count", "fc_count_assignment", "fc_count_assignments", "fc_count_sparse", "fc_count_batch", "fc_count_reduce",
+           "fc_score_parent_sets", "fc_pairs",
            "fc_batch_footprint", "fc_graph_create", "fc_graph_launch", "fc_graph_destroy",
            "fc_db_get_tuning", "fc_db_set_tuning", "fc_autotune",
            "fc_profile_enable", "fc_profile_read", "fc_last_error")
@@ -115,6 +116,8 @@ def load():
             "fc_count_sparse": (ctypes.c_int, [P, P, i32, P, P, i64, P, P]),
             "fc_count_batch": (ctypes.c_int, [P, P, P, i64, P, P, u32, P]),
             "fc_count_reduce": (ctypes.c_int, [P, P, P, i64, u32, P, P, P, P, P, u32, P]),
+            "fc_score_parent_sets": (ctypes.c_int, [P, i32, P, i32, i32, u32, P, ctypes.c_double,
+                                                    P, i64, P]),
             "fc_pairs": (ctypes.c_int, [P, P, i32, ctypes.c_double, P, P, i64, P, P]),
             "fc_batch_footprint": (ctypes.c_int, [P, P, P, i64, u32, P]),
             "fc_graph_create": (ctypes.c_int, [P, P, P, i64, u32, P, P, P, P, P, u32, P, P]),
@@ -205,6 +208,12 @@ def fc_count_reduce(db, vars_flat, var_off, nq, reducers, params, scores, err, t
                     flags, stream):
     return check(load().fc_count_reduce(db, vars_flat, var_off, nq, reducers, params, scores, err,
                                         tables, table_off, flags, stream))
+
+
+def fc_score_parent_sets(db, child, cand, ncand, size, reducers, params, prune_mdl, scores,
+                         nsets, stream):
+    return check(load().fc_score_parent_sets(db, child, cand, ncand, size, reducers, params,
+                                             prune_mdl, scores, nsets, stream))
 
 
 def fc_pairs(db, items, ni, minsup, gram, out, cap, stream):

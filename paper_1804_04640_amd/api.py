@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import ctypes
 import hashlib
+import math
 import json
 import os
 from typing import Dict, Iterable, Optional, Sequence
@@ -246,6 +247,27 @@ class Database:
         sc = {r: scores[i * nq:(i + 1) * nq] for i, r in enumerate(names)}
         er = {r: err[i * nq:(i + 1) * nq] for i, r in enumerate(names)} if err is not None else None
         return sc, er, tables, toff
+
+    def score_parent_sets(self, child: int, cand, size: int, reducers: Sequence[str] = ("mdl",),
+                          ess: float = 1.0, prune_mdl: float = 0.0, stream=None):
+        """Scores of every `size`-subset of `cand` as the parent set of
+        `child` (lexicographic order of positions in `cand`), enumerated by
+        the library: {name: tensor[C(len(cand), size)]}.  prune_mdl > 0 (MDL
+        only): sets whose penalty alone reaches it score +inf, uncounted."""
+        c = np.ascontiguousarray(np.asarray(cand, dtype=np.int32).ravel())
+        names = [r for r in ("ll", "mdl", "bdeu", "mi") if r in reducers]
+        if len(names) != len(set(reducers)):
+            raise ValueError("unknown reducer in %r" % (reducers,))
+        mask = 0
+        for r in names:
+            mask |= REDUCER_BITS[r]
+        nsets = math.comb(len(c), size) if 0 <= size <= len(c) else 0
+        scores = self._empty(len(names) * max(nsets, 1), torch.float32)
+        params = L.fc_reduce_params(float(ess))
+        L.fc_score_parent_sets(self.handle, int(child), _np_ptr(c), len(c), int(size), mask,
+                               ctypes.addressof(params), float(prune_mdl), scores.data_ptr(),
+                               nsets, _stream(stream))
+        return {r: scores[i * nsets:(i + 1) * nsets] for i, r in enumerate(names)}
 
     def graph(self, queries, reducers: Sequence[str] = ("mdl",), ess: float = 1.0,
               keep_tables: bool = False, strategy: str = "auto", stream=None) -> "BatchGraph":

@@ -1456,9 +1456,26 @@ static void make_image(const fc_db *db, const Plan &P, uint32_t reducers, Image 
     I.bytes = b;
 }
 
+// memcpy split over host threads for large plans (pinned destination).
+static void parallel_copy(void *dst, const void *src, size_t bytes) {
+    const size_t kPiece = size_t(4) << 20;
+    unsigned hw = std::thread::hardware_concurrency();
+    const size_t T = std::min<size_t>(std::min(16u, hw ? hw : 1u), bytes / kPiece);
+    if (T <= 1) {
+        std::memcpy(dst, src, bytes);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (size_t t = 0; t < T; ++t) {
+        const size_t lo = bytes * t / T, hi = bytes * (t + 1) / T;
+        th.emplace_back([=] { std::memcpy((char *)dst + lo, (const char *)src + lo, hi - lo); });
+    }
+    for (auto &x : th) x.join();
+}
+
 static void fill_image(const Plan &P, const Image &I, void *host) {
     char *h = (char *)host;
-    std::memcpy(h, P.work.data(), sizeof(QDesc) * P.work.size());
+    parallel_copy(h, P.work.data(), sizeof(QDesc) * P.work.size());
     if (I.with_query) std::memcpy(h + I.off_query, P.query.data(), sizeof(QDesc) * P.query.size());
     std::memcpy(h + I.off_groups, I.groups.data(), sizeof(PGroup) * I.groups.size());
     std::memset(h + I.off_heads, 0, 64);
@@ -1540,6 +1557,19 @@ static int run_batch(fc_db *db, Plan &P, int32_t *tables, uint32_t reducers, dou
         return FC_ERR_DEVICE;
     }
     return enqueue_batch(db, P, I, dimg.p, tables, reducers, ess, scores, err, s);
+}
+
+// Counts and reduces a validated-on-entry batch into device score buffers
+// ([slot][nq], slot = set bits of `reducers` in ascending order); the tables
+// live in stream-ordered scratch.  Used by the native drivers.
+int count_reduce_device(fc_db *db, const int32_t *vars_flat, const int64_t *var_off, int64_t nq,
+                        uint32_t reducers, double ess, float *scores, hipStream_t s) {
+    Plan P;
+    int rc = build_plan(db, vars_flat, var_off, nq, nullptr, FC_STRAT_AUTO, true, P);
+    if (rc || nq == 0) return rc;
+    DevBuf dt;
+    FC_HIP(dt.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(P.total_cells, 1), s));
+    return run_batch(db, P, (int32_t *)dt.p, reducers, ess, scores, nullptr, s);
 }
 
 }  // namespace fc

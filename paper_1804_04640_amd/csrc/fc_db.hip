@@ -59,25 +59,29 @@ static std::mutex g_stage_mu;
 static std::vector<Staging *> g_stage_free;
 
 static size_t g_stage_count = 0;
-constexpr size_t kStageMax = 8;
+constexpr size_t kStageMax = 12;
 
 Staging *staging_acquire(size_t bytes) {
-    // Prefer a free buffer whose last copy has completed and that is large
-    // enough, then any completed one, then a new buffer (up to kStageMax), and
-    // only then wait for the oldest: the host can plan ahead of the device.
+    // Prefer the smallest free buffer whose last copy has completed and that
+    // is large enough, then a new buffer (up to kStageMax), then the largest
+    // completed one, which must grow (pinning memory is slow: buffers are
+    // resized only when the pool is full, and small requests never take the
+    // large buffers), and only then wait for the oldest: the host can plan
+    // ahead of the device.
     Staging *st = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_stage_mu);
-        int pick = -1;
-        for (int pass = 0; pass < 2 && pick < 0; ++pass)
-            for (size_t i = 0; i < g_stage_free.size(); ++i) {
-                Staging *c = g_stage_free[i];
-                const bool idle = !c->done || hipEventQuery(c->done) == hipSuccess;
-                if (idle && (pass == 1 || c->cap >= bytes)) {
-                    pick = (int)i;
-                    break;
-                }
-            }
+        int fit = -1, largest = -1;
+        for (size_t i = 0; i < g_stage_free.size(); ++i) {
+            Staging *c = g_stage_free[i];
+            const bool idle = !c->done || hipEventQuery(c->done) == hipSuccess;
+            if (!idle) continue;
+            if (c->cap >= bytes && (fit < 0 || c->cap < g_stage_free[(size_t)fit]->cap))
+                fit = (int)i;
+            if (largest < 0 || c->cap > g_stage_free[(size_t)largest]->cap) largest = (int)i;
+        }
+        int pick = fit;
+        if (pick < 0 && g_stage_count >= kStageMax) pick = largest;
         if (pick < 0 && g_stage_count >= kStageMax && !g_stage_free.empty()) pick = 0;
         if (pick >= 0) {
             st = g_stage_free[(size_t)pick];
@@ -288,6 +292,18 @@ extern "C" int fc_db_create(const uint8_t *data, int64_t m, int32_t n, const uin
     DbGuard guard{db};
     FC_HIP(hipGetDevice(&db->device));
     FC_HIP(hipDeviceGetAttribute(&db->cu_count, hipDeviceAttributeMultiprocessorCount, db->device));
+    {
+        // Per-call scratch (tables, plans) comes from the device's default
+        // stream-ordered pool; keep freed blocks cached in it instead of
+        // returning them at every synchronisation, so that steady batches
+        // reuse memory instead of mapping it anew.
+        hipMemPool_t pool = nullptr;
+        if (hipDeviceGetDefaultMemPool(&pool, db->device) == hipSuccess && pool) {
+            uint64_t keep = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        }
+        (void)hipGetLastError();
+    }
     db->m = m;
     db->n = n;
     db->m_pad = ((m + kTileRows - 1) / kTileRows) * kTileRows;

@@ -131,6 +131,11 @@ struct ProfScope {
     void end(hipStream_t s);
 };
 
+// Counts and reduces a batch (validated inside) into device scores
+// [slot * nq + i], tables in stream-ordered scratch (fc_count.hip).
+int count_reduce_device(fc_db *db, const int32_t *vars_flat, const int64_t *var_off, int64_t nq,
+                        uint32_t reducers, double ess, float *scores, hipStream_t s);
+
 // Reducer launch (fc_reduce.hip).  descs: exactly one QDesc per query
 // (device, any order); scores[slot * nq + qid].
 hipError_t launch_reduce(const fc_db *db, const QDesc *descs, int64_t nd, int64_t nq,

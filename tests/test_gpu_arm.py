@@ -1,6 +1,7 @@
 """GPU association-rule mining and batched single-assignment counts."""
 import numpy as np
 import pytest
+import torch
 
 from oracle import oracle as orc
 from paper_1804_04640_amd import arm, synth
@@ -104,3 +105,45 @@ def test_parent_set_assignment_is_exact(score):
         assert abs(got_s - ref[tuple(sorted(got_pa))]) <= 1e-6 * abs(opt) + 1e-9
     if score == "mdl":
         assert stats["scored"] + stats["pruned"] == n * (1 + 6 + 15 + 20)
+
+
+def test_score_parent_sets_matches_explicit_families():
+    import ctypes
+    import itertools
+    import math
+    from paper_1804_04640_amd import _lib
+    w = synth.bn_family(m=30_011, nq=1)
+    D, ar = w.D[:9].copy(), w.arity[:9].copy()
+    child, cand = 4, np.array([7, 0, 2, 8, 1, 5], np.int32)
+    with Database(D, ar) as db:
+        for size in (0, 1, 3, 6):
+            sets = [list(cand[list(p)]) for p in itertools.combinations(range(len(cand)), size)]
+            ref, _, _, _ = db.count_reduce([s + [child] for s in sets], ("mdl", "bdeu"))
+            got = db.score_parent_sets(child, cand, size, ("mdl", "bdeu"))
+            for name in ("mdl", "bdeu"):
+                assert torch.equal(got[name], ref[name]), (size, name)
+            # pruning: +inf exactly where the penalty alone reaches the bound
+            mdl = ref["mdl"].cpu().numpy()
+            bound = float(np.median(mdl)) if size else float(mdl[0]) + 1.0
+            pruned = db.score_parent_sets(child, cand, size, ("mdl",), prune_mdl=bound)["mdl"]
+            pruned = pruned.cpu().numpy()
+            lg = 0.5 * math.log2(D.shape[1]) * (int(ar[child]) - 1)
+            for i, s in enumerate(sets):
+                pen = lg * float(np.prod(ar[s].astype(np.float64))) if s else lg
+                if pen < bound:
+                    assert pruned[i] == mdl[i], (size, i)
+                else:
+                    assert np.isinf(pruned[i]) and pruned[i] > 0, (size, i)
+        # host output buffer, and argument errors
+        out = np.empty(math.comb(len(cand), 2), np.float32)
+        params = _lib.fc_reduce_params(1.0)
+        _lib.fc_score_parent_sets(db.handle, child, cand.ctypes.data, len(cand), 2,
+                                  _lib.FC_RED_MDL, ctypes.addressof(params), 0.0,
+                                  out.ctypes.data, len(out), 0)
+        sets = [list(cand[list(p)]) + [child] for p in itertools.combinations(range(len(cand)), 2)]
+        np.testing.assert_array_equal(out, db.count_reduce(sets, ("mdl",))[0]["mdl"].cpu().numpy())
+        for bad_cand in (np.array([1, 1], np.int32), np.array([child, 2], np.int32)):
+            with pytest.raises(_lib.FastcountError):
+                db.score_parent_sets(child, bad_cand, 1, ("mdl",))
+        with pytest.raises(_lib.FastcountError):
+            db.score_parent_sets(child, cand, 2, ("mdl", "bdeu"), prune_mdl=10.0)
