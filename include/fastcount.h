@@ -183,6 +183,26 @@ int fc_count_sparse(fc_db *db, const int32_t *vars, int32_t k, int64_t *keys,
                     int32_t *counts, int64_t cap, int64_t *nnz, void *stream);
 
 /*
+ * Sparse tables of many queries in one submission (the sparse form of
+ * Section 3.2 for a batch, as fc_count_batch is for dense tables).  Query i
+ * is vars_flat[var_off[i] .. var_off[i+1]) (1..FC_MAX_VARS distinct
+ * variables, key space below 2^63); var_off holds nq+1 int64 values starting
+ * at 0.  The pairs of all queries are packed in query order: query i's
+ * (key, count) pairs, keys increasing, occupy [out_off[i], out_off[i+1]) of
+ * keys (int64) and counts (int32); out_off is host memory of nq+1 entries,
+ * *total_nnz = out_off[nq].  keys and counts are both device or both host
+ * memory and hold `cap` entries (total_nnz <= nq * m always).  When the
+ * total exceeds cap the call returns FC_ERR_RANGE with out_off and
+ * *total_nnz set and keys/counts unspecified, so the caller can size and
+ * call again.  Consecutive queries share one radix sort of
+ * (query, key) composite keys (at most 2^26 keys per sort).  Synchronises
+ * `stream`.
+ */
+int fc_count_sparse_batch(fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
+                          int64_t nq, int64_t *keys, int32_t *counts, int64_t cap,
+                          int64_t *out_off, int64_t *total_nnz, void *stream);
+
+/*
  * Many single-assignment counts in one submission (the queries of the
  * association-rule search of Section 4.3, each a path of |Pa|+1 bitmap
  * intersections and a popcount).  Query i assigns states_flat[var_off[i] ..

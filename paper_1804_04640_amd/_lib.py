@@ -32,7 +32,7 @@ FC_RED_MI = 8
 
 # every symbol the header declares
 EXPORTS = ("fc_db_create", "fc_db_append", "fc_db_destroy", "fc_db_info", "fc_db_marginals", "fc_table_cells",
-           "fc_count", "fc_count_assignment", "fc_count_assignments", "fc_count_sparse", "fc_count_batch", "fc_count_reduce",
+           "fc_count", "fc_count_assignment", "fc_count_assignments", "fc_count_sparse", "fc_count_sparse_batch", "fc_count_batch", "fc_count_reduce",
            "fc_score_parent_sets", "fc_pairs",
            "fc_batch_footprint", "fc_graph_create", "fc_graph_launch", "fc_graph_destroy",
            "fc_db_get_tuning", "fc_db_set_tuning", "fc_autotune",
@@ -114,6 +114,7 @@ def load():
             "fc_count_assignment": (ctypes.c_int, [P, P, P, i32, P, P]),
             "fc_count_assignments": (ctypes.c_int, [P, P, P, P, i64, P, P]),
             "fc_count_sparse": (ctypes.c_int, [P, P, i32, P, P, i64, P, P]),
+            "fc_count_sparse_batch": (ctypes.c_int, [P, P, P, i64, P, P, i64, P, P, P]),
             "fc_count_batch": (ctypes.c_int, [P, P, P, i64, P, P, u32, P]),
             "fc_count_reduce": (ctypes.c_int, [P, P, P, i64, u32, P, P, P, P, P, u32, P]),
             "fc_score_parent_sets": (ctypes.c_int, [P, i32, P, i32, i32, u32, P, ctypes.c_double,
@@ -197,6 +198,18 @@ def fc_count_sparse(db, vars_, k, keys, counts, cap, stream):
     nnz = ctypes.c_int64()
     check(load().fc_count_sparse(db, vars_, k, keys, counts, cap, ctypes.byref(nnz), stream))
     return nnz.value
+
+
+def fc_count_sparse_batch(db, vars_flat, var_off, nq, keys, counts, cap, out_off, stream):
+    """Returns (rc, total_nnz): rc is FC_OK or FC_ERR_RANGE (the total does not
+    fit cap; out_off is filled); other errors raise."""
+    total = ctypes.c_int64()
+    rc = load().fc_count_sparse_batch(db, vars_flat, var_off, nq, keys, counts, cap, out_off,
+                                      ctypes.byref(total), stream)
+    if rc == FC_ERR_RANGE and total.value > cap:
+        return rc, total.value
+    check(rc)
+    return rc, total.value
 
 
 def fc_count_batch(db, vars_flat, var_off, nq, tables, table_off, flags, stream):

@@ -158,10 +158,25 @@ class Database:
         s = np.ascontiguousarray(states, np.uint8)
         return L.fc_count_assignment(self.handle, _np_ptr(v), _np_ptr(s), len(v), _stream(stream))
 
-    def count_sparse(self, vars_, cap: Optional[int] = None, stream=None):
+    def count_sparse(self, vars_, cap: Optional[int] = None, stream=None,
+                     keys_out: Optional[torch.Tensor] = None,
+                     counts_out: Optional[torch.Tensor] = None):
         """(keys int64, counts int32) of the configurations that occur, in
-        increasing mixed-radix key order (host numpy arrays)."""
+        increasing mixed-radix key order: host numpy arrays, or views of
+        keys_out / counts_out (int64 / int32 device tensors of equal length,
+        which then set cap) when both are given."""
         v = np.ascontiguousarray(vars_, np.int32)
+        if keys_out is not None or counts_out is not None:
+            if keys_out is None or counts_out is None or keys_out.dtype != torch.int64 \
+                    or counts_out.dtype != torch.int32 or keys_out.numel() != counts_out.numel():
+                raise ValueError("keys_out (int64) and counts_out (int32) of equal length are "
+                                 "needed together")
+            cap = keys_out.numel()
+            nnz = L.fc_count_sparse(self.handle, _np_ptr(v), len(v),
+                                    keys_out.data_ptr() if cap else 0,
+                                    counts_out.data_ptr() if cap else 0, cap, _stream(stream))
+            n = min(nnz, cap)
+            return keys_out[:n], counts_out[:n], nnz
         cap = self.m if cap is None else int(cap)
         keys = np.zeros(max(cap, 1), np.int64)
         cnt = np.zeros(max(cap, 1), np.int32)
@@ -169,6 +184,35 @@ class Database:
                                 _stream(stream))
         n = min(nnz, cap)
         return keys[:n], cnt[:n], nnz
+
+    def count_sparse_batch(self, queries, stream=None, keys_out: Optional[torch.Tensor] = None,
+                           counts_out: Optional[torch.Tensor] = None):
+        """Sparse tables of many queries: (keys int64, counts int32, out_off
+        int64 numpy [nq+1]); query i's pairs are keys[out_off[i]:out_off[i+1]].
+        Outputs are device tensors: keys_out / counts_out when given (their
+        length is the capacity; a batch that does not fit raises), else new
+        ones of the nq * m upper bound."""
+        flat, off = flatten_queries(queries)
+        nq = len(off) - 1
+        if keys_out is None or counts_out is None:
+            if keys_out is not None or counts_out is not None:
+                raise ValueError("keys_out and counts_out are needed together")
+            cap = nq * self.m
+            keys_out = self._empty(max(cap, 1), torch.int64)
+            counts_out = self._empty(max(cap, 1), torch.int32)
+        elif keys_out.dtype != torch.int64 or counts_out.dtype != torch.int32 \
+                or keys_out.numel() != counts_out.numel():
+            raise ValueError("keys_out (int64) and counts_out (int32) of equal length are needed")
+        cap = keys_out.numel() if nq else 0
+        out_off = np.zeros(nq + 1, np.int64)
+        rc, total = L.fc_count_sparse_batch(self.handle, _np_ptr(flat), _np_ptr(off), nq,
+                                            keys_out.data_ptr() if cap else 0,
+                                            counts_out.data_ptr() if cap else 0, cap,
+                                            _np_ptr(out_off), _stream(stream))
+        if rc != L.FC_OK:
+            raise L.FastcountError(rc, "%d configurations do not fit the %d-entry outputs"
+                                   % (total, cap))
+        return keys_out[:total], counts_out[:total], out_off
 
     def count_assignments(self, queries, states, stream=None) -> np.ndarray:
         """Batched single-assignment counts; `states` mirrors `queries`

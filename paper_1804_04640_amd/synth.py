@@ -110,10 +110,22 @@ def forward_sample(rng, arity, order, parents, m, alpha, chunk=1 << 20) -> np.nd
             for p in pa:
                 idx = idx * int(arity[p]) + D[p, lo:hi]
             u = rng.random(hi - lo)
-            s = np.zeros(hi - lo, dtype=np.uint8)
-            rows = cdf[idx]
-            for k in range(r - 1):
-                s += (u >= rows[:, k]).astype(np.uint8)
+            if r <= 8:
+                s = np.zeros(hi - lo, dtype=np.uint8)
+                rows = cdf[idx]
+                for k in range(r - 1):
+                    s += (u >= rows[:, k]).astype(np.uint8)
+            else:
+                # the same count #{k < r-1 : cdf[k] <= u}, per parent
+                # configuration: a CDF row is nondecreasing, so the count is
+                # a right-sided binary search
+                s = np.empty(hi - lo, dtype=np.uint8)
+                order_ = np.argsort(idx, kind="stable")
+                keys, starts = np.unique(idx[order_], return_index=True)
+                ends = np.append(starts[1:], len(order_))
+                for key, a, b in zip(keys, starts, ends):
+                    sel = order_[a:b]
+                    s[sel] = np.searchsorted(cdf[key, :r - 1], u[sel], side="right")
             D[v, lo:hi] = s
     return D
 
@@ -300,6 +312,29 @@ def serving(m=1 << 22, nbatches=64) -> Workload:
     return Workload("serving", D, arity, flat, off, ("mdl",), batches=ids,
                     desc="n=64 r~U{2..5} m=%d DAG(indeg<=4, Dir(1)); %d hill-climbing batches"
                     % (m, nbatches))
+
+
+def high_arity(m=1_000_000, nq=64) -> Workload:
+    """Key spaces far beyond the data (the sparse-table path): n=30 with
+    Mildew-like arities (half in 2..8, half in 9..99), a random DAG
+    (in-degree <= 2, Dirichlet(0.5)); queries of 5..8 variables whose tables
+    have more than 2^24 cells."""
+    rng = rng_for(6)
+    n = 30
+    arity = np.where(rng.random(n) < 0.5, rng.integers(2, 9, size=n),
+                     rng.integers(9, 100, size=n)).astype(np.uint8)
+    order, parents = random_dag(rng, n, 2)
+    D = forward_sample(rng, arity, order, parents, m, 0.5)
+    qs = []
+    while len(qs) < nq:
+        k = int(rng.integers(5, 9))
+        q = rng.choice(n, size=k, replace=False).astype(np.int32)
+        if float(np.prod(arity[q].astype(np.float64))) > float(1 << 24):
+            qs.append(q)
+    flat, off = flatten(qs)
+    return Workload("high-arity", D, arity, flat, off, (),
+                    desc="n=30 arities half U{2..8} half U{9..99}, m=%d DAG(indeg<=2, Dir(0.5)); "
+                         "%d queries k~U{5..8} with more than 2^24 cells" % (m, nq))
 
 
 WORKLOADS = {"plain-small": plain_small, "bn-family": bn_family,

@@ -147,3 +147,109 @@ def test_score_parent_sets_matches_explicit_families():
                 db.score_parent_sets(child, bad_cand, 1, ("mdl",))
         with pytest.raises(_lib.FastcountError):
             db.score_parent_sets(child, cand, 2, ("mdl", "bdeu"), prune_mdl=10.0)
+
+
+def test_sparse_tables_high_arity_full_size_device_outputs():
+    """The high-arity workload at its full size (m = 1,000,000, tables of more
+    than 2^24 cells): device-resident outputs equal the oracle's pairs, and a
+    cap below the number of configurations keeps the smallest keys."""
+    w = synth.high_arity()
+    keys = torch.empty(w.m, dtype=torch.int64, device="cuda")
+    cnts = torch.empty(w.m, dtype=torch.int32, device="cuda")
+    with Database(w.D, w.arity, bitvectors=False) as db:
+        for i in (0, 1, 17, 63):
+            q = w.query(i)
+            k, c, nnz = db.count_sparse(q, keys_out=keys, counts_out=cnts)
+            rk, rc = orc.count_sparse(w.D, w.arity, q)
+            assert nnz == len(rk) and k.is_cuda
+            np.testing.assert_array_equal(k.cpu().numpy(), rk)
+            np.testing.assert_array_equal(c.cpu().numpy(), rc)
+        small_k, small_c = keys[:1000], cnts[:1000]
+        k, c, nnz = db.count_sparse(w.query(0), keys_out=small_k, counts_out=small_c)
+        rk, rc = orc.count_sparse(w.D, w.arity, w.query(0))
+        assert nnz == len(rk) and len(k) == 1000
+        np.testing.assert_array_equal(k.cpu().numpy(), rk[:1000])
+        np.testing.assert_array_equal(c.cpu().numpy(), rc[:1000])
+
+
+def test_sparse_batch_high_arity_full_size():
+    """All 64 high-arity queries in one batched call (one composite-key sort
+    per group) equal the oracle's sparse tables query by query."""
+    w = synth.high_arity()
+    with Database(w.D, w.arity, bitvectors=False) as db:
+        keys, cnts, off = db.count_sparse_batch((w.vars_flat, w.var_off))
+        keys, cnts = keys.cpu().numpy(), cnts.cpu().numpy()
+    assert off[0] == 0 and off[-1] == len(keys)
+    for i in range(w.nq):
+        rk, rc = orc.count_sparse(w.D, w.arity, w.query(i))
+        np.testing.assert_array_equal(keys[off[i]:off[i + 1]], rk)
+        np.testing.assert_array_equal(cnts[off[i]:off[i + 1]], rc)
+
+
+def _mixed_sparse_batch():
+    rng = synth.rng_for(78)
+    n, m = 20, 3001
+    ar = rng.integers(2, 100, size=n).astype(np.uint8)
+    ar[:3] = 1                                   # single-state variables: key space 1
+    D = np.stack([rng.integers(0, a, size=m) for a in ar]).astype(np.uint8)
+    qs = [[0], [1, 2], [5], [7, 3]]              # tiny key spaces (32-bit groups)
+    for _ in range(300):
+        k = int(rng.integers(1, 9))
+        qs.append(rng.choice(n, size=k, replace=False).astype(np.int32))
+    big = np.argsort(ar)[-8:][::-1]              # the 8 largest arities: > 2^48 keys
+    qs += [big, big[::-1], [big[0]]]
+    return D, ar, qs
+
+
+def test_sparse_batch_mixed_groups_and_host_outputs():
+    """Key spaces from 1 to beyond 2^48 in one batch (several groups, 32- and
+    64-bit composite keys, groups split by the 64-bit budget), checked
+    against the oracle; host-memory outputs give the same pairs."""
+    from paper_1804_04640_amd import _lib as L
+    from paper_1804_04640_amd.api import flatten_queries
+    D, ar, qs = _mixed_sparse_batch()
+    with Database(D, ar, bitvectors=False) as db:
+        keys, cnts, off = db.count_sparse_batch(qs)
+        keys, cnts = keys.cpu().numpy(), cnts.cpu().numpy()
+        for i, q in enumerate(qs):
+            rk, rc = orc.count_sparse(D, ar, q)
+            np.testing.assert_array_equal(keys[off[i]:off[i + 1]], rk)
+            np.testing.assert_array_equal(cnts[off[i]:off[i + 1]], rc)
+        flat, voff = flatten_queries(qs)
+        total = int(off[-1])
+        hk = np.zeros(total, np.int64)
+        hc = np.zeros(total, np.int32)
+        hoff = np.zeros(len(qs) + 1, np.int64)
+        rc, t2 = L.fc_count_sparse_batch(db.handle, flat.ctypes.data, voff.ctypes.data, len(qs),
+                                         hk.ctypes.data, hc.ctypes.data, total, hoff.ctypes.data,
+                                         torch.cuda.current_stream().cuda_stream)
+        assert rc == L.FC_OK and t2 == total
+        np.testing.assert_array_equal(hoff, off)
+        np.testing.assert_array_equal(hk, keys)
+        np.testing.assert_array_equal(hc, cnts)
+
+
+def test_sparse_batch_capacity_and_errors():
+    from paper_1804_04640_amd import _lib as L
+    from paper_1804_04640_amd.api import flatten_queries
+    D, ar, qs = _mixed_sparse_batch()
+    with Database(D, ar, bitvectors=False) as db:
+        _, _, off = db.count_sparse_batch(qs)
+        total = int(off[-1])
+        small_k = torch.empty(total - 1, dtype=torch.int64, device="cuda")
+        small_c = torch.empty(total - 1, dtype=torch.int32, device="cuda")
+        flat, voff = flatten_queries(qs)
+        hoff = np.zeros(len(qs) + 1, np.int64)
+        rc, t2 = L.fc_count_sparse_batch(db.handle, flat.ctypes.data, voff.ctypes.data, len(qs),
+                                         small_k.data_ptr(), small_c.data_ptr(), total - 1,
+                                         hoff.ctypes.data, torch.cuda.current_stream().cuda_stream)
+        assert rc == L.FC_ERR_RANGE and t2 == total
+        np.testing.assert_array_equal(hoff, off)          # sizes come back for a retry
+        with pytest.raises(L.FastcountError):
+            db.count_sparse_batch(qs, keys_out=small_k, counts_out=small_c)
+        k, c, o = db.count_sparse_batch([])
+        assert len(k) == 0 and list(o) == [0]
+        with pytest.raises(L.FastcountError):
+            db.count_sparse_batch([[1, 4, 1]])             # a repeated variable
+        with pytest.raises(L.FastcountError):
+            db.count_sparse_batch([list(range(9))])        # more than 8 variables
