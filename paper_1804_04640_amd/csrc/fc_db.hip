@@ -121,6 +121,70 @@ void staging_release(Staging *st, hipStream_t s) {
     g_stage_free.push_back(st);
 }
 
+// ------------------------------------------------------- device workspaces
+constexpr size_t kWorkspaceMax = 4;
+
+Workspace *workspace_acquire(fc_db *db, size_t bytes, hipStream_t s) {
+    // The smallest idle workspace that is large enough, else a new one (up to
+    // kWorkspaceMax), else the largest idle one grown, else a new one beyond
+    // the limit (calls never wait for each other on the host).
+    Workspace *w = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(db->ws_mu);
+        int fit = -1, largest = -1;
+        for (size_t i = 0; i < db->ws_free.size(); ++i) {
+            const Workspace *c = db->ws_free[i];
+            if (c->cap >= bytes && (fit < 0 || c->cap < db->ws_free[(size_t)fit]->cap))
+                fit = (int)i;
+            if (largest < 0 || c->cap > db->ws_free[(size_t)largest]->cap) largest = (int)i;
+        }
+        int pick = fit;
+        if (pick < 0 && db->ws_count >= kWorkspaceMax) pick = largest;
+        if (pick >= 0) {
+            w = db->ws_free[(size_t)pick];
+            db->ws_free.erase(db->ws_free.begin() + pick);
+        } else {
+            ++db->ws_count;
+        }
+    }
+    if (!w) w = new (std::nothrow) Workspace();
+    if (!w) return nullptr;
+    if (w->cap < bytes) {
+        if (w->p) {
+            if (w->done) (void)hipEventSynchronize(w->done);
+            (void)hipFree(w->p);
+            db->device_bytes -= (int64_t)w->cap;
+            w->p = nullptr;
+            w->cap = 0;
+        }
+        const size_t cap = bytes + bytes / 8;
+        if (hipMalloc(&w->p, cap) != hipSuccess) {
+            (void)hipGetLastError();
+            w->p = nullptr;
+            if (w->done) (void)hipEventDestroy(w->done);
+            delete w;
+            std::lock_guard<std::mutex> lk(db->ws_mu);
+            --db->ws_count;
+            return nullptr;
+        }
+        w->cap = cap;
+        db->device_bytes += (int64_t)cap;
+    }
+    if (!w->done && hipEventCreateWithFlags(&w->done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        w->done = nullptr;
+    }
+    if (w->done) (void)hipStreamWaitEvent(s, w->done, 0);
+    return w;
+}
+
+void workspace_release(fc_db *db, Workspace *w, hipStream_t s) {
+    if (!w) return;
+    if (w->done) (void)hipEventRecord(w->done, s);
+    std::lock_guard<std::mutex> lk(db->ws_mu);
+    db->ws_free.push_back(w);
+}
+
 // ------------------------------------------------------------ kernels
 // Row-major [m][n] -> column-major [n][m_pad] through an LDS tile.
 __global__ void k_transpose(const uint8_t *__restrict__ rm, int64_t m, int32_t n,
@@ -232,6 +296,11 @@ extern "C" void fc_db_destroy(fc_db *db) {
     if (db->d_arity) (void)hipFree(db->d_arity);
     if (db->d_soff) (void)hipFree(db->d_soff);
     if (db->d_marg) (void)hipFree(db->d_marg);
+    for (Workspace *w : db->ws_free) {
+        if (w->p) (void)hipFree(w->p);
+        if (w->done) (void)hipEventDestroy(w->done);
+        delete w;
+    }
     (void)hipSetDevice(cur);
     delete db;
 }

@@ -55,6 +55,15 @@ struct Tuning {
     }
 };
 
+// Device workspace kept by a database handle between calls (large sort
+// scratch whose allocation and release cost more host time than the work):
+// handed from call to call in stream order through `done`.
+struct Workspace {
+    void *p = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;  // last use of the memory, on its caller's stream
+};
+
 }  // namespace fc
 
 struct fc_db {
@@ -75,6 +84,9 @@ struct fc_db {
     int64_t device_bytes = 0;
     uint64_t epoch = 0;              // bumped by every append
     fc::Tuning tune;
+    std::mutex ws_mu;                       // guards the workspace list
+    std::vector<fc::Workspace *> ws_free;   // idle workspaces
+    size_t ws_count = 0;                    // workspaces in existence
 };
 
 namespace fc {
@@ -121,6 +133,12 @@ struct Staging {
 };
 Staging *staging_acquire(size_t bytes);
 void staging_release(Staging *st, hipStream_t s);
+
+// A workspace of at least `bytes` for work enqueued on `s` (which is made to
+// wait for the workspace's previous user); nullptr when device memory is
+// exhausted.  Released with workspace_release after the last enqueue.
+Workspace *workspace_acquire(fc_db *db, size_t bytes, hipStream_t s);
+void workspace_release(fc_db *db, Workspace *w, hipStream_t s);
 
 // Launch profiling: RAII bracket of one launch with events on its stream.
 bool profiling_on();
