@@ -95,3 +95,43 @@ def test_all_pairs_full():
     got = [(int(r["a"]), int(r["b"]), int(r["n_ab"])) for r in recs]
     assert got == [e[:3] for e in exp]
     print("pairs above minsup: %d" % total, flush=True)
+
+
+def test_maximum_instances():
+    """m = 2^31 - 1, the largest database int32 counts allow (the padded
+    extent is exactly 2^31 rows).  The data repeats a random block of
+    P = 2^20 + 7 instances, so every expected table is reps * T(block) +
+    T(first rem instances of the block), both counted by the oracle."""
+    m = (1 << 31) - 1
+    P = (1 << 20) + 7
+    reps, rem = divmod(m, P)
+    rng = synth.rng_for(91)
+    ar = np.array([2, 3, 16], np.uint8)
+    block = np.stack([rng.integers(0, a, size=P) for a in ar]).astype(np.uint8)
+    print("maximum-size database: m=%d, n=3, period %d" % (m, P), flush=True)
+    D = np.empty((3, m), np.uint8)
+    for v in range(3):
+        D[v, :reps * P] = np.tile(block[v], reps)
+        D[v, reps * P:] = block[v, :rem]
+
+    def expect(q):
+        return reps * orc.count(block, ar, q).astype(np.int64) + \
+            orc.count(np.ascontiguousarray(block[:, :rem]), ar, q).astype(np.int64)
+
+    queries = [[0, 1], [1, 0], [2, 1], [0, 1, 2], [2, 0, 1], [2]]
+    with Database(D, ar) as db:
+        del D
+        for strategy in ("auto", "bitmap", "hist", "partition"):
+            tables, off = db.count_batch(queries, strategy=strategy)
+            T = tables.cpu().numpy()
+            for i, q in enumerate(queries):
+                np.testing.assert_array_equal(T[off[i]:off[i + 1]], expect(q), err_msg=strategy)
+        sc, _, _, _ = db.count_reduce(queries, ("ll",))
+        assert np.all(np.isfinite(sc["ll"].cpu().numpy()))
+        assert db.count_assignment([2, 1], [5, 2]) == int(expect([2, 1])[5 * 3 + 2])
+        keys, cnt, nnz = db.count_sparse([2, 1, 0], cap=4096)
+        ref = expect([2, 1, 0])
+        nz = np.nonzero(ref)[0]
+        assert nnz == len(nz)
+        np.testing.assert_array_equal(keys, nz)
+        np.testing.assert_array_equal(cnt, ref[nz])
