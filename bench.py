@@ -35,9 +35,15 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA
 
 
-def src_hash() -> str:
+def src_hash(files=None) -> str:
+    """Hash of the kernel sources a counter figure depends on: the listed
+    files of the library's csrc/ (the kernel's own file and the shared
+    header), or all of them."""
+    csrc = os.path.join(ROOT, "paper_1804_04640_amd", "csrc")
+    paths = ([os.path.join(csrc, f) for f in sorted(files)] if files
+             else sorted(glob.glob(os.path.join(csrc, "*"))))
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1804_04640_amd", "csrc", "*"))):
+    for p in paths:
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -46,12 +52,12 @@ def src_hash() -> str:
 def counter_traffic(workload_name: str, kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
-    summary was taken on other kernel sources."""
+    kernel's sources changed after the counters were taken."""
     tfile = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(tfile) as f:
             ent = json.load(f).get(workload_name, {}).get(kernel)
-        if ent and ent.get("src_hash") == src_hash():
+        if ent and ent.get("src_hash") == src_hash(ent.get("src_files")):
             return ent["bytes_per_launch"]
     except (OSError, ValueError):
         pass
