@@ -72,7 +72,7 @@ __device__ __forceinline__ uint32_t byte_of(const uint4 &v, int i) {
 // LDS histogram count of one descriptor over one row chunk.
 // SMALL: every stride is below 2^24, so 24-bit multiplies suffice.
 template <int K, bool SMALL>
-__device__ __forceinline__ void hist_body(const uint8_t *__restrict__ cols, int64_t m_pad,
+__device__ __forceinline__ void hist_body(const uint8_t *__restrict__ cols, int64_t pitch,
                                           const uint8_t *__restrict__ arity, const QDesc &q,
                                           int32_t c, int32_t chunks, int32_t lds_words,
                                           int32_t pad_rows, int32_t *__restrict__ tables,
@@ -89,7 +89,7 @@ __device__ __forceinline__ void hist_body(const uint8_t *__restrict__ cols, int6
             int32_t v = q.var[t];
             stride[t] = s;
             s *= arity[v];
-            colp[t] = make_col(cols + (int64_t)v * m_pad, m_pad);
+            colp[t] = make_col(cols + (int64_t)v * pitch, pitch);
         }
     }
     const int32_t cs = (int32_t)(win | 1u);
@@ -99,7 +99,7 @@ __device__ __forceinline__ void hist_body(const uint8_t *__restrict__ cols, int6
     for (int32_t i = threadIdx.x; i < copies * cs; i += kBlock) lds[i] = 0;
     __syncthreads();
 
-    const int64_t tiles = m_pad / kTileRows;
+    const int64_t tiles = q.tiles;
     const int64_t r0 = (int64_t)c * tiles / chunks * kTileRows;
     const int64_t r1 = (int64_t)(c + 1) * tiles / chunks * kTileRows;
     uint32_t *h = lds + (threadIdx.x & (copies - 1)) * cs;
@@ -121,7 +121,7 @@ __device__ __forceinline__ void hist_body(const uint8_t *__restrict__ cols, int6
         }
     }
     __syncthreads();
-    const bool has_pad = (r1 == m_pad) && (r0 < r1) && win_base == 0;
+    const bool has_pad = (r1 == tiles * kTileRows) && (r0 < r1) && win_base == 0;
     int32_t *out = tables + q.table_off + win_base;
     for (int32_t cell = threadIdx.x; cell < (int32_t)win; cell += kBlock) {
         uint32_t sum = 0;
@@ -132,7 +132,7 @@ __device__ __forceinline__ void hist_body(const uint8_t *__restrict__ cols, int6
 }
 
 template <int K, bool SMALL>
-__global__ __launch_bounds__(kBlock) void k_hist(const uint8_t *__restrict__ cols, int64_t m_pad,
+__global__ __launch_bounds__(kBlock) void k_hist(const uint8_t *__restrict__ cols, int64_t pitch,
                                                  const uint8_t *__restrict__ arity,
                                                  const QDesc *__restrict__ descs, int32_t nd,
                                                  int32_t chunks, int32_t lds_words,
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void k_hist(const uint8_t *__restrict__ col
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     int32_t di, c;
     map_block(blockIdx.x, nd, chunks, di, c);
-    hist_body<K, SMALL>(cols, m_pad, arity, descs[di], c, chunks, lds_words, pad_rows, tables, lds);
+    hist_body<K, SMALL>(cols, pitch, arity, descs[di], c, chunks, lds_words, pad_rows, tables, lds);
 }
 
 // Lane-column histograms: every cell owns B consecutive LDS words (B a power
@@ -199,7 +199,7 @@ __device__ __forceinline__ uint32_t pk_mad_u16(uint32_t a, uint32_t b, uint32_t 
 }
 
 template <int K>
-__device__ __forceinline__ void hist16_body(const uint8_t *__restrict__ cols, int64_t m_pad,
+__device__ __forceinline__ void hist16_body(const uint8_t *__restrict__ cols, int64_t pitch,
                                             const uint8_t *__restrict__ arity, const QDesc &q,
                                             int32_t c, int32_t chunks, int32_t lds_words,
                                             int32_t pad_rows, int32_t *__restrict__ tables,
@@ -214,7 +214,7 @@ __device__ __forceinline__ void hist16_body(const uint8_t *__restrict__ cols, in
             const int32_t v = q.var[t];
             sb[t] = (s * 4u) * 0x00010001u;  // byte stride in both halves
             s *= arity[v];
-            colp[t] = make_col(cols + (int64_t)v * m_pad, m_pad);
+            colp[t] = make_col(cols + (int64_t)v * pitch, pitch);
         }
     }
     // Lane columns: each cell owns B consecutive words (B = 64, 32, ..., 1,
@@ -228,7 +228,7 @@ __device__ __forceinline__ void hist16_body(const uint8_t *__restrict__ cols, in
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < K; ++t) sb[t] *= (uint32_t)B;
-    const int64_t tiles = m_pad / kTileRows;
+    const int64_t tiles = q.tiles;
     const int64_t r0 = (int64_t)c * tiles / chunks * kTileRows;
     const int64_t r1 = (int64_t)(c + 1) * tiles / chunks * kTileRows;
     const uint32_t init = ((threadIdx.x & (uint32_t)(B - 1)) * 4u) * 0x00010001u;
@@ -254,7 +254,7 @@ __device__ __forceinline__ void hist16_body(const uint8_t *__restrict__ cols, in
         }
     }
     __syncthreads();
-    flush_cols(lds, cells, B, (r1 == m_pad) && (r0 < r1), pad_rows, tables + q.table_off);
+    flush_cols(lds, cells, B, (r1 == tiles * kTileRows) && (r0 < r1), pad_rows, tables + q.table_off);
 }
 
 // LDS byte address of byte-key `i` of `key` (selector 0x0c0c0400 + i*256):
@@ -277,7 +277,7 @@ __device__ __forceinline__ uint32_t lds_addr(uint32_t key, uint32_t slot, uint32
 // conflict whatever the keys.  B = 32 (tables of up to 256 cells in 32 KiB):
 // the permute builds key*256 + (lane mod 32)*8 and one shift halves it.
 template <int K, int B>
-__device__ __forceinline__ void hist8_body(const uint8_t *__restrict__ cols, int64_t m_pad,
+__device__ __forceinline__ void hist8_body(const uint8_t *__restrict__ cols, int64_t pitch,
                                            const uint8_t *__restrict__ arity, const QDesc &q,
                                            int32_t c, int32_t chunks, int32_t pad_rows,
                                            int32_t *__restrict__ tables, uint32_t *lds) {
@@ -291,12 +291,12 @@ __device__ __forceinline__ void hist8_body(const uint8_t *__restrict__ cols, int
             const int32_t v = q.var[t];
             sb[t] = s * 0x00010001u;  // the stride in both halves
             s *= arity[v];
-            colp[t] = make_col(cols + (int64_t)v * m_pad, m_pad);
+            colp[t] = make_col(cols + (int64_t)v * pitch, pitch);
         }
     }
     zero_cols(lds, cells * B);
     __syncthreads();
-    const int64_t tiles = m_pad / kTileRows;
+    const int64_t tiles = q.tiles;
     const int64_t r0 = (int64_t)c * tiles / chunks * kTileRows;
     const int64_t r1 = (int64_t)(c + 1) * tiles / chunks * kTileRows;
     const uint32_t slot = B == 64 ? (threadIdx.x & 63u) * 4u : (threadIdx.x & 31u) * 8u;
@@ -322,7 +322,7 @@ __device__ __forceinline__ void hist8_body(const uint8_t *__restrict__ cols, int
         }
     }
     __syncthreads();
-    flush_cols(lds, cells, B, (r1 == m_pad) && (r0 < r1), pad_rows, tables + q.table_off);
+    flush_cols(lds, cells, B, (r1 == tiles * kTileRows) && (r0 < r1), pad_rows, tables + q.table_off);
 }
 
 // CAP: the launch group's largest table.  The histogram is a static LDS
@@ -330,7 +330,7 @@ __device__ __forceinline__ void hist8_body(const uint8_t *__restrict__ cols, int
 // instance on the LDS base.
 template <int K, int CAP>
 __global__ __launch_bounds__(kBlock) void k_hist8(const uint8_t *__restrict__ cols,
-                                                  int64_t m_pad,
+                                                  int64_t pitch,
                                                   const uint8_t *__restrict__ arity,
                                                   const QDesc *__restrict__ descs, int32_t nd,
                                                   int32_t chunks, int32_t pad_rows,
@@ -339,12 +339,12 @@ __global__ __launch_bounds__(kBlock) void k_hist8(const uint8_t *__restrict__ co
     __shared__ __attribute__((aligned(16))) uint32_t lds[CAP * B];
     int32_t di, c;
     map_block(blockIdx.x, nd, chunks, di, c);
-    hist8_body<K, B>(cols, m_pad, arity, descs[di], c, chunks, pad_rows, tables, lds);
+    hist8_body<K, B>(cols, pitch, arity, descs[di], c, chunks, pad_rows, tables, lds);
 }
 
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_hist16(const uint8_t *__restrict__ cols,
-                                                   int64_t m_pad,
+                                                   int64_t pitch,
                                                    const uint8_t *__restrict__ arity,
                                                    const QDesc *__restrict__ descs, int32_t nd,
                                                    int32_t chunks, int32_t lds_words,
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_hist16(const uint8_t *__restrict__ c
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     int32_t di, c;
     map_block(blockIdx.x, nd, chunks, di, c);
-    hist16_body<K>(cols, m_pad, arity, descs[di], c, chunks, lds_words, pad_rows, tables, lds);
+    hist16_body<K>(cols, pitch, arity, descs[di], c, chunks, lds_words, pad_rows, tables, lds);
 }
 
 // The same two histograms over the 4-bit packed columns (all arities at most
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_hist16(const uint8_t *__restrict__ c
 // word, masked into bytes, give two chains of packed multiply-adds, four
 // keys each.
 template <int K, int B>
-__device__ __forceinline__ void hist8n_body(const uint8_t *__restrict__ nib, int64_t m_pad,
+__device__ __forceinline__ void hist8n_body(const uint8_t *__restrict__ nib, int64_t pitch,
                                             const uint8_t *__restrict__ arity, const QDesc &q,
                                             int32_t c, int32_t chunks, int32_t pad_rows,
                                             int32_t *__restrict__ tables, uint32_t *lds) {
@@ -378,12 +378,12 @@ __device__ __forceinline__ void hist8n_body(const uint8_t *__restrict__ nib, int
             const int32_t v = q.var[t];
             sb[t] = s * 0x00010001u;
             s *= arity[v];
-            colp[t] = make_col(nib + (int64_t)v * (m_pad / 2), m_pad / 2);
+            colp[t] = make_col(nib + (int64_t)v * (pitch / 2), pitch / 2);
         }
     }
     zero_cols(lds, cells * B);
     __syncthreads();
-    const int64_t tiles = m_pad / kTileRows;
+    const int64_t tiles = q.tiles;
     const int64_t r0 = (int64_t)c * tiles / chunks * kTileRows;
     const int64_t r1 = (int64_t)(c + 1) * tiles / chunks * kTileRows;
     const uint32_t slot = B == 64 ? (threadIdx.x & 63u) * 4u : (threadIdx.x & 31u) * 8u;
@@ -413,12 +413,12 @@ __device__ __forceinline__ void hist8n_body(const uint8_t *__restrict__ nib, int
         }
     }
     __syncthreads();
-    flush_cols(lds, cells, B, (r1 == m_pad) && (r0 < r1), pad_rows, tables + q.table_off);
+    flush_cols(lds, cells, B, (r1 == tiles * kTileRows) && (r0 < r1), pad_rows, tables + q.table_off);
 }
 
 template <int K, int CAP>
 __global__ __launch_bounds__(kBlock) void k_hist8n(const uint8_t *__restrict__ nib,
-                                                   int64_t m_pad,
+                                                   int64_t pitch,
                                                    const uint8_t *__restrict__ arity,
                                                    const QDesc *__restrict__ descs, int32_t nd,
                                                    int32_t chunks, int32_t pad_rows,
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(kBlock) void k_hist8n(const uint8_t *__restrict__ n
     __shared__ __attribute__((aligned(16))) uint32_t lds[CAP * B];
     int32_t di, c;
     map_block(blockIdx.x, nd, chunks, di, c);
-    hist8n_body<K, B>(nib, m_pad, arity, descs[di], c, chunks, pad_rows, tables, lds);
+    hist8n_body<K, B>(nib, pitch, arity, descs[di], c, chunks, pad_rows, tables, lds);
 }
 
 // Address keys (lane columns of B words per cell): the key of two instances
@@ -437,7 +437,7 @@ __global__ __launch_bounds__(kBlock) void k_hist8n(const uint8_t *__restrict__ n
 // exact because a cell is 4 B >= 16 bytes wide; positions 2 and 3 come from
 // the word shifted by 8.  Otherwise every position is shifted down first.
 template <int K, bool WIDE>
-__device__ __forceinline__ void hist16n_body(const uint8_t *__restrict__ nib, int64_t m_pad,
+__device__ __forceinline__ void hist16n_body(const uint8_t *__restrict__ nib, int64_t pitch,
                                              const uint8_t *__restrict__ arity, const QDesc &q,
                                              int32_t c, int32_t chunks, int32_t lds_words,
                                              int32_t pad_rows, int32_t *__restrict__ tables,
@@ -456,12 +456,12 @@ __device__ __forceinline__ void hist16n_body(const uint8_t *__restrict__ nib, in
             sq[t] = WIDE ? (s * (uint32_t)B / 4u) * 0x00010001u  // the same for 16 x state
                          : sa[t];
             s *= arity[v];
-            colp[t] = make_col(nib + (int64_t)v * (m_pad / 2), m_pad / 2);
+            colp[t] = make_col(nib + (int64_t)v * (pitch / 2), pitch / 2);
         }
     }
     zero_cols(lds, cells * B);
     __syncthreads();
-    const int64_t tiles = m_pad / kTileRows;
+    const int64_t tiles = q.tiles;
     const int64_t r0 = (int64_t)c * tiles / chunks * kTileRows;
     const int64_t r1 = (int64_t)(c + 1) * tiles / chunks * kTileRows;
     const uint32_t init = ((threadIdx.x & (uint32_t)(B - 1)) * 4u) * 0x00010001u;
@@ -499,12 +499,12 @@ __device__ __forceinline__ void hist16n_body(const uint8_t *__restrict__ nib, in
         }
     }
     __syncthreads();
-    flush_cols(lds, cells, B, (r1 == m_pad) && (r0 < r1), pad_rows, tables + q.table_off);
+    flush_cols(lds, cells, B, (r1 == tiles * kTileRows) && (r0 < r1), pad_rows, tables + q.table_off);
 }
 
 template <int K, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_hist16n(const uint8_t *__restrict__ nib,
-                                                    int64_t m_pad,
+                                                    int64_t pitch,
                                                     const uint8_t *__restrict__ arity,
                                                     const QDesc *__restrict__ descs, int32_t nd,
                                                     int32_t chunks, int32_t lds_words,
@@ -513,7 +513,7 @@ __global__ __launch_bounds__(kBlock) void k_hist16n(const uint8_t *__restrict__ 
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     int32_t di, c;
     map_block(blockIdx.x, nd, chunks, di, c);
-    hist16n_body<K, WIDE>(nib, m_pad, arity, descs[di], c, chunks, lds_words, pad_rows, tables,
+    hist16n_body<K, WIDE>(nib, pitch, arity, descs[di], c, chunks, lds_words, pad_rows, tables,
                           lds);
 }
 
@@ -525,7 +525,7 @@ constexpr int kLeafMax = 8;
 template <int L, int K, int W>
 struct Walk {
     __device__ __forceinline__ static void go(const uint64_t (&pre)[W], uint32_t cell,
-                                              const uint64_t *__restrict__ bits, int64_t words,
+                                              const uint64_t *__restrict__ bits, int64_t wpitch,
                                               int64_t w, const int32_t (&base)[K],
                                               const int32_t (&rad)[K], bool cached,
                                               const uint64_t (&leaf)[kLeafMax][W],
@@ -545,7 +545,7 @@ struct Walk {
             }
         }
         for (int32_t s = 0; s < rad[L]; ++s) {
-            const uint64_t *row = bits + (int64_t)(base[L] + s) * words + w;
+            const uint64_t *row = bits + (int64_t)(base[L] + s) * wpitch + w;
             uint64_t x[W];
 #pragma unroll
             for (int i = 0; i < W; ++i) x[i] = row[i] & pre[i];
@@ -560,14 +560,14 @@ struct Walk {
 #pragma unroll
                 for (int i = 0; i < W; ++i) any |= x[i];
                 if (__any(any != 0))
-                    Walk<L + 1, K, W>::go(x, c2, bits, words, w, base, rad, cached, leaf, acc);
+                    Walk<L + 1, K, W>::go(x, c2, bits, wpitch, w, base, rad, cached, leaf, acc);
             }
         }
     }
 };
 
 template <int K, int W>
-__device__ __forceinline__ void bitmap_body(const uint64_t *__restrict__ bits, int64_t words,
+__device__ __forceinline__ void bitmap_body(const uint64_t *__restrict__ bits, int64_t wpitch,
                                             const int32_t *__restrict__ soff,
                                             const uint8_t *__restrict__ arity, const QDesc &q,
                                             int32_t c, int32_t chunks,
@@ -582,7 +582,7 @@ __device__ __forceinline__ void bitmap_body(const uint64_t *__restrict__ bits, i
     }
     for (int32_t i = threadIdx.x; i < cells * kBlock; i += kBlock) acc[i] = 0;
     __syncthreads();
-    const int64_t tiles = words / (kTileRows / 64);
+    const int64_t tiles = q.tiles;
     const int64_t w0 = (int64_t)c * tiles / chunks * (kTileRows / 64);
     const int64_t w1 = (int64_t)(c + 1) * tiles / chunks * (kTileRows / 64);
     uint64_t ones[W];
@@ -596,7 +596,7 @@ __device__ __forceinline__ void bitmap_body(const uint64_t *__restrict__ bits, i
 #pragma unroll
             for (int s = 0; s < kLeafMax; ++s) {
                 if (s < rad[K - 1]) {  // uniform: no load for absent states
-                    const uint64_t *row = bits + (int64_t)(base[K - 1] + s) * words + w;
+                    const uint64_t *row = bits + (int64_t)(base[K - 1] + s) * wpitch + w;
 #pragma unroll
                     for (int i = 0; i < W; ++i) leaf[s][i] = row[i];
                 } else {
@@ -605,7 +605,7 @@ __device__ __forceinline__ void bitmap_body(const uint64_t *__restrict__ bits, i
                 }
             }
         }
-        Walk<0, K, W>::go(ones, 0u, bits, words, w, base, rad, cached, leaf, acc + threadIdx.x);
+        Walk<0, K, W>::go(ones, 0u, bits, wpitch, w, base, rad, cached, leaf, acc + threadIdx.x);
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -621,7 +621,7 @@ __device__ __forceinline__ void bitmap_body(const uint64_t *__restrict__ bits, i
 
 template <int K, int W>
 __global__ __launch_bounds__(kBlock) void k_bitmap(const uint64_t *__restrict__ bits,
-                                                   int64_t words,
+                                                   int64_t wpitch,
                                                    const int32_t *__restrict__ soff,
                                                    const uint8_t *__restrict__ arity,
                                                    const QDesc *__restrict__ descs, int32_t nd,
@@ -629,7 +629,7 @@ __global__ __launch_bounds__(kBlock) void k_bitmap(const uint64_t *__restrict__ 
     extern __shared__ uint32_t acc[];  // [cells][kBlock], thread-private columns
     int32_t di, c;
     map_block(blockIdx.x, nd, chunks, di, c);
-    bitmap_body<K, W>(bits, words, soff, arity, descs[di], c, chunks, tables, acc);
+    bitmap_body<K, W>(bits, wpitch, soff, arity, descs[di], c, chunks, tables, acc);
 }
 
 // One persistent launch over many launch groups.  Each group is a set of
@@ -651,35 +651,35 @@ struct PGroup {
 enum { PK_HIST16 = 1, PK_HIST_S = 2, PK_HIST_B = 3, PK_BITMAP = 4, PK_HIST8 = 5 };
 
 template <int K, int W>
-__device__ __forceinline__ void persistent_case(int type, const uint8_t *cols, int64_t m_pad,
-                                                const uint64_t *bits, int64_t words,
+__device__ __forceinline__ void persistent_case(int type, const uint8_t *cols, int64_t pitch,
+                                                const uint64_t *bits, int64_t wpitch,
                                                 const int32_t *soff, const uint8_t *arity,
                                                 const QDesc &q, int32_t c, int32_t chunks,
                                                 int32_t lds_words, int32_t pad, int32_t *tables,
                                                 uint32_t *lds) {
     switch (type) {
         case PK_HIST8:
-            hist8_body<K, 64>(cols, m_pad, arity, q, c, chunks, pad, tables, lds);
+            hist8_body<K, 64>(cols, pitch, arity, q, c, chunks, pad, tables, lds);
             break;
         case PK_HIST16:
-            hist16_body<K>(cols, m_pad, arity, q, c, chunks, lds_words, pad, tables, lds);
+            hist16_body<K>(cols, pitch, arity, q, c, chunks, lds_words, pad, tables, lds);
             break;
         case PK_HIST_S:
-            hist_body<K, true>(cols, m_pad, arity, q, c, chunks, lds_words, pad, tables, lds);
+            hist_body<K, true>(cols, pitch, arity, q, c, chunks, lds_words, pad, tables, lds);
             break;
         case PK_HIST_B:
-            hist_body<K, false>(cols, m_pad, arity, q, c, chunks, lds_words, pad, tables, lds);
+            hist_body<K, false>(cols, pitch, arity, q, c, chunks, lds_words, pad, tables, lds);
             break;
         default:
-            bitmap_body<K, W>(bits, words, soff, arity, q, c, chunks, tables, lds);
+            bitmap_body<K, W>(bits, wpitch, soff, arity, q, c, chunks, tables, lds);
             break;
     }
 }
 
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_count_persistent(
-    const uint8_t *__restrict__ cols, int64_t m_pad, const uint64_t *__restrict__ bits,
-    int64_t words, const int32_t *__restrict__ soff, const uint8_t *__restrict__ arity,
+    const uint8_t *__restrict__ cols, int64_t pitch, const uint64_t *__restrict__ bits,
+    int64_t wpitch, const int32_t *__restrict__ soff, const uint8_t *__restrict__ arity,
     const QDesc *__restrict__ descs, const PGroup *__restrict__ groups, int32_t ngroups,
     int64_t total_v, uint32_t *__restrict__ heads, int32_t lds_words, int32_t pad_rows,
     int32_t *__restrict__ tables) {
@@ -713,14 +713,14 @@ __global__ __launch_bounds__(kBlock) void k_count_persistent(
         const QDesc &q = descs[G.first + di];
         const int type = G.kind >> 4;
         switch (G.kind & 15) {
-            case 1: persistent_case<1, W>(type, cols, m_pad, bits, words, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
-            case 2: persistent_case<2, W>(type, cols, m_pad, bits, words, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
-            case 3: persistent_case<3, W>(type, cols, m_pad, bits, words, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
-            case 4: persistent_case<4, W>(type, cols, m_pad, bits, words, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
-            case 5: persistent_case<5, W>(type, cols, m_pad, bits, words, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
-            case 6: persistent_case<6, W>(type, cols, m_pad, bits, words, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
-            case 7: persistent_case<7, W>(type, cols, m_pad, bits, words, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
-            default: persistent_case<8, W>(type, cols, m_pad, bits, words, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+            case 1: persistent_case<1, W>(type, cols, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+            case 2: persistent_case<2, W>(type, cols, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+            case 3: persistent_case<3, W>(type, cols, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+            case 4: persistent_case<4, W>(type, cols, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+            case 5: persistent_case<5, W>(type, cols, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+            case 6: persistent_case<6, W>(type, cols, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+            case 7: persistent_case<7, W>(type, cols, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+            default: persistent_case<8, W>(type, cols, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
         }
     }
 }
@@ -738,13 +738,13 @@ __global__ void k_zero_tables(const QDesc *__restrict__ descs, int32_t nd,
 struct Rows8 {
     int32_t r[FC_MAX_VARS];
 };
-__global__ void k_assign_bits(const uint64_t *__restrict__ bits, int64_t words, Rows8 rows,
-                              int32_t k, unsigned long long *__restrict__ out) {
+__global__ void k_assign_bits(const uint64_t *__restrict__ bits, int64_t words, int64_t wpitch,
+                              Rows8 rows, int32_t k, unsigned long long *__restrict__ out) {
     unsigned long long cnt = 0;
     for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words;
          w += (int64_t)gridDim.x * blockDim.x) {
         uint64_t x = ~0ull;
-        for (int32_t t = 0; t < k; ++t) x &= bits[(int64_t)rows.r[t] * words + w];
+        for (int32_t t = 0; t < k; ++t) x &= bits[(int64_t)rows.r[t] * wpitch + w];
         cnt += (unsigned long long)__popcll(x);
     }
 #pragma unroll
@@ -757,14 +757,14 @@ struct Assign8 {
     int32_t var[FC_MAX_VARS];
     int32_t state[FC_MAX_VARS];
 };
-__global__ void k_assign_cols(const uint8_t *__restrict__ cols, int64_t m, int64_t m_pad,
+__global__ void k_assign_cols(const uint8_t *__restrict__ cols, int64_t m, int64_t pitch,
                               Assign8 a, int32_t k, unsigned long long *__restrict__ out) {
     unsigned long long cnt = 0;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m;
          p += (int64_t)gridDim.x * blockDim.x) {
         bool ok = true;
         for (int32_t t = 0; t < k; ++t)
-            ok = ok && cols[(int64_t)a.var[t] * m_pad + p] == (uint8_t)a.state[t];
+            ok = ok && cols[(int64_t)a.var[t] * pitch + p] == (uint8_t)a.state[t];
         cnt += ok ? 1ull : 0ull;
     }
 #pragma unroll
@@ -782,7 +782,7 @@ struct ADesc {
 };
 
 __global__ __launch_bounds__(kBlock) void k_assign_batch(const uint64_t *__restrict__ bits,
-                                                         int64_t words,
+                                                         int64_t words, int64_t wpitch,
                                                          const ADesc *__restrict__ descs,
                                                          int32_t nd, int32_t chunks,
                                                          unsigned long long *__restrict__ out) {
@@ -797,7 +797,7 @@ __global__ __launch_bounds__(kBlock) void k_assign_batch(const uint64_t *__restr
     for (int64_t w = w0 + 2 * (int64_t)threadIdx.x; w < w1; w += 2 * kBlock) {
         uint64_t x0 = ~0ull, x1 = ~0ull;
         for (int32_t t = 0; t < q.k; ++t) {
-            const ulonglong2 v = *reinterpret_cast<const ulonglong2 *>(bits + (int64_t)q.row[t] * words + w);
+            const ulonglong2 v = *reinterpret_cast<const ulonglong2 *>(bits + (int64_t)q.row[t] * wpitch + w);
             x0 &= v.x;
             x1 &= v.y;
         }
@@ -816,20 +816,20 @@ __global__ __launch_bounds__(kBlock) void k_assign_batch(const uint64_t *__restr
 
 // The same counts from the state columns (no bit-vectors).
 __global__ __launch_bounds__(kBlock) void k_assign_batch_cols(
-    const uint8_t *__restrict__ cols, int64_t m, int64_t m_pad, const int32_t *__restrict__ vflat,
+    const uint8_t *__restrict__ cols, int64_t m, int64_t pitch, const int32_t *__restrict__ vflat,
     const int64_t *__restrict__ voff, const uint8_t *__restrict__ sflat, int32_t nd,
     int32_t chunks, unsigned long long *__restrict__ out) {
     __shared__ unsigned long long part[kWaves];
     int32_t di, c;
     map_block(blockIdx.x, nd, chunks, di, c);
     const int64_t o0 = voff[di], o1 = voff[di + 1];
-    const int64_t tiles = m_pad / kTileRows;
+    const int64_t tiles = (m + kTileRows - 1) / kTileRows;
     const int64_t r0 = (int64_t)c * tiles / chunks * kTileRows;
     const int64_t r1 = std::min<int64_t>(m, (int64_t)(c + 1) * tiles / chunks * kTileRows);
     unsigned long long cnt = 0;
     for (int64_t p = r0 + threadIdx.x; p < r1; p += kBlock) {
         bool ok = true;
-        for (int64_t t = o0; t < o1; ++t) ok = ok && cols[(int64_t)vflat[t] * m_pad + p] == sflat[t];
+        for (int64_t t = o0; t < o1; ++t) ok = ok && cols[(int64_t)vflat[t] * pitch + p] == sflat[t];
         cnt += ok ? 1ull : 0ull;
     }
 #pragma unroll
@@ -1195,6 +1195,7 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
             off += c;
             d.win_base = 0;
             d.win_cells = (int32_t)c;
+            d.tiles = (int32_t)(db->m_pad / kTileRows);
             if (need_query) P.query[(size_t)i] = d;
             int64_t win;
             const int st = choose(db, forced, k, c, win);
@@ -1269,41 +1270,41 @@ static hipError_t launch_hist_k(const fc_db *db, const Launch &L, const QDesc *d
     const int32_t pad = (int32_t)(db->m_pad - db->m);
     if (L.hk == HK_HIST8N && L.lds_bytes <= 16 * 64 * 4)
         hipLaunchKernelGGL((k_hist8n<K, 16>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                           db->d_nib, db->m_pad, db->d_arity, d, L.count, L.chunks, pad, tables);
+                           db->d_nib, db->pitch, db->d_arity, d, L.count, L.chunks, pad, tables);
     else if (L.hk == HK_HIST8N && L.lds_bytes <= 64 * 64 * 4)
         hipLaunchKernelGGL((k_hist8n<K, 64>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                           db->d_nib, db->m_pad, db->d_arity, d, L.count, L.chunks, pad, tables);
+                           db->d_nib, db->pitch, db->d_arity, d, L.count, L.chunks, pad, tables);
     else if (L.hk == HK_HIST8N)
         hipLaunchKernelGGL((k_hist8n<K, 256>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                           db->d_nib, db->m_pad, db->d_arity, d, L.count, L.chunks, pad, tables);
+                           db->d_nib, db->pitch, db->d_arity, d, L.count, L.chunks, pad, tables);
     else if (L.hk == HK_HIST16N && L.wide)
         hipLaunchKernelGGL((k_hist16n<K, true>), dim3((unsigned)blocks), dim3(kBlock), L.lds_bytes,
-                           s, db->d_nib, db->m_pad, db->d_arity, d, L.count, L.chunks,
+                           s, db->d_nib, db->pitch, db->d_arity, d, L.count, L.chunks,
                            L.lds_bytes / 4, pad, tables);
     else if (L.hk == HK_HIST16N)
         hipLaunchKernelGGL((k_hist16n<K, false>), dim3((unsigned)blocks), dim3(kBlock),
-                           L.lds_bytes, s, db->d_nib, db->m_pad, db->d_arity, d, L.count, L.chunks,
+                           L.lds_bytes, s, db->d_nib, db->pitch, db->d_arity, d, L.count, L.chunks,
                            L.lds_bytes / 4, pad, tables);
     else if (L.hk == HK_HIST8 && L.lds_bytes <= 16 * 64 * 4)
         hipLaunchKernelGGL((k_hist8<K, 16>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                           db->d_cols, db->m_pad, db->d_arity, d, L.count, L.chunks, pad, tables);
+                           db->d_cols, db->pitch, db->d_arity, d, L.count, L.chunks, pad, tables);
     else if (L.hk == HK_HIST8 && L.lds_bytes <= 64 * 64 * 4)
         hipLaunchKernelGGL((k_hist8<K, 64>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                           db->d_cols, db->m_pad, db->d_arity, d, L.count, L.chunks, pad, tables);
+                           db->d_cols, db->pitch, db->d_arity, d, L.count, L.chunks, pad, tables);
     else if (L.hk == HK_HIST8)
         hipLaunchKernelGGL((k_hist8<K, 256>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                           db->d_cols, db->m_pad, db->d_arity, d, L.count, L.chunks, pad, tables);
+                           db->d_cols, db->pitch, db->d_arity, d, L.count, L.chunks, pad, tables);
     else if (L.hk == HK_HIST16)
         hipLaunchKernelGGL((k_hist16<K>), dim3((unsigned)blocks), dim3(kBlock), L.lds_bytes, s,
-                           db->d_cols, db->m_pad, db->d_arity, d, L.count, L.chunks,
+                           db->d_cols, db->pitch, db->d_arity, d, L.count, L.chunks,
                            L.lds_bytes / 4, pad, tables);
     else if (L.small)
         hipLaunchKernelGGL((k_hist<K, true>), dim3((unsigned)blocks), dim3(kBlock), L.lds_bytes,
-                           s, db->d_cols, db->m_pad, db->d_arity, d, L.count, L.chunks,
+                           s, db->d_cols, db->pitch, db->d_arity, d, L.count, L.chunks,
                            L.lds_bytes / 4, pad, tables);
     else
         hipLaunchKernelGGL((k_hist<K, false>), dim3((unsigned)blocks), dim3(kBlock), L.lds_bytes,
-                           s, db->d_cols, db->m_pad, db->d_arity, d, L.count, L.chunks,
+                           s, db->d_cols, db->pitch, db->d_arity, d, L.count, L.chunks,
                            L.lds_bytes / 4, pad, tables);
     return hipGetLastError();
 }
@@ -1314,15 +1315,15 @@ static hipError_t launch_bitmap_k(const fc_db *db, const Launch &L, const QDesc 
     const int64_t blocks = (int64_t)L.count * L.chunks;
     if (db->tune.bitmap_words >= 4)
         hipLaunchKernelGGL((k_bitmap<K, 4>), dim3((unsigned)blocks), dim3(kBlock), L.lds_bytes,
-                           s, db->d_bits, db->words, db->d_soff, db->d_arity, d, L.count,
+                           s, db->d_bits, db->pitch / 64, db->d_soff, db->d_arity, d, L.count,
                            L.chunks, tables);
     else if (db->tune.bitmap_words == 2)
         hipLaunchKernelGGL((k_bitmap<K, 2>), dim3((unsigned)blocks), dim3(kBlock), L.lds_bytes,
-                           s, db->d_bits, db->words, db->d_soff, db->d_arity, d, L.count,
+                           s, db->d_bits, db->pitch / 64, db->d_soff, db->d_arity, d, L.count,
                            L.chunks, tables);
     else
         hipLaunchKernelGGL((k_bitmap<K, 1>), dim3((unsigned)blocks), dim3(kBlock), L.lds_bytes,
-                           s, db->d_bits, db->words, db->d_soff, db->d_arity, d, L.count,
+                           s, db->d_bits, db->pitch / 64, db->d_soff, db->d_arity, d, L.count,
                            L.chunks, tables);
     return hipGetLastError();
 }
@@ -1403,7 +1404,7 @@ static hipError_t launch_persistent_w(const fc_db *db, const PGroup *d_groups, i
     grid = std::min<int64_t>(grid, vtotal);
     grid = std::max<int64_t>(grid, 1);
     hipLaunchKernelGGL((k_count_persistent<W>), dim3((unsigned)grid), dim3(kBlock), lds, s,
-                       db->d_cols, db->m_pad, db->d_bits, db->words, db->d_soff, db->d_arity, dw,
+                       db->d_cols, db->pitch, db->d_bits, db->pitch / 64, db->d_soff, db->d_arity, dw,
                        d_groups, ngroups, vtotal, heads, lds / 4, (int32_t)(db->m_pad - db->m),
                        tables);
     return hipGetLastError();
@@ -1734,7 +1735,7 @@ extern "C" int fc_count_assignment(fc_db *db, const int32_t *vars, const uint8_t
                 rows.r[t] = t < k ? db->state_off[vars[t]] + states[t] : 0;
             int64_t blocks = std::min<int64_t>((db->words + 255) / 256, 4 * db->cu_count);
             hipLaunchKernelGGL(k_assign_bits, dim3((unsigned)blocks), dim3(256), 0, s, db->d_bits,
-                               db->words, rows, k, (unsigned long long *)d.p);
+                               db->words, db->pitch / 64, rows, k, (unsigned long long *)d.p);
         } else {
             Assign8 a;
             for (int32_t t = 0; t < FC_MAX_VARS; ++t) {
@@ -1743,7 +1744,7 @@ extern "C" int fc_count_assignment(fc_db *db, const int32_t *vars, const uint8_t
             }
             int64_t blocks = std::min<int64_t>((db->m + 255) / 256, 4 * db->cu_count);
             hipLaunchKernelGGL(k_assign_cols, dim3((unsigned)blocks), dim3(256), 0, s, db->d_cols,
-                               db->m, db->m_pad, a, k, (unsigned long long *)d.p);
+                               db->m, db->pitch, a, k, (unsigned long long *)d.p);
         }
         FC_HIP(hipGetLastError());
     }
@@ -2158,7 +2159,7 @@ extern "C" int fc_count_assignments(fc_db *db, const int32_t *vars_flat, const i
             staging_release(st, s);
             FC_HIP(e);
             hipLaunchKernelGGL(k_assign_batch, dim3((unsigned)(nq * ch)), dim3(kBlock), 0, s,
-                               db->d_bits, db->words, (const ADesc *)dq.p, (int32_t)nq,
+                               db->d_bits, db->words, db->pitch / 64, (const ADesc *)dq.p, (int32_t)nq,
                                (int32_t)ch, out);
         } else {
             const size_t nv = (size_t)var_off[nq];
@@ -2179,7 +2180,7 @@ extern "C" int fc_count_assignments(fc_db *db, const int32_t *vars_flat, const i
             FC_HIP(e);
             char *dp = (char *)dq.p;
             hipLaunchKernelGGL(k_assign_batch_cols, dim3((unsigned)(nq * ch)), dim3(kBlock), 0, s,
-                               db->d_cols, db->m, db->m_pad, (const int32_t *)dp,
+                               db->d_cols, db->m, db->pitch, (const int32_t *)dp,
                                (const int64_t *)(dp + sizeof(int32_t) * nv),
                                (const uint8_t *)(dp + sizeof(int32_t) * nv +
                                                  sizeof(int64_t) * ((size_t)nq + 1)),

@@ -186,9 +186,10 @@ void workspace_release(fc_db *db, Workspace *w, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ kernels
-// Row-major [m][n] -> column-major [n][m_pad] through an LDS tile.
+// Row-major [m][n] -> column-major [n][pitch] through an LDS tile (rows
+// [m, pitch) of the destination receive state 0).
 __global__ void k_transpose(const uint8_t *__restrict__ rm, int64_t m, int32_t n,
-                            uint8_t *__restrict__ cols, int64_t m_pad) {
+                            uint8_t *__restrict__ cols, int64_t pitch) {
     __shared__ uint8_t tile[64][65];
     int64_t p0 = (int64_t)blockIdx.x * 64;
     int32_t v0 = blockIdx.y * 64;
@@ -202,13 +203,13 @@ __global__ void k_transpose(const uint8_t *__restrict__ rm, int64_t m, int32_t n
     for (int r = ty; r < 64; r += 4) {
         int32_t v = v0 + r;
         int64_t p = p0 + tx;
-        if (v < n && p < m_pad) cols[(int64_t)v * m_pad + p] = tile[tx][r];
+        if (v < n && p < pitch) cols[(int64_t)v * pitch + p] = tile[tx][r];
     }
 }
 
 // Checks every state against its arity and counts the states of each
 // variable (the marginals).  One workgroup per (variable, row slab).
-__global__ void k_check_marg(const uint8_t *__restrict__ cols, int64_t m, int64_t m_pad,
+__global__ void k_check_marg(const uint8_t *__restrict__ cols, int64_t m, int64_t pitch,
                              const uint8_t *__restrict__ arity, const int32_t *__restrict__ soff,
                              int32_t *__restrict__ marg, int32_t *__restrict__ bad) {
     __shared__ int32_t h[256];
@@ -216,7 +217,7 @@ __global__ void k_check_marg(const uint8_t *__restrict__ cols, int64_t m, int64_
     int r = arity[v];
     for (int i = threadIdx.x; i < 256; i += blockDim.x) h[i] = 0;
     __syncthreads();
-    const uint8_t *col = cols + (int64_t)v * m_pad;
+    const uint8_t *col = cols + (int64_t)v * pitch;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int nbad = 0;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += stride) {
@@ -230,24 +231,21 @@ __global__ void k_check_marg(const uint8_t *__restrict__ cols, int64_t m, int64_
     if (nbad) atomicAdd(bad, nbad);
 }
 
-// Per-state bit-vectors: bit (p mod 64) of word p/64 of row (v, s) is set when
-// instance p of variable v is in state s.  One wave per 64-row word; padding
-// rows (p >= m) contribute no bits.
 // 4-bit copy of the columns for databases whose arities are all at most 16:
 // byte b of a column holds instance 2b in its low and 2b + 1 in its high
 // nibble.  Each thread packs 8 instances (two input words -> one word) of
 // the word range [d_lo, d_hi) of every column.
-__global__ void k_pack_nib(const uint8_t *__restrict__ cols, int64_t m_pad, int32_t n,
+__global__ void k_pack_nib(const uint8_t *__restrict__ cols, int64_t pitch, int32_t n,
                            int64_t d_lo, int64_t d_hi, uint8_t *__restrict__ nib) {
     const int64_t per = d_hi - d_lo;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < per * n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t v = (int32_t)(i / per);
         const int64_t d = d_lo + i % per;
-        const uint2 x = *reinterpret_cast<const uint2 *>(cols + (int64_t)v * m_pad + 8 * d);
+        const uint2 x = *reinterpret_cast<const uint2 *>(cols + (int64_t)v * pitch + 8 * d);
         const uint32_t even = __builtin_amdgcn_perm(x.y, x.x, 0x06040200u);  // instances 0,2,4,6
         const uint32_t odd = __builtin_amdgcn_perm(x.y, x.x, 0x07050301u);   // instances 1,3,5,7
-        reinterpret_cast<uint32_t *>(nib + (int64_t)v * (m_pad / 2))[d] = even | (odd << 4);
+        reinterpret_cast<uint32_t *>(nib + (int64_t)v * (pitch / 2))[d] = even | (odd << 4);
     }
 }
 
@@ -255,13 +253,16 @@ static hipError_t pack_nib(fc_db *db, int64_t d_lo, int64_t d_hi, hipStream_t s)
     if (!db->d_nib || d_hi <= d_lo) return hipSuccess;
     const int64_t total = (d_hi - d_lo) * db->n;
     const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_pack_nib, dim3((unsigned)blocks), dim3(256), 0, s, db->d_cols, db->m_pad,
+    hipLaunchKernelGGL(k_pack_nib, dim3((unsigned)blocks), dim3(256), 0, s, db->d_cols, db->pitch,
                        db->n, d_lo, d_hi, db->d_nib);
     return hipGetLastError();
 }
 
-__global__ void k_bitvectors(const uint8_t *__restrict__ cols, int64_t m, int64_t m_pad,
-                             int64_t words, int64_t w_lo, int64_t w_hi,
+// Per-state bit-vectors: bit (p mod 64) of word p/64 of row (v, s) is set when
+// instance p of variable v is in state s.  One wave per 64-row word; padding
+// rows (p >= m) contribute no bits.
+__global__ void k_bitvectors(const uint8_t *__restrict__ cols, int64_t m, int64_t pitch,
+                             int64_t wpitch, int64_t w_lo, int64_t w_hi,
                              const uint8_t *__restrict__ arity,
                              const int32_t *__restrict__ soff, uint64_t *__restrict__ bits) {
     int32_t v = blockIdx.y;
@@ -269,12 +270,12 @@ __global__ void k_bitvectors(const uint8_t *__restrict__ cols, int64_t m, int64_
     int64_t w = w_lo + (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     if (w >= w_hi) return;
     int64_t p = w * 64 + lane;
-    int s = (p < m) ? cols[(int64_t)v * m_pad + p] : 255;
+    int s = (p < m) ? cols[(int64_t)v * pitch + p] : 255;
     int r = arity[v];
-    uint64_t *row = bits + (int64_t)soff[v] * words + w;
+    uint64_t *row = bits + (int64_t)soff[v] * wpitch + w;
     for (int st = 0; st < r; ++st) {
         uint64_t b = __ballot(s == st);
-        if (lane == (st & 63)) row[(int64_t)st * words] = b;
+        if (lane == (st & 63)) row[(int64_t)st * wpitch] = b;
     }
 }
 
@@ -378,6 +379,7 @@ extern "C" int fc_db_create(const uint8_t *data, int64_t m, int32_t n, const uin
     db->m_pad = ((m + kTileRows - 1) / kTileRows) * kTileRows;
     if (db->m_pad == 0) db->m_pad = kTileRows;
     db->words = db->m_pad / 64;
+    db->pitch = db->m_pad;
     db->arity.assign(arity, arity + n);
     db->state_off.resize((size_t)n + 1);
     db->state_off[0] = 0;
@@ -385,7 +387,7 @@ extern "C" int fc_db_create(const uint8_t *data, int64_t m, int32_t n, const uin
     const int32_t sum_r = db->state_off[n];
 
     int rc;
-    if ((rc = db_alloc((void **)&db->d_cols, (size_t)n * (size_t)db->m_pad, db))) return rc;
+    if ((rc = db_alloc((void **)&db->d_cols, (size_t)n * (size_t)db->pitch, db))) return rc;
     if ((rc = db_alloc((void **)&db->d_arity, (size_t)n, db))) return rc;
     if ((rc = db_alloc((void **)&db->d_soff, sizeof(int32_t) * ((size_t)n + 1), db))) return rc;
     if ((rc = db_alloc((void **)&db->d_marg, sizeof(int32_t) * (size_t)sum_r, db))) return rc;
@@ -394,12 +396,12 @@ extern "C" int fc_db_create(const uint8_t *data, int64_t m, int32_t n, const uin
                           hipMemcpyHostToDevice, s));
     FC_HIP(fill_zero_i32(db->d_marg, sum_r, s));
     // padding rows hold state 0 (removed from every count arithmetically)
-    FC_HIP(fill_zero_i32((int32_t *)db->d_cols, (int64_t)n * db->m_pad / 4, s));
+    FC_HIP(fill_zero_i32((int32_t *)db->d_cols, (int64_t)n * db->pitch / 4, s));
 
     const bool on_dev = (flags & FC_DB_DATA_ON_DEVICE) != 0;
     if (m > 0) {
         if (layout == FC_COL_MAJOR) {
-            FC_HIP(hipMemcpy2DAsync(db->d_cols, (size_t)db->m_pad, data, (size_t)m, (size_t)m,
+            FC_HIP(hipMemcpy2DAsync(db->d_cols, (size_t)db->pitch, data, (size_t)m, (size_t)m,
                                     (size_t)n,
                                     on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
         } else {
@@ -413,7 +415,7 @@ extern "C" int fc_db_create(const uint8_t *data, int64_t m, int32_t n, const uin
             }
             dim3 grid((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64));
             hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, s, src, m, n, db->d_cols,
-                               db->m_pad);
+                               db->pitch);
             FC_HIP(hipGetLastError());
             FC_HIP(hipStreamSynchronize(s));  // tmp is freed on s after this
         }
@@ -426,7 +428,7 @@ extern "C" int fc_db_create(const uint8_t *data, int64_t m, int32_t n, const uin
         int64_t slabs = (m + 65535) / 65536;
         if (slabs > 64) slabs = 64;
         hipLaunchKernelGGL(k_check_marg, dim3((unsigned)slabs, (unsigned)n), dim3(256), 0, s,
-                           db->d_cols, m, db->m_pad, db->d_arity, db->d_soff, db->d_marg,
+                           db->d_cols, m, db->pitch, db->d_arity, db->d_soff, db->d_marg,
                            (int32_t *)bad.p);
         FC_HIP(hipGetLastError());
     }
@@ -454,16 +456,17 @@ extern "C" int fc_db_create(const uint8_t *data, int64_t m, int32_t n, const uin
     bool small_arity = true;
     for (int32_t v = 0; v < n; ++v) small_arity = small_arity && arity[v] <= 16;
     if (small_arity) {
-        if ((rc = db_alloc((void **)&db->d_nib, (size_t)n * (size_t)(db->m_pad / 2), db)))
+        if ((rc = db_alloc((void **)&db->d_nib, (size_t)n * (size_t)(db->pitch / 2), db)))
             return rc;
         FC_HIP(pack_nib(db, 0, db->m_pad / 8, s));
     }
     if (flags & FC_DB_BITVECTORS) {
-        size_t bytes = sizeof(uint64_t) * (size_t)sum_r * (size_t)db->words;
+        size_t bytes = sizeof(uint64_t) * (size_t)sum_r * (size_t)(db->pitch / 64);
         if ((rc = db_alloc((void **)&db->d_bits, bytes, db))) return rc;
         dim3 grid((unsigned)((db->words + 3) / 4), (unsigned)n);
-        hipLaunchKernelGGL(k_bitvectors, grid, dim3(256), 0, s, db->d_cols, m, db->m_pad,
-                           db->words, (int64_t)0, db->words, db->d_arity, db->d_soff, db->d_bits);
+        hipLaunchKernelGGL(k_bitvectors, grid, dim3(256), 0, s, db->d_cols, m, db->pitch,
+                           db->pitch / 64, (int64_t)0, db->words, db->d_arity, db->d_soff,
+                           db->d_bits);
         FC_HIP(hipGetLastError());
         FC_HIP(hipStreamSynchronize(s));
     }
@@ -556,72 +559,82 @@ extern "C" int fc_db_append(fc_db *db, const uint8_t *data, int64_t m_new, int32
                   "(nothing was appended)", nbad);
         return FC_ERR_INVALID;
     }
-    // 2. grow the padded columns and bit-vectors when the tile count changes
+    // 2. the scanned extent grows to the new tile count; the allocation (the
+    //    column pitch) only when the extent outgrows it, then geometrically
     FC_HIP(hipDeviceSynchronize());  // no launch may still read the old buffers
-    const int64_t m_pad_before = db->m_pad;
     const int64_t m_pad = ((m + kTileRows - 1) / kTileRows) * kTileRows;
-    const int64_t words = m_pad / 64;
-    if (m_pad != db->m_pad) {
+    const bool regrown = m_pad > db->pitch;
+    if (regrown) {
+        const int64_t grown = ((db->pitch + db->pitch / 2 + kTileRows - 1) / kTileRows) * kTileRows;
+        const int64_t pitch = std::min<int64_t>(std::max(m_pad, grown), int64_t(1) << 31);
+        const int64_t wpitch = pitch / 64;
         uint8_t *cols = nullptr;
-        if (hipMalloc(&cols, (size_t)n * (size_t)m_pad) != hipSuccess) {
+        if (hipMalloc(&cols, (size_t)n * (size_t)pitch) != hipSuccess) {
             (void)hipGetLastError();
             set_error("fc_db_append: device allocation failed");
             return FC_ERR_NOMEM;
         }
         uint64_t *bits = nullptr;
         if (db->d_bits &&
-            hipMalloc(&bits, sizeof(uint64_t) * (size_t)sum_r * (size_t)words) != hipSuccess) {
+            hipMalloc(&bits, sizeof(uint64_t) * (size_t)sum_r * (size_t)wpitch) != hipSuccess) {
             (void)hipGetLastError();
             (void)hipFree(cols);
             set_error("fc_db_append: device allocation failed");
             return FC_ERR_NOMEM;
         }
         uint8_t *nib = nullptr;
-        if (db->d_nib && hipMalloc(&nib, (size_t)n * (size_t)(m_pad / 2)) != hipSuccess) {
+        if (db->d_nib && hipMalloc(&nib, (size_t)n * (size_t)(pitch / 2)) != hipSuccess) {
             (void)hipGetLastError();
             (void)hipFree(cols);
             if (bits) (void)hipFree(bits);
             set_error("fc_db_append: device allocation failed");
             return FC_ERR_NOMEM;
         }
-        FC_HIP(fill_zero_i32((int32_t *)cols, (int64_t)n * m_pad / 4, s));
-        FC_HIP(hipMemcpy2DAsync(cols, (size_t)m_pad, db->d_cols, (size_t)db->m_pad,
+        // every row past m holds state 0 and no bit, in all three stores
+        FC_HIP(fill_zero_i32((int32_t *)cols, (int64_t)n * pitch / 4, s));
+        FC_HIP(hipMemcpy2DAsync(cols, (size_t)pitch, db->d_cols, (size_t)db->pitch,
                                 (size_t)db->m_pad, (size_t)n, hipMemcpyDeviceToDevice, s));
+        if (nib) {
+            FC_HIP(fill_zero_i32((int32_t *)nib, (int64_t)n * pitch / 8, s));
+            FC_HIP(hipMemcpy2DAsync(nib, (size_t)(pitch / 2), db->d_nib, (size_t)(db->pitch / 2),
+                                    (size_t)(db->m_pad / 2), (size_t)n, hipMemcpyDeviceToDevice,
+                                    s));
+        }
         if (bits) {
-            FC_HIP(fill_zero_i32((int32_t *)bits, 2 * (int64_t)sum_r * words, s));
-            FC_HIP(hipMemcpy2DAsync(bits, sizeof(uint64_t) * (size_t)words, db->d_bits,
-                                    sizeof(uint64_t) * (size_t)db->words,
+            FC_HIP(fill_zero_i32((int32_t *)bits, 2 * (int64_t)sum_r * wpitch, s));
+            FC_HIP(hipMemcpy2DAsync(bits, sizeof(uint64_t) * (size_t)wpitch, db->d_bits,
+                                    sizeof(uint64_t) * (size_t)(db->pitch / 64),
                                     sizeof(uint64_t) * (size_t)db->words, (size_t)sum_r,
                                     hipMemcpyDeviceToDevice, s));
         }
         FC_HIP(hipStreamSynchronize(s));
         (void)hipFree(db->d_cols);
-        db->device_bytes += (int64_t)n * (m_pad - db->m_pad);
+        db->device_bytes += (int64_t)n * (pitch - db->pitch);
         db->d_cols = cols;
-        if (nib) {  // repacked whole below
+        if (nib) {
             (void)hipFree(db->d_nib);
-            db->device_bytes += (int64_t)n * (m_pad - db->m_pad) / 2;
+            db->device_bytes += (int64_t)n * (pitch - db->pitch) / 2;
             db->d_nib = nib;
         }
         if (bits) {
             (void)hipFree(db->d_bits);
-            db->device_bytes += (int64_t)sizeof(uint64_t) * sum_r * (words - db->words);
+            db->device_bytes += (int64_t)sizeof(uint64_t) * sum_r * (wpitch - db->pitch / 64);
             db->d_bits = bits;
         }
-        db->m_pad = m_pad;
-        db->words = words;
+        db->pitch = pitch;
     }
+    db->m_pad = m_pad;
+    db->words = m_pad / 64;
     // 3. the new instances into the columns, then the packed words and the
-    //    bit-vector words they touch (all packed words after a regrowth)
-    const bool regrown = db->m_pad != m_pad_before;
-    FC_HIP(hipMemcpy2DAsync(db->d_cols + m_old, (size_t)db->m_pad, tmp.p, (size_t)m_new,
+    //    bit-vector words they touch (rows past m stay state 0 / no bit)
+    FC_HIP(hipMemcpy2DAsync(db->d_cols + m_old, (size_t)db->pitch, tmp.p, (size_t)m_new,
                             (size_t)m_new, (size_t)n, hipMemcpyDeviceToDevice, s));
-    FC_HIP(pack_nib(db, regrown ? 0 : m_old / 8, regrown ? db->m_pad / 8 : (m + 7) / 8, s));
+    FC_HIP(pack_nib(db, m_old / 8, (m + 7) / 8, s));
     if (db->d_bits) {
         const int64_t w_lo = m_old / 64, w_hi = (m + 63) / 64;
         dim3 grid((unsigned)((w_hi - w_lo + 3) / 4), (unsigned)n);
-        hipLaunchKernelGGL(k_bitvectors, grid, dim3(256), 0, s, db->d_cols, m, db->m_pad,
-                           db->words, w_lo, w_hi, db->d_arity, db->d_soff, db->d_bits);
+        hipLaunchKernelGGL(k_bitvectors, grid, dim3(256), 0, s, db->d_cols, m, db->pitch,
+                           db->pitch / 64, w_lo, w_hi, db->d_arity, db->d_soff, db->d_bits);
         FC_HIP(hipGetLastError());
     }
     std::vector<int32_t> marg32((size_t)sum_r);

@@ -32,7 +32,7 @@ struct alignas(16) QDesc {
     int32_t win_base;   // first key of the window (0 when not partitioned)
     int32_t win_cells;  // keys in the window
     int32_t qid;        // query index in the caller's batch
-    int32_t pad;
+    int32_t tiles;      // kTileRows tiles scanned: the padded extent m_pad / kTileRows
 };
 static_assert(sizeof(QDesc) == 64, "QDesc must be 64 bytes");
 
@@ -69,15 +69,20 @@ struct Workspace {
 struct fc_db {
     int device = 0;
     int cu_count = 256;
-    int64_t m = 0, m_pad = 0, words = 0;
+    // m_pad: m rounded up to whole tiles, the extent every scan covers;
+    // words = m_pad / 64.  pitch: rows allocated per column (a multiple of
+    // kTileRows, >= m_pad; appends grow it geometrically), the stride of the
+    // columns; the packed columns' stride is pitch / 2 bytes and the
+    // bit-vectors' pitch / 64 words.  Rows in [m, pitch) hold state 0.
+    int64_t m = 0, m_pad = 0, words = 0, pitch = 0;
     int32_t n = 0;
     std::vector<uint8_t> arity;      // n
     std::vector<int32_t> state_off;  // n+1, prefix sums of arities
     std::vector<int64_t> marg;       // sum of arities
     std::vector<float> entropy;      // n, bits
-    uint8_t *d_cols = nullptr;       // [n][m_pad] states
-    uint8_t *d_nib = nullptr;        // [n][m_pad/2] states, 4 bits each (all arities <= 16)
-    uint64_t *d_bits = nullptr;      // [sum r][words] per-state bit-vectors
+    uint8_t *d_cols = nullptr;       // [n][pitch] states
+    uint8_t *d_nib = nullptr;        // [n][pitch/2] states, 4 bits each (all arities <= 16)
+    uint64_t *d_bits = nullptr;      // [sum r][pitch/64] per-state bit-vectors
     uint8_t *d_arity = nullptr;      // [n]
     int32_t *d_soff = nullptr;       // [n+1]
     int32_t *d_marg = nullptr;       // [sum r]

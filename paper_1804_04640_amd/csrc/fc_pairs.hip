@@ -118,6 +118,7 @@ __device__ __forceinline__ void gram_step(const Words &xn, const uint4 (&ma)[2],
 }
 
 __global__ __launch_bounds__(256, 2) void k_gram(const uint64_t *__restrict__ bits, int64_t words,
+                                                 int64_t wpitch,
                                                  const int32_t *__restrict__ rowidx, int32_t nrb,
                                                  int32_t ncb, int32_t npairs, int32_t splits,
                                                  int32_t *__restrict__ C, int32_t ldc) {
@@ -142,14 +143,14 @@ __global__ __launch_bounds__(256, 2) void k_gram(const uint64_t *__restrict__ bi
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const int32_t r = rowidx[I * kGT + (2 * wave + i) * 16 + col];
-        pa[i] = bits + (int64_t)(r < 0 ? 0 : r) * words + 2 * grp;
+        pa[i] = bits + (int64_t)(r < 0 ? 0 : r) * wpitch + 2 * grp;
         const uint32_t m = r < 0 ? 0u : 0xFFFFFFFFu;
         ma[i] = make_uint4(m, m, m, m);
     }
 #pragma unroll
     for (int j = 0; j < kGK; ++j) {
         const int32_t r = rowidx[col0 + j * 16 + col];
-        pb[j] = bits + (int64_t)(r < 0 ? 0 : r) * words + 2 * grp;
+        pb[j] = bits + (int64_t)(r < 0 ? 0 : r) * wpitch + 2 * grp;
         const uint32_t m = r < 0 ? 0u : 0xFFFFFFFFu;
         mb[j] = make_uint4(m, m, m, m);
     }
@@ -329,7 +330,8 @@ extern "C" int fc_pairs(fc_db *db, const int32_t *items, int32_t ni, double mins
         const double ops = 2.0 * (double)db->m * (double)ni * (double)(ni + 1) / 2.0;
         ProfScope ps("k_gram", s, 0.0, ops);
         hipLaunchKernelGGL(k_gram, dim3((unsigned)(npairs * splits)), dim3(256), 0, s,
-                           db->d_bits, db->words, (const int32_t *)dRow.p, nrb, ncb, npairs,
+                           db->d_bits, db->words, db->pitch / 64, (const int32_t *)dRow.p, nrb, ncb,
+                           npairs,
                            (int32_t)splits, C, (int32_t)ldc);
         FC_HIP(hipGetLastError());
         ps.end(s);

@@ -37,7 +37,7 @@ constexpr int kKeysPerThread = 8;
 // all loads issued before the arithmetic.
 template <typename K>
 __global__ __launch_bounds__(256) void k_keys_batch(const uint8_t *__restrict__ cols, int64_t m,
-                                                    int64_t m_pad,
+                                                    int64_t pitch,
                                                     const BatchSpec *__restrict__ specs,
                                                     int32_t bits, K *__restrict__ keys) {
     const int32_t j = blockIdx.y;
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void k_keys_batch(const uint8_t *__restrict__ 
         uint64_t w[FC_MAX_VARS];
 #pragma unroll
         for (int t = 0; t < FC_MAX_VARS; ++t)
-            w[t] = t < q.k ? *(const uint64_t *)(cols + (int64_t)q.var[t] * m_pad + p0) : 0;
+            w[t] = t < q.k ? *(const uint64_t *)(cols + (int64_t)q.var[t] * pitch + p0) : 0;
         uint64_t key[kKeysPerThread];
 #pragma unroll
         for (int e = 0; e < kKeysPerThread; ++e) key[e] = 0;
@@ -230,7 +230,7 @@ int sparse_group(fc_db *db, const Group &g, const BatchSpec *d_specs, double col
         const int64_t bx = std::max<int64_t>(
             1, std::min<int64_t>((per_q + 255) / 256, (8 * (int64_t)db->cu_count + g.G - 1) / g.G));
         hipLaunchKernelGGL(k_keys_batch<K>, dim3((unsigned)bx, (unsigned)g.G), dim3(256), 0, s,
-                           db->d_cols, m, db->m_pad, d_specs + g.q0, g.B, S.kin);
+                           db->d_cols, m, db->pitch, d_specs + g.q0, g.B, S.kin);
         FC_HIP(hipGetLastError());
         ps.end(s);
     }

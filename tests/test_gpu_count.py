@@ -388,3 +388,57 @@ def test_concurrent_host_threads_on_separate_streams():
         for i in range(len(parts)):
             for a, b in zip(ref[i], got[i]):
                 assert torch.equal(a, b), i
+
+
+def test_appends_within_and_beyond_the_allocation():
+    """Appends of uneven sizes (1 instance to several tiles): some fit the
+    allocated pitch, some grow it. After every append each strategy, both
+    column stores, batched single assignments, sparse tables and the
+    reducers agree with the oracle on the data so far."""
+    w = synth.bn_family(m=60_000, nq=150)
+    D, ar = w.D, w.arity
+    qs = (w.vars_flat, w.var_off)
+    # pitch (rows allocated per column) after each append: 4096, 4096, 8192, 8192, 12288,
+    # 12288, 32768, 32768, 49152 (grown 1.5x), 49152, 49152 (the scanned extent grows
+    # inside it), 49152, 73728
+    cuts = [3000, 3001, 8001, 8101, 12197, 12204, 32204, 32205, 32800, 33000, 41000, 45000,
+            60_000]
+    rng = np.random.default_rng(5)
+    aq = [rng.choice(w.n, size=int(rng.integers(1, 5)), replace=False) for _ in range(40)]
+    ast = [[int(rng.integers(0, ar[v])) for v in q] for q in aq]
+    with Database(np.ascontiguousarray(D[:, :cuts[0]]), ar) as db:
+        for lo, hi in zip(cuts[:-1], cuts[1:]):
+            db.append(np.ascontiguousarray(D[:, lo:hi]))
+            sub = synth.Workload(w.name, np.ascontiguousarray(D[:, :hi]), ar, w.vars_flat,
+                                 w.var_off, w.reducers)
+            print("after append to m=%d" % hi, flush=True)
+            for packed in (1, 0):
+                t = db.tuning()
+                t["packed_columns"] = packed
+                db.set_tuning(t)
+                for strategy in ("auto", "bitmap", "hist"):
+                    tables, toff = db.count_batch(qs, strategy=strategy)
+                    check_tables(sub, tables, toff)
+            got = db.count_assignments(aq, ast)
+            for q, s_, g in zip(aq, ast, got):
+                assert g == orc.count_assignment(sub.D, ar, q, s_)
+            keys, cnt, _ = db.count_sparse(w.query(3))
+            rk, rc = orc.count_sparse(sub.D, ar, w.query(3))
+            np.testing.assert_array_equal(keys, rk)
+            np.testing.assert_array_equal(cnt, rc)
+            sc, _, _, _ = db.count_reduce([w.query(0)], ("mdl",))
+            ref = orc.score("mdl", orc.count(sub.D, ar, w.query(0)), int(ar[w.query(0)[-1]]), 1.0)
+            assert abs(float(sc["mdl"][0]) - ref) <= 1e-6 * max(1.0, abs(ref))
+
+
+def test_appends_then_pairs():
+    """The all-pairs Gram on bit-vectors that grew through appends equals the
+    oracle's co-occurrence counts."""
+    rng = np.random.default_rng(12)
+    n, m = 90, 50_001
+    D = (rng.random((n, m)) < rng.random((n, 1)) * 0.3).astype(np.uint8)
+    with Database(np.ascontiguousarray(D[:, :7000]), np.full(n, 2, np.uint8)) as db:
+        for lo, hi in ((7000, 7001), (7001, 20_000), (20_000, 21_000), (21_000, 29_000), (29_000, m)):
+            db.append(np.ascontiguousarray(D[:, lo:hi]))
+            _, G, _ = db.pairs(0.01, gram=True)
+            np.testing.assert_array_equal(G.cpu().numpy(), orc.gram(np.ascontiguousarray(D[:, :hi])))
