@@ -278,6 +278,56 @@ int fc_pairs(fc_db *db, const int32_t *items, int32_t ni, double minsup,
              void *stream);
 
 /*
+ * Bottom-up association-rule mining over binary items (Section 4.3), the
+ * whole level-wise search in one call.  Level 1 comes from the marginals,
+ * level 2 from the co-occurrence Gram (as fc_pairs), and every level k >= 3
+ * joins the frequent (k-1)-itemsets that share their first k-2 items, keeps
+ * a candidate only when all its (k-1)-subsets are frequent, and counts the
+ * candidates as batched single-assignment queries Count(X_a = 1 AND ...)
+ * (as fc_count_assignments).  An itemset S is frequent when Count(S)/m >
+ * minsup; a rule S - {X} => X is kept when Count(S)/Count(S - {X}) >
+ * minconf (both binary64).  Itemsets have at most max_size items
+ * (1..FC_MAX_VARS; the paper mines rules of fewer than seven items).
+ *
+ * items   host array of ni distinct variables, each of arity 2 (item a is
+ *         present in an instance when X_a = 1).  Needs bit-vectors.
+ * out     receives a result owned by the caller (fc_arm_free); read it with
+ *         fc_arm_sizes and fc_arm_read.  Synchronises `stream`.
+ * Fails with FC_ERR_INVALID on a bad argument (unknown, repeated or
+ * non-binary item, max_size out of range).
+ */
+typedef struct fc_arm_result fc_arm_result;
+int fc_mine(fc_db *db, const int32_t *items, int32_t ni, double minsup,
+            double minconf, int32_t max_size, fc_arm_result **out, void *stream);
+
+/*
+ * Sizes of a mining result: itemsets, items over all itemsets, rules, and
+ * antecedent items over all rules.
+ */
+int fc_arm_sizes(const fc_arm_result *r, int64_t *n_sets, int64_t *n_set_items,
+                 int64_t *n_rules, int64_t *n_rule_items);
+
+/*
+ * Copies a mining result into host arrays sized by fc_arm_sizes (any
+ * pointer may be NULL to skip that array):
+ *   set_items[n_set_items], set_off[n_sets+1], set_count[n_sets]: itemset i
+ *     is set_items[set_off[i] .. set_off[i+1]) (increasing item ids) with
+ *     Count = set_count[i]; itemsets come level by level, lexicographic
+ *     within a level;
+ *   rule_items[n_rule_items], rule_off[n_rules+1], rule_cons[n_rules],
+ *   rule_support[n_rules], rule_conf[n_rules]: rule j is antecedent
+ *     rule_items[rule_off[j] .. rule_off[j+1]) => rule_cons[j], support
+ *     Count(S)/m, confidence Count(S)/Count(antecedent); rules are ordered by
+ *     antecedent (item by item, a proper prefix first), then consequent.
+ */
+int fc_arm_read(const fc_arm_result *r, int32_t *set_items, int64_t *set_off,
+                int64_t *set_count, int32_t *rule_items, int64_t *rule_off,
+                int32_t *rule_cons, double *rule_support, double *rule_conf);
+
+/* Releases a mining result (NULL is ignored). */
+void fc_arm_free(fc_arm_result *r);
+
+/*
  * Device bytes a batch needs beyond the resident database: tables and
  * scratch of fc_count_reduce with tables == NULL, the work plan, and the
  * staging of host outputs.  Used by callers that admit work by memory.

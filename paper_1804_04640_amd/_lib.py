@@ -33,7 +33,7 @@ FC_RED_MI = 8
 # every symbol the header declares
 EXPORTS = ("fc_db_create", "fc_db_append", "fc_db_destroy", "fc_db_info", "fc_db_marginals", "fc_table_cells",
            "fc_count", "fc_count_assignment", "fc_count_assignments", "fc_count_sparse", "fc_count_sparse_batch", "fc_count_batch", "fc_count_reduce",
-           "fc_score_parent_sets", "fc_pairs",
+           "fc_score_parent_sets", "fc_pairs", "fc_mine", "fc_arm_sizes", "fc_arm_read", "fc_arm_free",
            "fc_batch_footprint", "fc_graph_create", "fc_graph_launch", "fc_graph_destroy",
            "fc_db_get_tuning", "fc_db_set_tuning", "fc_autotune",
            "fc_profile_enable", "fc_profile_read", "fc_last_error")
@@ -120,6 +120,10 @@ def load():
             "fc_score_parent_sets": (ctypes.c_int, [P, i32, P, i32, i32, u32, P, ctypes.c_double,
                                                     P, i64, P]),
             "fc_pairs": (ctypes.c_int, [P, P, i32, ctypes.c_double, P, P, i64, P, P]),
+            "fc_mine": (ctypes.c_int, [P, P, i32, ctypes.c_double, ctypes.c_double, i32, P, P]),
+            "fc_arm_sizes": (ctypes.c_int, [P, P, P, P, P]),
+            "fc_arm_read": (ctypes.c_int, [P, P, P, P, P, P, P, P, P]),
+            "fc_arm_free": (None, [P]),
             "fc_batch_footprint": (ctypes.c_int, [P, P, P, i64, u32, P]),
             "fc_graph_create": (ctypes.c_int, [P, P, P, i64, u32, P, P, P, P, P, u32, P, P]),
             "fc_graph_launch": (ctypes.c_int, [P, P]),
@@ -233,6 +237,29 @@ def fc_pairs(db, items, ni, minsup, gram, out, cap, stream):
     n_out = ctypes.c_int64()
     check(load().fc_pairs(db, items, ni, minsup, gram, out, cap, ctypes.byref(n_out), stream))
     return n_out.value
+
+
+def fc_mine(db, items, ni, minsup, minconf, max_size, stream):
+    h = ctypes.c_void_p()
+    check(load().fc_mine(db, items, ni, minsup, minconf, max_size, ctypes.byref(h), stream))
+    return h.value
+
+
+def fc_arm_sizes(r):
+    a, b, c, d = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    check(load().fc_arm_sizes(r, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                              ctypes.byref(d)))
+    return a.value, b.value, c.value, d.value
+
+
+def fc_arm_read(r, set_items, set_off, set_count, rule_items, rule_off, rule_cons, rule_support,
+                rule_conf):
+    return check(load().fc_arm_read(r, set_items, set_off, set_count, rule_items, rule_off,
+                                    rule_cons, rule_support, rule_conf))
+
+
+def fc_arm_free(r):
+    load().fc_arm_free(r)
 
 
 def fc_batch_footprint(db, vars_flat, var_off, nq, flags):

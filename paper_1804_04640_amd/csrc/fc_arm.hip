@@ -1,0 +1,404 @@
+// Bottom-up association-rule mining over binary items (Section 4.3), the
+// whole level-wise search in the library:
+//
+//   level 1   item supports from the database marginals;
+//   level 2   every pair support at once from the co-occurrence Gram
+//             (fc_pairs, int8 MFMA);
+//   level k   candidates joined from frequent (k-1)-itemsets that share their
+//             first k-2 items, kept when every (k-1)-subset is frequent
+//             (anti-monotonicity), counted in batches of single-assignment
+//             queries Count(X_a = 1 AND ...) (fc_count_assignments: one path
+//             of bit-vector intersections and a popcount each).
+//
+// An itemset S is frequent when Count(S)/m > minsup and a rule S - {X} => X
+// is kept when Count(S)/Count(S - {X}) > minconf, both decided in binary64.
+// Itemsets of a level are held sorted (lexicographic item ids), so every
+// subset lookup is a binary search in the level below.
+#include <algorithm>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "fc_internal.h"
+
+struct fc_arm_result {
+    // itemsets, level by level, lexicographic within a level
+    std::vector<int32_t> set_items;
+    std::vector<int64_t> set_off{0};
+    std::vector<int64_t> set_count;
+    // rules ordered by (antecedent, consequent) as tuples compare
+    std::vector<int32_t> rule_items;
+    std::vector<int64_t> rule_off{0};
+    std::vector<int32_t> rule_cons;
+    std::vector<double> rule_support, rule_conf;
+};
+
+namespace fc {
+namespace {
+
+// One level: n itemsets of k items each, sorted, with their counts.
+struct Level {
+    int32_t k = 0;
+    std::vector<int32_t> items;  // n * k
+    std::vector<int64_t> count;  // n
+    int64_t size() const { return (int64_t)count.size(); }
+    const int32_t *at(int64_t i) const { return items.data() + i * k; }
+    // index of the itemset equal to s (k items), or -1
+    int64_t find(const int32_t *s) const {
+        int64_t lo = 0, hi = size();
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            const int c = cmp(at(mid), s);
+            if (c == 0) return mid;
+            if (c < 0) lo = mid + 1; else hi = mid;
+        }
+        return -1;
+    }
+    int cmp(const int32_t *a, const int32_t *b) const {
+        for (int32_t t = 0; t < k; ++t)
+            if (a[t] != b[t]) return a[t] < b[t] ? -1 : 1;
+        return 0;
+    }
+};
+
+bool frequent(int64_t count, int64_t m, double minsup) {
+    return m > 0 && (double)count / (double)m > minsup;
+}
+
+// Apriori join of `prev` (sorted (k-1)-itemsets): pairs a < b of a block that
+// shares the first k-2 items give prefix + {last_a, last_b}; a candidate is
+// kept when each of its (k-1)-subsets that drops one of the prefix items is
+// in `prev` (the two that drop a last item are the joined pair itself).
+// Blocks are split over host threads; the output stays lexicographic.
+std::vector<int32_t> candidates(const Level &prev) {
+    const int32_t k1 = prev.k, k = k1 + 1;
+    const int64_t n = prev.size();
+    std::vector<int64_t> blocks;  // block starts, plus n
+    for (int64_t i = 0; i < n;) {
+        blocks.push_back(i);
+        int64_t j = i + 1;
+        while (j < n && std::equal(prev.at(i), prev.at(i) + (k1 - 1), prev.at(j))) ++j;
+        i = j;
+    }
+    blocks.push_back(n);
+    const int64_t nb = (int64_t)blocks.size() - 1;
+    unsigned hw = std::thread::hardware_concurrency();
+    const int64_t T = std::max<int64_t>(1, std::min<int64_t>({(int64_t)std::min(16u, hw ? hw : 1u),
+                                                             nb, n / 2048 + 1}));
+    std::vector<std::vector<int32_t>> part((size_t)T);
+    auto work = [&](int64_t t) {
+        std::vector<int32_t> &out = part[(size_t)t];
+        std::vector<int32_t> cand((size_t)k), sub((size_t)k1);
+        for (int64_t bi = nb * t / T; bi < nb * (t + 1) / T; ++bi) {
+            const int64_t lo = blocks[(size_t)bi], hi = blocks[(size_t)bi + 1];
+            for (int64_t a = lo; a < hi; ++a)
+                for (int64_t b = a + 1; b < hi; ++b) {
+                    std::copy(prev.at(a), prev.at(a) + k1, cand.begin());
+                    cand[(size_t)k1] = prev.at(b)[k1 - 1];
+                    bool ok = true;
+                    for (int32_t x = 0; ok && x < k - 2; ++x) {
+                        int32_t u = 0;
+                        for (int32_t t2 = 0; t2 < k; ++t2)
+                            if (t2 != x) sub[(size_t)u++] = cand[(size_t)t2];
+                        ok = prev.find(sub.data()) >= 0;
+                    }
+                    if (ok) out.insert(out.end(), cand.begin(), cand.end());
+                }
+        }
+    };
+    if (T == 1) {
+        work(0);
+    } else {
+        std::vector<std::thread> th;
+        for (int64_t t = 0; t < T; ++t) th.emplace_back(work, t);
+        for (auto &x : th) x.join();
+    }
+    std::vector<int32_t> all;
+    for (auto &p : part) all.insert(all.end(), p.begin(), p.end());
+    return all;
+}
+
+}  // namespace
+}  // namespace fc
+
+using namespace fc;
+
+extern "C" int fc_mine(fc_db *db, const int32_t *items, int32_t ni, double minsup, double minconf,
+                       int32_t max_size, fc_arm_result **out, void *stream) {
+    clear_error();
+    if (!db || !out || ni < 0 || (ni > 0 && !items) || max_size < 1) {
+        set_error("fc_mine: need a database, items (ni >= 0), max_size >= 1 and out");
+        return FC_ERR_INVALID;
+    }
+    if (max_size > FC_MAX_VARS) {
+        set_error("fc_mine: itemsets of at most %d items (max_size = %d)", FC_MAX_VARS, max_size);
+        return FC_ERR_INVALID;
+    }
+    *out = nullptr;
+    std::vector<uint8_t> seen((size_t)db->n, 0);
+    for (int32_t i = 0; i < ni; ++i) {
+        const int32_t v = items[i];
+        if (v < 0 || v >= db->n) {
+            set_error("fc_mine: item %d out of range [0, %d)", v, db->n);
+            return FC_ERR_INVALID;
+        }
+        if (db->arity[(size_t)v] != 2) {
+            set_error("fc_mine: item %d is not binary (arity %d)", v, db->arity[(size_t)v]);
+            return FC_ERR_INVALID;
+        }
+        if (seen[(size_t)v]++) {
+            set_error("fc_mine: item %d appears twice", v);
+            return FC_ERR_INVALID;
+        }
+    }
+    auto *R = new (std::nothrow) fc_arm_result();
+    if (!R) {
+        set_error("fc_mine: host allocation failed");
+        return FC_ERR_NOMEM;
+    }
+    struct Guard {
+        fc_arm_result *r;
+        ~Guard() { delete r; }
+    } guard{R};
+    const int64_t m = db->m;
+    std::vector<Level> levels;
+
+    // level 1: supports from the marginals (state 1 of each item)
+    Level L1;
+    L1.k = 1;
+    {
+        std::vector<int32_t> it(items, items + ni);
+        std::sort(it.begin(), it.end());
+        for (int32_t v : it) {
+            const int64_t c = db->marg[(size_t)db->state_off[(size_t)v] + 1];
+            if (frequent(c, m, minsup)) {
+                L1.items.push_back(v);
+                L1.count.push_back(c);
+            }
+        }
+    }
+    levels.push_back(std::move(L1));
+
+    // level 2: the Gram's pair records over the frequent items
+    if (max_size >= 2 && levels[0].size() >= 2) {
+        const Level &p = levels[0];
+        const int32_t n1 = (int32_t)p.size();
+        const int64_t cap = (int64_t)n1 * (n1 - 1) / 2;
+        std::vector<fc_pair_rec> rec((size_t)std::max<int64_t>(cap, 1));
+        int64_t n_out = 0;
+        const int rc = fc_pairs(db, p.items.data(), n1, minsup, nullptr, rec.data(), cap, &n_out,
+                                stream);
+        if (rc != FC_OK) return rc;
+        Level L2;
+        L2.k = 2;
+        for (int64_t r = 0; r < std::min(n_out, cap); ++r) {  // ordered by (a, b), a < b
+            L2.items.push_back(p.items[(size_t)rec[(size_t)r].a]);
+            L2.items.push_back(p.items[(size_t)rec[(size_t)r].b]);
+            L2.count.push_back(rec[(size_t)r].n_ab);
+        }
+        levels.push_back(std::move(L2));
+    }
+
+    // levels 3..max_size: join, prune, count in batches, keep the frequent
+    constexpr int64_t kBatch = int64_t(1) << 20;
+    while ((int32_t)levels.size() >= 2 && (int32_t)levels.size() < max_size &&
+           levels.back().size() >= 2) {
+        const Level &prev = levels.back();
+        const int32_t k = prev.k + 1;
+        const std::vector<int32_t> cand = candidates(prev);
+        const int64_t nc = (int64_t)cand.size() / k;
+        Level L;
+        L.k = k;
+        std::vector<int64_t> off, cnt;
+        std::vector<uint8_t> ones;
+        for (int64_t lo = 0; lo < nc; lo += kBatch) {
+            const int64_t nb = std::min(kBatch, nc - lo);
+            off.resize((size_t)nb + 1);
+            for (int64_t i = 0; i <= nb; ++i) off[(size_t)i] = i * k;
+            ones.assign((size_t)(nb * k), 1);
+            cnt.assign((size_t)nb, 0);
+            const int rc = fc_count_assignments(db, cand.data() + lo * k, off.data(), ones.data(),
+                                                nb, cnt.data(), stream);
+            if (rc != FC_OK) return rc;
+            for (int64_t i = 0; i < nb; ++i)
+                if (frequent(cnt[(size_t)i], m, minsup)) {
+                    L.items.insert(L.items.end(), cand.begin() + (lo + i) * k,
+                                   cand.begin() + (lo + i + 1) * k);
+                    L.count.push_back(cnt[(size_t)i]);
+                }
+        }
+        if (L.size() == 0) break;
+        levels.push_back(std::move(L));
+    }
+
+    // itemsets, level by level
+    for (const Level &L : levels) {
+        for (int64_t i = 0; i < L.size(); ++i) {
+            R->set_items.insert(R->set_items.end(), L.at(i), L.at(i) + L.k);
+            R->set_off.push_back((int64_t)R->set_items.size());
+            R->set_count.push_back(L.count[(size_t)i]);
+        }
+    }
+    // Rank of every itemset in tuple order (a proper prefix first): the
+    // pre-order of the trie whose children of a (k-1)-itemset are the
+    // k-itemsets extending it by one larger item -- a contiguous run of level
+    // k, found by one merge of two sorted levels.
+    const int32_t nl = (int32_t)levels.size();
+    std::vector<std::vector<int64_t>> child0((size_t)nl), rank((size_t)nl);
+    for (int32_t li = 0; li < nl; ++li) {
+        const int64_t n = levels[(size_t)li].size();
+        rank[(size_t)li].assign((size_t)n, 0);
+        child0[(size_t)li].assign((size_t)n + 1, 0);
+        if (li + 1 < nl) {
+            const Level &up = levels[(size_t)li + 1], &L = levels[(size_t)li];
+            int64_t c = 0;
+            for (int64_t p = 0; p < n; ++p) {
+                child0[(size_t)li][(size_t)p] = c;
+                while (c < up.size() && std::equal(up.at(c), up.at(c) + L.k, L.at(p))) ++c;
+            }
+            child0[(size_t)li][(size_t)n] = c;
+        }
+    }
+    {
+        int64_t next = 0;
+        std::vector<std::pair<int32_t, int64_t>> stack;  // (level, index)
+        for (int64_t i = levels[0].size() - 1; i >= 0; --i) stack.push_back({0, i});
+        while (!stack.empty()) {
+            const auto [li, i] = stack.back();
+            stack.pop_back();
+            rank[(size_t)li][(size_t)i] = next++;
+            if (li + 1 < nl)
+                for (int64_t c = child0[(size_t)li][(size_t)i + 1] - 1;
+                     c >= child0[(size_t)li][(size_t)i]; --c)
+                    stack.push_back({li + 1, c});
+        }
+    }
+    // rules S - {X} => X of every frequent S with |S| >= 2, generated on host
+    // threads over the itemsets of each level
+    struct Rule {
+        int64_t key;  // rank of the antecedent
+        int32_t li, i, x;
+        double conf;
+    };
+    std::vector<Rule> rules;
+    for (int32_t li = 1; li < nl; ++li) {
+        const Level &L = levels[(size_t)li], &below = levels[(size_t)li - 1];
+        const int64_t n = L.size();
+        unsigned hw = std::thread::hardware_concurrency();
+        const int64_t T = std::max<int64_t>(1, std::min<int64_t>((int64_t)std::min(16u, hw ? hw : 1u),
+                                                                 n / 4096 + 1));
+        std::vector<std::vector<Rule>> part((size_t)T);
+        std::vector<int> bad((size_t)T, 0);
+        auto work = [&](int64_t t) {
+            int32_t ante[FC_MAX_VARS];
+            for (int64_t i = n * t / T; i < n * (t + 1) / T; ++i) {
+                const int32_t *sv = L.at(i);
+                const int64_t cnt = L.count[(size_t)i];
+                for (int32_t x = 0; x < L.k; ++x) {
+                    int32_t u = 0;
+                    for (int32_t t2 = 0; t2 < L.k; ++t2)
+                        if (t2 != x) ante[u++] = sv[t2];
+                    const int64_t j = below.find(ante);
+                    if (j < 0) {  // anti-monotonicity makes this impossible
+                        bad[(size_t)t] = 1;
+                        return;
+                    }
+                    const double conf = (double)cnt / (double)below.count[(size_t)j];
+                    if (conf > minconf)
+                        part[(size_t)t].push_back({rank[(size_t)li - 1][(size_t)j], li, (int32_t)i, x,
+                                                   conf});
+                }
+            }
+        };
+        if (T == 1) {
+            work(0);
+        } else {
+            std::vector<std::thread> th;
+            for (int64_t t = 0; t < T; ++t) th.emplace_back(work, t);
+            for (auto &x : th) x.join();
+        }
+        for (int64_t t = 0; t < T; ++t) {
+            if (bad[(size_t)t]) {
+                set_error("fc_mine: a subset of a frequent itemset is missing");
+                return FC_ERR_DEVICE;
+            }
+            rules.insert(rules.end(), part[(size_t)t].begin(), part[(size_t)t].end());
+        }
+    }
+    // order: counting sort by antecedent rank, then by consequent within one
+    // antecedent (a handful of rules each)
+    int64_t nsets = 0;
+    for (const Level &L : levels) nsets += L.size();
+    std::vector<int64_t> start((size_t)nsets + 1, 0);
+    for (const Rule &r : rules) ++start[(size_t)r.key + 1];
+    for (int64_t i = 0; i < nsets; ++i) start[(size_t)i + 1] += start[(size_t)i];
+    std::vector<int64_t> ord(rules.size()), fill(start.begin(), start.end() - 1);
+    for (int64_t q = 0; q < (int64_t)rules.size(); ++q)
+        ord[(size_t)fill[(size_t)rules[(size_t)q].key]++] = q;
+    auto cons_of = [&](int64_t q) {
+        const Rule &r = rules[(size_t)q];
+        return levels[(size_t)r.li].at(r.i)[r.x];
+    };
+    for (int64_t g = 0; g < nsets; ++g)
+        if (start[(size_t)g + 1] - start[(size_t)g] > 1)
+            std::sort(ord.begin() + start[(size_t)g], ord.begin() + start[(size_t)g + 1],
+                      [&](int64_t a, int64_t b) { return cons_of(a) < cons_of(b); });
+    const int64_t nr = (int64_t)rules.size();
+    R->rule_cons.resize((size_t)nr);
+    R->rule_support.resize((size_t)nr);
+    R->rule_conf.resize((size_t)nr);
+    R->rule_off.resize((size_t)nr + 1);
+    R->rule_off[0] = 0;
+    for (int64_t q = 0; q < nr; ++q) {
+        const Rule &r = rules[(size_t)ord[(size_t)q]];
+        const Level &L = levels[(size_t)r.li];
+        const int32_t *sv = L.at(r.i);
+        for (int32_t t = 0; t < L.k; ++t)
+            if (t != r.x) R->rule_items.push_back(sv[t]);
+        R->rule_off[(size_t)q + 1] = (int64_t)R->rule_items.size();
+        R->rule_cons[(size_t)q] = sv[r.x];
+        R->rule_support[(size_t)q] = (double)L.count[(size_t)r.i] / (double)m;
+        R->rule_conf[(size_t)q] = r.conf;
+    }
+    *out = R;
+    guard.r = nullptr;
+    return FC_OK;
+}
+
+extern "C" int fc_arm_sizes(const fc_arm_result *r, int64_t *n_sets, int64_t *n_set_items,
+                            int64_t *n_rules, int64_t *n_rule_items) {
+    clear_error();
+    if (!r || !n_sets || !n_set_items || !n_rules || !n_rule_items) {
+        set_error("fc_arm_sizes: need a result and four outputs");
+        return FC_ERR_INVALID;
+    }
+    *n_sets = (int64_t)r->set_count.size();
+    *n_set_items = (int64_t)r->set_items.size();
+    *n_rules = (int64_t)r->rule_cons.size();
+    *n_rule_items = (int64_t)r->rule_items.size();
+    return FC_OK;
+}
+
+extern "C" int fc_arm_read(const fc_arm_result *r, int32_t *set_items, int64_t *set_off,
+                           int64_t *set_count, int32_t *rule_items, int64_t *rule_off,
+                           int32_t *rule_cons, double *rule_support, double *rule_conf) {
+    clear_error();
+    if (!r) {
+        set_error("fc_arm_read: need a result");
+        return FC_ERR_INVALID;
+    }
+    auto put = [](auto *dst, const auto &v) {
+        if (dst && !v.empty()) std::memcpy(dst, v.data(), sizeof(v[0]) * v.size());
+    };
+    put(set_items, r->set_items);
+    put(set_off, r->set_off);
+    put(set_count, r->set_count);
+    put(rule_items, r->rule_items);
+    put(rule_off, r->rule_off);
+    put(rule_cons, r->rule_cons);
+    put(rule_support, r->rule_support);
+    put(rule_conf, r->rule_conf);
+    return FC_OK;
+}
+
+extern "C" void fc_arm_free(fc_arm_result *r) { delete r; }

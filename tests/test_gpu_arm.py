@@ -44,6 +44,33 @@ def test_mining_matches_exhaustive_definition():
     assert max(len(s) for s in freq) >= 4
 
 
+def test_mining_edge_cases_and_item_subsets():
+    from paper_1804_04640_amd import _lib
+    rng = np.random.default_rng(21)
+    n, m = 12, 9_001
+    D = (rng.random((n, m)) < rng.random((n, 1)) * 0.6).astype(np.uint8)
+    ar = np.full(n, 2, np.uint8)
+    ar[11] = 3
+    D[11] = rng.integers(0, 3, size=m)
+    sub = [0, 3, 4, 7, 9, 10]
+    with Database(D, ar) as db:
+        for max_size in (1, 2, 4):
+            freq, rules = arm.mine(db, minsup=0.02, minconf=0.2, items=sub, max_size=max_size)
+            ref_freq, ref_rules = orc.arm_bruteforce(D[sub], 0.02, 0.2, max_size=max_size)
+            remap = lambda t: tuple(sub[i] for i in t)
+            assert freq == {remap(s): c for s, c in ref_freq.items()}
+            assert rules == sorted((remap(a), sub[x], sp, cf) for a, x, sp, cf in ref_rules)
+        freq, rules = arm.mine(db, minsup=1.0, minconf=0.0, items=sub)
+        assert freq == {} and rules == []
+        freq, rules = arm.mine(db, minsup=0.0, minconf=1.0, items=[])
+        assert freq == {} and rules == []
+        for bad in ([0, 11], [2, 2], [0, 40]):
+            with pytest.raises(_lib.FastcountError):
+                arm.mine(db, minsup=0.1, minconf=0.1, items=bad)
+        with pytest.raises(_lib.FastcountError):
+            arm.mine(db, minsup=0.1, minconf=0.1, items=sub, max_size=9)
+
+
 def test_mining_on_planted_transactions():
     w = synth.all_pairs(m=1 << 16, n=64, groups=4)
     with Database(w.D, w.arity) as db:
