@@ -495,6 +495,8 @@ def main():
                     help="JSON tuning to install instead (keys of fc_tuning)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON file of autotuner results to reuse / fill")
+    ap.add_argument("--graph", type=int, default=1,
+                    help="also time the batch captured once into a hipGraph and replayed")
     ap.add_argument("--serve", action="store_true",
                     help="serving mode (hill-climbing batches, Poisson arrivals, p50/p99)")
     ap.add_argument("--serve-requests", type=int, default=1000)
@@ -622,6 +624,28 @@ def main():
                          "sample": "first %d queries, one call each, synchronised" % n,
                          "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99)}
 
+        # the same batch captured once into a hipGraph and replayed: every
+        # device step of the path, no host planning per step
+        graph = None
+        if args.graph:
+            g = db.graph(q, reducers, ess=w.ess, stream=stream)
+            g.replay(stream)
+            stream.synchronize()
+            gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(args.steps)]
+            for a, b in gev:
+                a.record(stream)
+                g.replay(stream)
+                b.record(stream)
+            stream.synchronize()
+            g_ms = [a.elapsed_time(b) for a, b in gev]
+            same = bool(torch.equal(g.scores[:scores.numel()], scores))
+            g.close()
+            gm = float(np.mean(g_ms))
+            graph = {"ms_per_step": gm, "value": rows / (gm * 1e-3),
+                     "p50_ms": percentile(g_ms, 50), "p99_ms": percentile(g_ms, 99),
+                     "scores_equal_eager": same}
+
     ms = float(np.mean(step_ms))
     value = rows / (ms * 1e-3)
     # dominant kernel: the one with the largest summed time
@@ -664,6 +688,7 @@ def main():
                     "kernels": {k: {"launches": v["launches"], "avg_us": 1e3 * v["ms"] / v["launches"],
                                     "share": v["ms"] / sum(x["ms"] for x in prof.values())}
                                 for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}},
+        "graph_replay": graph,
         "per_query": per_query,
         "batched_vs_per_query": (value / per_query["value"]) if per_query else None,
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved,
