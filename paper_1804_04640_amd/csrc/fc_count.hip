@@ -1538,39 +1538,53 @@ static int enqueue_batch(fc_db *db, const Plan &P, const Image &I, void *dimg, i
 
 // Runs a whole batch: one plan upload, then the device steps.
 // tables: device buffer of P.total_cells cells.
+// The plan image, and the tables when `tables` is NULL (consumed by the
+// reducers), live in a device workspace of the handle: released in stream
+// order after the last launch that reads them.
 static int run_batch(fc_db *db, Plan &P, int32_t *tables, uint32_t reducers, double ess,
                      float *scores, float *err, hipStream_t s) {
     ensure_attrs();
     Image I;
     make_image(db, P, reducers, I);
-    DevBuf dimg;
-    FC_HIP(dimg.alloc(I.bytes, s));
+    const size_t img = (I.bytes + 255) & ~(size_t)255;
+    const size_t tbytes = tables ? 0 : sizeof(int32_t) * (size_t)std::max<int64_t>(P.total_cells, 1);
+    Workspace *w = workspace_acquire(db, img + tbytes, s);
+    if (!w) {
+        set_error("device workspace of %zu bytes could not be allocated", img + tbytes);
+        return FC_ERR_NOMEM;
+    }
+    struct Release {
+        fc_db *db;
+        Workspace *w;
+        hipStream_t s;
+        ~Release() { workspace_release(db, w, s); }
+    } release{db, w, s};
+    void *dimg = w->p;
+    if (!tables) tables = (int32_t *)((char *)w->p + img);
     Staging *st = staging_acquire(I.bytes);
     if (!st) {
         set_error("pinned staging allocation of %zu bytes failed", I.bytes);
         return FC_ERR_NOMEM;
     }
     fill_image(P, I, st->host);
-    hipError_t e = hipMemcpyAsync(dimg.p, st->host, I.bytes, hipMemcpyHostToDevice, s);
+    hipError_t e = hipMemcpyAsync(dimg, st->host, I.bytes, hipMemcpyHostToDevice, s);
     staging_release(st, s);
     if (e != hipSuccess) {
         set_error("plan upload failed: %s", hipGetErrorString(e));
         return FC_ERR_DEVICE;
     }
-    return enqueue_batch(db, P, I, dimg.p, tables, reducers, ess, scores, err, s);
+    return enqueue_batch(db, P, I, dimg, tables, reducers, ess, scores, err, s);
 }
 
 // Counts and reduces a validated-on-entry batch into device score buffers
 // ([slot][nq], slot = set bits of `reducers` in ascending order); the tables
-// live in stream-ordered scratch.  Used by the native drivers.
+// live in a workspace of the handle.  Used by the native drivers.
 int count_reduce_device(fc_db *db, const int32_t *vars_flat, const int64_t *var_off, int64_t nq,
                         uint32_t reducers, double ess, float *scores, hipStream_t s) {
     Plan P;
     int rc = build_plan(db, vars_flat, var_off, nq, nullptr, FC_STRAT_AUTO, true, P);
     if (rc || nq == 0) return rc;
-    DevBuf dt;
-    FC_HIP(dt.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(P.total_cells, 1), s));
-    return run_batch(db, P, (int32_t *)dt.p, reducers, ess, scores, nullptr, s);
+    return run_batch(db, P, nullptr, reducers, ess, scores, nullptr, s);
 }
 
 }  // namespace fc
@@ -1670,11 +1684,11 @@ extern "C" int fc_count_reduce(fc_db *db, const int32_t *vars_flat, const int64_
     const bool sdev = is_device_ptr(scores);
     const bool edev = err && is_device_ptr(err);
     DevBuf dt, ds, de;
-    int32_t *t = tables;
-    if (!tdev) {
+    int32_t *t = tables;  // NULL: the tables live in run_batch's workspace
+    if (tables && !tdev) {
         FC_HIP(dt.alloc(sizeof(int32_t) * (size_t)P.total_cells, s));
         t = (int32_t *)dt.p;
-        if (tables && !P.packed)
+        if (!P.packed)
             FC_HIP(hipMemcpyAsync(t, tables, sizeof(int32_t) * (size_t)P.total_cells,
                                   hipMemcpyHostToDevice, s));
     }

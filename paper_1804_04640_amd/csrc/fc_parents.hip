@@ -199,25 +199,35 @@ extern "C" int fc_score_parent_sets(fc_db *db, int32_t child, const int32_t *can
         for (size_t i = 0; i < off.size(); ++i) off[i] = (int64_t)i * (size + 1);
         const int64_t nkept = (int64_t)idx.size();
         if (nkept == 0) continue;
-        DevBuf dpart, didx;
-        FC_HIP(dpart.alloc(sizeof(float) * (size_t)nred * (size_t)nkept, s));
-        FC_HIP(didx.alloc(sizeof(int64_t) * (size_t)nkept, s));
+        // the chunk's scores and set indices in a workspace of the handle
+        const size_t pbytes = (sizeof(float) * (size_t)nred * (size_t)nkept + 255) & ~(size_t)255;
+        Workspace *w = workspace_acquire(db, pbytes + sizeof(int64_t) * (size_t)nkept, s);
+        if (!w) {
+            set_error("fc_score_parent_sets: device workspace could not be allocated");
+            return FC_ERR_NOMEM;
+        }
+        struct Release {
+            fc_db *db;
+            Workspace *w;
+            hipStream_t s;
+            ~Release() { workspace_release(db, w, s); }
+        } release{db, w, s};
+        float *dpart = (float *)w->p;
+        int64_t *didx = (int64_t *)((char *)w->p + pbytes);
         Staging *st = staging_acquire(sizeof(int64_t) * (size_t)nkept);
         if (!st) {
             set_error("fc_score_parent_sets: pinned staging allocation failed");
             return FC_ERR_NOMEM;
         }
         std::memcpy(st->host, idx.data(), sizeof(int64_t) * (size_t)nkept);
-        const hipError_t e = hipMemcpyAsync(didx.p, st->host, sizeof(int64_t) * (size_t)nkept,
+        const hipError_t e = hipMemcpyAsync(didx, st->host, sizeof(int64_t) * (size_t)nkept,
                                             hipMemcpyHostToDevice, s);
         staging_release(st, s);
         FC_HIP(e);
-        int rc = count_reduce_device(db, flat.data(), off.data(), nkept, reducers, ess,
-                                     (float *)dpart.p, s);
+        int rc = count_reduce_device(db, flat.data(), off.data(), nkept, reducers, ess, dpart, s);
         if (rc) return rc;
         hipLaunchKernelGGL(k_scatter_scores, dim3(grid_for(nkept * nred)), dim3(256), 0, s,
-                           (const float *)dpart.p, (const int64_t *)didx.p, nkept, nred, nsets,
-                           out);
+                           (const float *)dpart, (const int64_t *)didx, nkept, nred, nsets, out);
         FC_HIP(hipGetLastError());
     }
     if (!sdev) {
