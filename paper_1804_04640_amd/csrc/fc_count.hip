@@ -2135,12 +2135,25 @@ extern "C" int fc_count_assignments(fc_db *db, const int32_t *vars_flat, const i
     hipStream_t s = (hipStream_t)stream;
     FC_HIP(hipSetDevice(db->device));
     const bool cdev = is_device_ptr(counts);
-    DevBuf dout, dq;
-    unsigned long long *out = (unsigned long long *)counts;
-    if (!cdev) {
-        FC_HIP(dout.alloc(sizeof(int64_t) * (size_t)nq, s));
-        out = (unsigned long long *)dout.p;
+    // one workspace of the handle: host-bound counts, then the descriptors
+    const size_t nv = (size_t)var_off[nq];
+    const size_t obytes = cdev ? 0 : ((sizeof(int64_t) * (size_t)nq + 255) & ~(size_t)255);
+    const size_t qbytes = db->d_bits ? sizeof(ADesc) * (size_t)nq
+                                     : sizeof(int32_t) * nv + sizeof(int64_t) * ((size_t)nq + 1) + nv;
+    Workspace *w = workspace_acquire(db, obytes + qbytes, s);
+    if (!w) {
+        set_error("fc_count_assignments: device workspace could not be allocated");
+        return FC_ERR_NOMEM;
     }
+    struct Release {
+        fc_db *db;
+        Workspace *w;
+        hipStream_t s;
+        ~Release() { workspace_release(db, w, s); }
+    } release{db, w, s};
+    void *dq = (char *)w->p + obytes;
+    unsigned long long *out = (unsigned long long *)counts;
+    if (!cdev) out = (unsigned long long *)w->p;
     FC_HIP(fill_zero_i32((int32_t *)out, 2 * nq, s));
     // enough workgroups, chunks a multiple of 8 (XCD order), >= 64K instances each
     const int64_t tiles = db->m_pad / kTileRows;
@@ -2161,44 +2174,40 @@ extern "C" int fc_count_assignments(fc_db *db, const int32_t *vars_flat, const i
                     d.row[t] = db->state_off[v] + states_flat[var_off[i] + t];
                 }
             }
-            FC_HIP(dq.alloc(sizeof(ADesc) * (size_t)nq, s));
             Staging *st = staging_acquire(sizeof(ADesc) * (size_t)nq);
             if (!st) {
                 set_error("pinned staging allocation failed");
                 return FC_ERR_NOMEM;
             }
             std::memcpy(st->host, h.data(), sizeof(ADesc) * (size_t)nq);
-            hipError_t e = hipMemcpyAsync(dq.p, st->host, sizeof(ADesc) * (size_t)nq,
+            hipError_t e = hipMemcpyAsync(dq, st->host, sizeof(ADesc) * (size_t)nq,
                                           hipMemcpyHostToDevice, s);
             staging_release(st, s);
             FC_HIP(e);
             hipLaunchKernelGGL(k_assign_batch, dim3((unsigned)(nq * ch)), dim3(kBlock), 0, s,
-                               db->d_bits, db->words, db->pitch / 64, (const ADesc *)dq.p, (int32_t)nq,
+                               db->d_bits, db->words, db->pitch / 64, (const ADesc *)dq, (int32_t)nq,
                                (int32_t)ch, out);
         } else {
-            const size_t nv = (size_t)var_off[nq];
-            const size_t bytes = sizeof(int32_t) * nv + sizeof(int64_t) * ((size_t)nq + 1) + nv;
-            FC_HIP(dq.alloc(bytes, s));
+            const size_t bytes = qbytes;
             Staging *st = staging_acquire(bytes);
             if (!st) {
                 set_error("pinned staging allocation failed");
                 return FC_ERR_NOMEM;
             }
+            // var_off first (8-byte aligned), then the variables, then the states
+            const size_t ob = sizeof(int64_t) * ((size_t)nq + 1), vb = sizeof(int32_t) * nv;
             char *hp = (char *)st->host;
-            std::memcpy(hp, vars_flat, sizeof(int32_t) * nv);
-            std::memcpy(hp + sizeof(int32_t) * nv, var_off, sizeof(int64_t) * ((size_t)nq + 1));
-            std::memcpy(hp + sizeof(int32_t) * nv + sizeof(int64_t) * ((size_t)nq + 1),
-                        states_flat, nv);
-            hipError_t e = hipMemcpyAsync(dq.p, st->host, bytes, hipMemcpyHostToDevice, s);
+            std::memcpy(hp, var_off, ob);
+            std::memcpy(hp + ob, vars_flat, vb);
+            std::memcpy(hp + ob + vb, states_flat, nv);
+            hipError_t e = hipMemcpyAsync(dq, st->host, bytes, hipMemcpyHostToDevice, s);
             staging_release(st, s);
             FC_HIP(e);
-            char *dp = (char *)dq.p;
+            char *dp = (char *)dq;
             hipLaunchKernelGGL(k_assign_batch_cols, dim3((unsigned)(nq * ch)), dim3(kBlock), 0, s,
-                               db->d_cols, db->m, db->pitch, (const int32_t *)dp,
-                               (const int64_t *)(dp + sizeof(int32_t) * nv),
-                               (const uint8_t *)(dp + sizeof(int32_t) * nv +
-                                                 sizeof(int64_t) * ((size_t)nq + 1)),
-                               (int32_t)nq, (int32_t)ch, out);
+                               db->d_cols, db->m, db->pitch, (const int32_t *)(dp + ob),
+                               (const int64_t *)dp, (const uint8_t *)(dp + ob + vb), (int32_t)nq,
+                               (int32_t)ch, out);
         }
         FC_HIP(hipGetLastError());
         ps.end(s);
