@@ -171,10 +171,23 @@ Workspace *workspace_acquire(fc_db *db, size_t bytes, hipStream_t s) {
         db->device_bytes += (int64_t)cap;
     }
     if (!w->done && hipEventCreateWithFlags(&w->done, hipEventDisableTiming) != hipSuccess) {
+        // without its event a workspace cannot be handed over in stream order
         (void)hipGetLastError();
         w->done = nullptr;
+        (void)hipFree(w->p);
+        db->device_bytes -= (int64_t)w->cap;
+        delete w;
+        std::lock_guard<std::mutex> lk(db->ws_mu);
+        --db->ws_count;
+        return nullptr;
     }
-    if (w->done) (void)hipStreamWaitEvent(s, w->done, 0);
+    if (hipStreamWaitEvent(s, w->done, 0) != hipSuccess) {
+        // back to the idle list untouched: its event still marks the last use
+        (void)hipGetLastError();
+        std::lock_guard<std::mutex> lk(db->ws_mu);
+        db->ws_free.push_back(w);
+        return nullptr;
+    }
     return w;
 }
 
