@@ -310,13 +310,30 @@ extern "C" int fc_pairs(fc_db *db, const int32_t *items, int32_t ni, double mins
     if (db->m == 0) nmin = 1;  // no instance: no pair has support
     hipStream_t s = (hipStream_t)stream;
     FC_HIP(hipSetDevice(db->device));
-    DevBuf dC, dRow, dCnt, dOff, dRec, dG;
+    // the Gram, the row items, the per-row counts and offsets in one
+    // workspace of the handle; device copies of host outputs separately
+    DevBuf dRec, dG;
     const int64_t ldc = np;
-    FC_HIP(dC.alloc(sizeof(int32_t) * (size_t)np * (size_t)np, s));
-    FC_HIP(dRow.alloc(sizeof(int32_t) * (size_t)np, s));
-    FC_HIP(hipMemcpyAsync(dRow.p, rowidx.data(), sizeof(int32_t) * (size_t)np,
+    const size_t cb = (sizeof(int32_t) * (size_t)np * (size_t)np + 255) & ~(size_t)255;
+    const size_t rb = (sizeof(int32_t) * (size_t)np + 255) & ~(size_t)255;
+    const size_t nb = (sizeof(int32_t) * (size_t)ni + 255) & ~(size_t)255;
+    Workspace *w = workspace_acquire(db, cb + rb + nb + sizeof(int64_t) * (size_t)ni, s);
+    if (!w) {
+        set_error("fc_pairs: device workspace could not be allocated");
+        return FC_ERR_NOMEM;
+    }
+    struct Release {
+        fc_db *db;
+        Workspace *w;
+        hipStream_t s;
+        ~Release() { workspace_release(db, w, s); }
+    } release{db, w, s};
+    int32_t *C = (int32_t *)w->p;
+    int32_t *d_row = (int32_t *)((char *)w->p + cb);
+    int32_t *d_cnt = (int32_t *)((char *)w->p + cb + rb);
+    int64_t *d_off = (int64_t *)((char *)w->p + cb + rb + nb);
+    FC_HIP(hipMemcpyAsync(d_row, rowidx.data(), sizeof(int32_t) * (size_t)np,
                           hipMemcpyHostToDevice, s));
-    int32_t *C = (int32_t *)dC.p;
     FC_HIP(fill_zero_i32(C, (int64_t)np * np, s));
     int32_t npairs = 0;  // (row block, column block) pairs reaching the upper triangle
     for (int32_t I = 0; I < nrb; ++I) npairs += ncb - I / 2;
@@ -330,20 +347,19 @@ extern "C" int fc_pairs(fc_db *db, const int32_t *items, int32_t ni, double mins
         const double ops = 2.0 * (double)db->m * (double)ni * (double)(ni + 1) / 2.0;
         ProfScope ps("k_gram", s, 0.0, ops);
         hipLaunchKernelGGL(k_gram, dim3((unsigned)(npairs * splits)), dim3(256), 0, s,
-                           db->d_bits, db->words, db->pitch / 64, (const int32_t *)dRow.p, nrb, ncb,
+                           db->d_bits, db->words, db->pitch / 64, (const int32_t *)d_row, nrb, ncb,
                            npairs,
                            (int32_t)splits, C, (int32_t)ldc);
         FC_HIP(hipGetLastError());
         ps.end(s);
     }
     // records: per-row counts -> offsets (host) -> ordered writes
-    FC_HIP(dCnt.alloc(sizeof(int32_t) * (size_t)ni, s));
     hipLaunchKernelGGL(k_pair_count, dim3((unsigned)((ni + 3) / 4)), dim3(256), 0, s, C,
                        (int32_t)ldc, ni, (int32_t)std::min<int64_t>(nmin, INT32_MAX),
-                       (int32_t *)dCnt.p);
+                       d_cnt);
     FC_HIP(hipGetLastError());
     std::vector<int32_t> cnt((size_t)ni);
-    FC_HIP(hipMemcpyAsync(cnt.data(), dCnt.p, sizeof(int32_t) * (size_t)ni,
+    FC_HIP(hipMemcpyAsync(cnt.data(), d_cnt, sizeof(int32_t) * (size_t)ni,
                           hipMemcpyDeviceToHost, s));
     FC_HIP(hipStreamSynchronize(s));
     std::vector<int64_t> off((size_t)ni + 1, 0);
@@ -353,8 +369,7 @@ extern "C" int fc_pairs(fc_db *db, const int32_t *items, int32_t ni, double mins
     const int64_t nrec = std::min(total, cap);
     if (nrec > 0) {
         const bool odev = is_device_ptr(out);
-        FC_HIP(dOff.alloc(sizeof(int64_t) * (size_t)ni, s));
-        FC_HIP(hipMemcpyAsync(dOff.p, off.data(), sizeof(int64_t) * (size_t)ni,
+        FC_HIP(hipMemcpyAsync(d_off, off.data(), sizeof(int64_t) * (size_t)ni,
                               hipMemcpyHostToDevice, s));
         fc_pair_rec *rec = out;
         if (!odev) {
@@ -363,7 +378,7 @@ extern "C" int fc_pairs(fc_db *db, const int32_t *items, int32_t ni, double mins
         }
         hipLaunchKernelGGL(k_pair_write, dim3((unsigned)((ni + 3) / 4)), dim3(256), 0, s, C,
                            (int32_t)ldc, ni, (int32_t)std::min<int64_t>(nmin, INT32_MAX),
-                           (const int64_t *)dOff.p, nrec, (float)(1.0 / m), rec);
+                           (const int64_t *)d_off, nrec, (float)(1.0 / m), rec);
         FC_HIP(hipGetLastError());
         if (!odev)
             FC_HIP(hipMemcpyAsync(out, rec, sizeof(fc_pair_rec) * (size_t)nrec,
