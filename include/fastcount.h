@@ -119,7 +119,8 @@ int fc_db_create(const uint8_t *data, int64_t m, int32_t n,
  * and FC_DB_DATA_ON_DEVICE are as in fc_db_create; the new states are
  * validated before anything changes, so a rejected append leaves the handle
  * as it was.  Columns, marginals, entropies and bit-vectors are updated in
- * place (columns grow when the padded size changes).  Graphs captured before
+ * place; their allocation grows 1.5x at a time when the rows outgrow it, so
+ * appends cost O(m_new) amortised.  Graphs captured before
  * the append are invalidated: fc_graph_launch then fails with
  * FC_ERR_INVALID.  Must not run concurrently with other calls on the handle;
  * synchronises the device.
@@ -129,6 +130,19 @@ int fc_db_append(fc_db *db, const uint8_t *data, int64_t m_new, int32_t layout,
 
 /* Free every device and host resource of the handle (NULL is a no-op). */
 void fc_db_destroy(fc_db *db);
+
+/*
+ * Release the handle's idle device workspaces.  Batches take their plan,
+ * the tables their reducers consume, and sort or descriptor scratch from up
+ * to four workspaces that the handle keeps between calls (allocation and
+ * release cost more host time than small batches take), so after a batch
+ * the handle holds device memory up to a few times its largest batch
+ * footprint (fc_batch_footprint) beyond the database; fc_db_info's device
+ * bytes include it.  Waits for each workspace's last use, frees it, and
+ * leaves workspaces in use by concurrent calls alone.  Later calls allocate
+ * again as needed.
+ */
+int fc_db_trim(fc_db *db);
 
 /*
  * Database facts: instances, variables, whether bit-vectors exist, and the

@@ -31,7 +31,7 @@ FC_RED_BDEU = 4
 FC_RED_MI = 8
 
 # every symbol the header declares
-EXPORTS = ("fc_db_create", "fc_db_append", "fc_db_destroy", "fc_db_info", "fc_db_marginals", "fc_table_cells",
+EXPORTS = ("fc_db_create", "fc_db_append", "fc_db_destroy", "fc_db_trim", "fc_db_info", "fc_db_marginals", "fc_table_cells",
            "fc_count", "fc_count_assignment", "fc_count_assignments", "fc_count_sparse", "fc_count_sparse_batch", "fc_count_batch", "fc_count_reduce",
            "fc_score_parent_sets", "fc_pairs", "fc_mine", "fc_arm_sizes", "fc_arm_read", "fc_arm_free",
            "fc_batch_footprint", "fc_graph_create", "fc_graph_launch", "fc_graph_destroy",
@@ -107,6 +107,7 @@ def load():
             "fc_db_create": (ctypes.c_int, [P, i64, i32, P, i32, u32, P, P]),
             "fc_db_append": (ctypes.c_int, [P, P, i64, i32, u32, P]),
             "fc_db_destroy": (None, [P]),
+            "fc_db_trim": (ctypes.c_int, [P]),
             "fc_db_info": (ctypes.c_int, [P, P, P, P, P]),
             "fc_db_marginals": (ctypes.c_int, [P, P, P]),
             "fc_table_cells": (i64, [P, P, i32]),
@@ -166,6 +167,10 @@ def fc_db_append(db, data, m_new, layout, flags, stream):
 
 def fc_db_destroy(db):
     load().fc_db_destroy(db)
+
+
+def fc_db_trim(db):
+    return check(load().fc_db_trim(db))
 
 
 def fc_db_info(db):

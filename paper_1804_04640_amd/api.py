@@ -104,6 +104,10 @@ class Database:
         self.m += int(m_new)
 
     # ----------------------------------------------------------- lifecycle
+    def trim(self) -> None:
+        """Free the handle's idle device workspaces (see fc_db_trim)."""
+        L.fc_db_trim(self.handle)
+
     def close(self):
         if getattr(self, "_h", None):
             L.fc_db_destroy(self._h)

@@ -153,7 +153,10 @@ Workspace *workspace_acquire(fc_db *db, size_t bytes, hipStream_t s) {
         if (w->p) {
             if (w->done) (void)hipEventSynchronize(w->done);
             (void)hipFree(w->p);
-            db->device_bytes -= (int64_t)w->cap;
+            {
+                std::lock_guard<std::mutex> lk(db->ws_mu);
+                db->device_bytes -= (int64_t)w->cap;
+            }
             w->p = nullptr;
             w->cap = 0;
         }
@@ -168,6 +171,7 @@ Workspace *workspace_acquire(fc_db *db, size_t bytes, hipStream_t s) {
             return nullptr;
         }
         w->cap = cap;
+        std::lock_guard<std::mutex> lk(db->ws_mu);
         db->device_bytes += (int64_t)cap;
     }
     if (!w->done && hipEventCreateWithFlags(&w->done, hipEventDisableTiming) != hipSuccess) {
@@ -175,9 +179,9 @@ Workspace *workspace_acquire(fc_db *db, size_t bytes, hipStream_t s) {
         (void)hipGetLastError();
         w->done = nullptr;
         (void)hipFree(w->p);
+        std::lock_guard<std::mutex> lk(db->ws_mu);
         db->device_bytes -= (int64_t)w->cap;
         delete w;
-        std::lock_guard<std::mutex> lk(db->ws_mu);
         --db->ws_count;
         return nullptr;
     }
@@ -485,6 +489,35 @@ extern "C" int fc_db_create(const uint8_t *data, int64_t m, int32_t n, const uin
     }
     *out = db;
     guard.db = nullptr;
+    return FC_OK;
+}
+
+extern "C" int fc_db_trim(fc_db *db) {
+    clear_error();
+    if (!db) {
+        set_error("fc_db_trim: NULL database handle");
+        return FC_ERR_INVALID;
+    }
+    std::vector<Workspace *> idle;
+    {
+        std::lock_guard<std::mutex> lk(db->ws_mu);
+        idle.swap(db->ws_free);
+        db->ws_count -= idle.size();
+    }
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    FC_HIP(hipSetDevice(db->device));
+    for (Workspace *w : idle) {
+        if (w->done) (void)hipEventSynchronize(w->done);  // its last user has finished
+        if (w->p) (void)hipFree(w->p);
+        if (w->done) (void)hipEventDestroy(w->done);
+        {
+            std::lock_guard<std::mutex> lk(db->ws_mu);
+            db->device_bytes -= (int64_t)w->cap;
+        }
+        delete w;
+    }
+    (void)hipSetDevice(cur);
     return FC_OK;
 }
 

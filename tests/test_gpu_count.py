@@ -442,3 +442,23 @@ def test_appends_then_pairs():
             db.append(np.ascontiguousarray(D[:, lo:hi]))
             _, G, _ = db.pairs(0.01, gram=True)
             np.testing.assert_array_equal(G.cpu().numpy(), orc.gram(np.ascontiguousarray(D[:, :hi])))
+
+
+def test_trim_releases_idle_workspaces():
+    w = synth.batched_uneven(m=50_003, nq=400)
+    with Database(w.D, w.arity) as db:
+        base = db.info()[3]
+        tables, toff = db.count_batch((w.vars_flat, w.var_off))
+        sc, _, _, _ = db.count_reduce((w.vars_flat, w.var_off), ("bdeu",))
+        db.count_sparse_batch([w.query(i) for i in range(50)])
+        torch.cuda.synchronize()
+        held = db.info()[3]
+        assert held > base                      # plan, tables and sort scratch kept
+        db.trim()
+        assert db.info()[3] == base
+        check_tables(w, *db.count_batch((w.vars_flat, w.var_off)))   # allocates again
+        sc2, _, _, _ = db.count_reduce((w.vars_flat, w.var_off), ("bdeu",))
+        assert torch.equal(sc["bdeu"], sc2["bdeu"])
+        db.trim()
+        db.trim()                               # nothing idle: no-op
+        assert db.info()[3] == base
