@@ -36,3 +36,45 @@ def test_null_handle_is_rejected_without_device_work():
     L = _lib.load()
     assert L.fc_db_info(None, None, None, None, None) == _lib.FC_ERR_INVALID
     assert b"NULL" in L.fc_last_error()
+
+
+def header_prototypes():
+    """{name: number of parameters} of every function the header declares."""
+    src = open(os.path.join(ROOT, "include", "fastcount.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    out = {}
+    for name, params in re.findall(r"\b(fc_[a-z_]+)\s*\(([^;{]*?)\)\s*;", src, flags=re.S):
+        params = params.strip()
+        out[name] = 0 if params in ("", "void") else params.count(",") + 1
+    return out
+
+
+def test_binding_signatures_match_the_header():
+    protos = header_prototypes()
+    lib = _lib.load()
+    assert set(protos) == set(_lib.EXPORTS)
+    for name, n in protos.items():
+        assert len(getattr(lib, name).argtypes) == n, (name, n, len(getattr(lib, name).argtypes))
+
+
+def test_newer_entry_points_reject_a_null_handle_before_device_work():
+    L = _lib.load()
+    P = None
+    assert L.fc_db_trim(P) == _lib.FC_ERR_INVALID
+    assert L.fc_count_sparse_batch(P, P, P, 0, P, P, 0, P, P, P) == _lib.FC_ERR_INVALID
+    assert L.fc_mine(P, P, 0, 0.1, 0.1, 3, P, P) == _lib.FC_ERR_INVALID
+    assert L.fc_arm_sizes(P, P, P, P, P) == _lib.FC_ERR_INVALID
+    assert L.fc_arm_read(P, P, P, P, P, P, P, P, P) == _lib.FC_ERR_INVALID
+    L.fc_arm_free(P)                                   # NULL is ignored
+    assert L.fc_score_parent_sets(P, 0, P, 0, 0, 0, P, 0.0, P, 0, P) == _lib.FC_ERR_INVALID
+    assert L.fc_pairs(P, P, 1, 0.1, P, P, 0, P, P) == _lib.FC_ERR_INVALID
+    assert L.fc_last_error()                           # every refusal says why
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
