@@ -191,7 +191,8 @@ int fc_count_assignment(fc_db *db, const int32_t *vars, const uint8_t *states,
  * counts, found by sorting the instances' keys and run-length encoding them
  * (the MSD order of Section 3.3 carried to the last digit).  keys and counts
  * (device or host memory) hold `cap` entries; *nnz receives the number of
- * distinct configurations, which may exceed cap.  Synchronises `stream`.
+ * distinct configurations, which may exceed cap (then the cap smallest keys
+ * are written).  Synchronises `stream`.
  */
 int fc_count_sparse(fc_db *db, const int32_t *vars, int32_t k, int64_t *keys,
                     int32_t *counts, int64_t cap, int64_t *nnz, void *stream);
