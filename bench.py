@@ -83,9 +83,12 @@ def percentile(xs, p):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), p)) if len(xs) else None
 
 
-def cpu_baseline(w, reducers, budget_s: float):
+def cpu_baseline(w, reducers, budget_s: float, gpu_scores=None, gpu_err=None):
     """The CPU oracle, as it stands, on a bounded sample of the same queries,
-    one query per thread (query-level parallelism)."""
+    one query per thread (query-level parallelism).  With the GPU's scores
+    (float32, [reducer][query]) it also reports their largest relative error
+    against the oracle's binary64 scores over the sample, and whether every
+    error lies within the GPU's own per-result estimate."""
     from oracle import oracle as orc
 
     def one(i):
@@ -104,12 +107,28 @@ def cpu_baseline(w, reducers, budget_s: float):
     ids = list(range(sample))
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(max_workers=threads) as ex:
-        list(ex.map(one, ids))
+        ref = list(ex.map(one, ids))
     dt = time.perf_counter() - t0
-    return {"value": sample * w.m / dt, "unit": "query-rows/s", "cores": threads,
-            "kind": "oracle",
-            "sample": "first %d of %d queries (m=%d), count + %s, %d threads, %.1f s wall"
-                      % (sample, w.nq, w.m, "+".join(reducers), threads, dt)}
+    out = {"value": sample * w.m / dt, "unit": "query-rows/s", "cores": threads,
+           "kind": "oracle",
+           "sample": "first %d of %d queries (m=%d), count + %s, %d threads, %.1f s wall"
+                     % (sample, w.nq, w.m, "+".join(reducers), threads, dt)}
+    if gpu_scores is not None:
+        worst, within = {}, True
+        for slot, name in enumerate(reducers):
+            g = gpu_scores[slot * w.nq:slot * w.nq + sample]
+            e = gpu_err[slot * w.nq:slot * w.nq + sample] if gpu_err is not None else None
+            rel = 0.0
+            for i in range(sample):
+                d = abs(float(g[i]) - ref[i][slot])
+                if ref[i][slot] != 0.0:
+                    rel = max(rel, d / abs(ref[i][slot]))
+                if e is not None and d > float(e[i]):
+                    within = False
+            worst[name] = rel
+        out["gpu_score_max_rel_err_vs_fp64"] = worst
+        out["gpu_score_err_within_estimate"] = within
+    return out
 
 
 def bench_serve(args):
@@ -495,6 +514,8 @@ def main():
                     help="JSON tuning to install instead (keys of fc_tuning)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON file of autotuner results to reuse / fill")
+    ap.add_argument("--compare-strategies", type=int, default=1,
+                    help="also time the batch with the bitmap and the histogram strategy forced")
     ap.add_argument("--graph", type=int, default=1,
                     help="also time the batch captured once into a hipGraph and replayed")
     ap.add_argument("--serve", action="store_true",
@@ -601,6 +622,17 @@ def main():
         step_ms = [a.elapsed_time(b) for a, b in evs]
         print("# timed %d steps: %.2f ms/step (wall)" % (args.steps, 1e3 * wall / args.steps),
               file=sys.stderr, flush=True)
+        # the same steps without the per-launch profiling events, which
+        # lengthen launch-bound batches (the timed region above keeps them:
+        # the roofline's kernel times come from it)
+        uev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        for a, b in uev:
+            a.record(stream)
+            step()
+            b.record(stream)
+        stream.synchronize()
+        unprof_ms = [a.elapsed_time(b) for a, b in uev]
 
         # plain per-query path: one call (one counting launch + reduce) per query
         per_query = None
@@ -646,6 +678,28 @@ def main():
                      "p50_ms": percentile(g_ms, 50), "p99_ms": percentile(g_ms, 99),
                      "scores_equal_eager": same}
 
+        # forced strategies beside auto (the same batch and reducers; a
+        # forced bitmap falls back to the histogram for tables it cannot hold)
+        strategies = None
+        if args.compare_strategies:
+            strategies = {}
+            for strat in ("bitmap", "hist"):
+                sev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                       for _ in range(3)]
+                db.count_reduce(q, reducers, ess=w.ess, strategy=strat, out=scores, err_out=errs,
+                                stream=stream)
+                for a, b in sev:
+                    a.record(stream)
+                    db.count_reduce(q, reducers, ess=w.ess, strategy=strat, out=scores,
+                                    err_out=errs, stream=stream)
+                    b.record(stream)
+                stream.synchronize()
+                sm = float(np.median([a.elapsed_time(b) for a, b in sev]))
+                strategies[strat] = {"ms_per_step": sm, "value": rows / (sm * 1e-3)}
+            db.count_reduce(q, reducers, ess=w.ess, strategy=args.strategy, out=scores,
+                            err_out=errs, stream=stream)
+            stream.synchronize()
+
     ms = float(np.mean(step_ms))
     value = rows / (ms * 1e-3)
     # dominant kernel: the counting kernel (algorithmic bytes > 0) with the
@@ -689,7 +743,11 @@ def main():
                     "kernels": {k: {"launches": v["launches"], "avg_us": 1e3 * v["ms"] / v["launches"],
                                     "share": v["ms"] / sum(x["ms"] for x in prof.values())}
                                 for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}},
+        "unprofiled": {"ms_per_step": float(np.mean(unprof_ms)),
+                       "value": rows / (float(np.mean(unprof_ms)) * 1e-3),
+                       "p50_ms": percentile(unprof_ms, 50), "p99_ms": percentile(unprof_ms, 99)},
         "graph_replay": graph,
+        "forced_strategies": strategies,
         "per_query": per_query,
         "batched_vs_per_query": (value / per_query["value"]) if per_query else None,
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved,
@@ -700,7 +758,8 @@ def main():
         "cpu_baseline": None,
     }
     if args.cpu_budget > 0:
-        out["cpu_baseline"] = cpu_baseline(w, reducers, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(w, reducers, args.cpu_budget,
+                                           scores.cpu().numpy(), errs.cpu().numpy())
     db.close()
     print(json.dumps(out), flush=True)
 

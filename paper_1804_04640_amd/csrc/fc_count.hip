@@ -1897,7 +1897,7 @@ extern "C" int fc_autotune(fc_db *db, const int32_t *vars_flat, const int64_t *v
     };
     // 0. Batch size up to which one persistent launch beats one launch per
     //    group: prefixes of the sample of growing size, stop at the first loss.
-    {
+    auto tune_persistent = [&]() -> int {
         int32_t thr = 0;
         for (int64_t nsub : {16, 64, 256, 1024, 4096}) {
             if (nsub > nq) break;
@@ -1913,7 +1913,9 @@ extern "C" int fc_autotune(fc_db *db, const int32_t *vars_flat, const int64_t *v
             if (ms_p < ms_s) thr = (int32_t)nsub; else break;
         }
         db->tune.persistent_max_queries = thr;
-    }
+        return FC_OK;
+    };
+    if ((rc = tune_persistent())) return rc;
     // 1. Packed 4-bit columns against byte columns for the histograms (when
     //    the database has them), then the histogram chunk size.
     if (db->d_nib) {
@@ -1986,6 +1988,24 @@ extern "C" int fc_autotune(fc_db *db, const int32_t *vars_flat, const int64_t *v
             }
         }
         db->tune.bitmap_words = best_ms < 0.97f * cur_ms ? bestw : curw;
+    }
+    // 5. The per-shape bitmap choices against none at all, on the whole
+    //    batch: on a small, launch-bound batch the extra launch groups of the
+    //    mixed strategies can cost more than the bitmap walks save.  After a
+    //    switch the persistent threshold and chunk size are tuned again.
+    if (db->d_bits) {
+        uint8_t saved[FC_MAX_VARS][6];
+        std::memcpy(saved, db->tune.bitmap_cells, sizeof saved);
+        float ms_mix = 0.f, ms_hist = 0.f;
+        if ((rc = time_batch(db, flat, off, FC_STRAT_AUTO, tables, s, 5, ms_mix))) return rc;
+        std::memset(db->tune.bitmap_cells, 0, sizeof saved);
+        if ((rc = time_batch(db, flat, off, FC_STRAT_AUTO, tables, s, 5, ms_hist))) return rc;
+        if (!(ms_hist < 0.97f * ms_mix)) {
+            std::memcpy(db->tune.bitmap_cells, saved, sizeof saved);
+        } else {
+            if ((rc = tune_persistent())) return rc;
+            if ((rc = sweep_chunks(0))) return rc;
+        }
     }
     return FC_OK;
 }
