@@ -546,7 +546,7 @@ def main():
         print(json.dumps({"copy_bytes": n, "launches": 3}))
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU; --gpus %d is not supported "
+        print("bench.py: the counting path runs on one GPU; --gpus %d is not supported "
               "(sharding across GPUs is a design note only)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
