@@ -33,6 +33,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA
+CLOCK_HZ = 2.4e9               # MI355X peak engine clock
+N_CU = 256                     # MI355X compute units
 
 
 def src_hash(files=None) -> str:
@@ -59,6 +61,20 @@ def counter_traffic(workload_name: str, kernel: str):
             ent = json.load(f).get(workload_name, {}).get(kernel)
         if ent and ent.get("src_hash") == src_hash(ent.get("src_files")):
             return ent["bytes_per_launch"]
+    except (OSError, ValueError):
+        pass
+    return None
+
+
+def counter_figures(workload_name: str, kernel: str):
+    """Per-launch VALU and LDS wave instructions of `kernel` from the
+    committed rocprofv3 counter summary, or None when the kernel's sources
+    changed after the counters were taken."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "counters.json")) as f:
+            ent = json.load(f).get(workload_name, {}).get(kernel)
+        if ent and ent.get("src_hash") == src_hash(ent.get("src_files")):
+            return ent
     except (OSError, ValueError):
         pass
     return None
@@ -719,6 +735,14 @@ def main():
             h_ms += v["ms"]
     achieved = dom["alg_bytes"] / (dom["ms"] * 1e-3) / 1e9 if dom["ms"] > 0 else 0.0
     traffic = counter_traffic(args.workload, dom_name)
+    # the issue rate the kernel reaches: its counted VALU wave instructions
+    # per launch over the live launch time, against one wave instruction per
+    # clock per CU (four SIMDs, each issuing a 64-lane instruction over four
+    # clocks) at 2.4 GHz on 256 CUs
+    cf = counter_figures(args.workload, dom_name)
+    launch_s = dom["ms"] * 1e-3 / dom["launches"] if dom["launches"] else 0.0
+    valu_frac = (cf["valu_inst_per_launch"] / (launch_s * CLOCK_HZ * N_CU)
+                 if cf and launch_s > 0 else None)
     out = {
         "metric": "exact query-rows counted/s + HBM GB/s frac; batched vs per-query; p50/p99 ms",
         "value": value,
@@ -754,7 +778,9 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "avg_launch_us": 1e3 * dom["ms"] / dom["launches"],
                      "alg_bytes_per_launch": dom["alg_bytes"] / dom["launches"],
-                     "traffic": traffic},
+                     "traffic": traffic,
+                     "valu_issue_frac": valu_frac,
+                     "lds_inst_per_launch": cf["lds_inst_per_launch"] if cf else None},
         "cpu_baseline": None,
     }
     if args.cpu_budget > 0:
