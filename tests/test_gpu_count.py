@@ -462,3 +462,29 @@ def test_trim_releases_idle_workspaces():
         db.trim()
         db.trim()                               # nothing idle: no-op
         assert db.info()[3] == base
+
+
+def test_empty_database_then_appends():
+    """A database created with no instances answers every entry point, then
+    grows by appends from empty (its first allocation is one tile)."""
+    from paper_1804_04640_amd import arm
+    rng = np.random.default_rng(17)
+    ar = np.array([2, 3, 2, 4, 2], np.uint8)
+    D = np.stack([rng.integers(0, a, size=30_011) for a in ar]).astype(np.uint8)
+    with Database(np.zeros((5, 0), np.uint8), ar) as db:
+        assert db.count([0, 3]).cpu().numpy().tolist() == [0] * 8
+        keys, cnts, off = db.count_sparse_batch([[0, 1], [3]])
+        assert len(keys) == 0 and list(off) == [0, 0, 0]
+        assert db.count_assignments([[0, 2]], [[1, 1]]).tolist() == [0]
+        freq, rules = arm.mine(db, minsup=0.0, minconf=0.0, items=[0, 2, 4])
+        assert freq == {} and rules == []
+        lo = 0
+        for hi in (1, 4097, 9000, 30_011):
+            db.append(np.ascontiguousarray(D[:, lo:hi]))
+            lo = hi
+            for vs in ([0, 3], [1, 2, 4], [3]):
+                np.testing.assert_array_equal(db.count(vs).cpu().numpy(),
+                                              orc.count(np.ascontiguousarray(D[:, :hi]), ar, vs))
+        freq, _ = arm.mine(db, minsup=0.1, minconf=0.5, items=[0, 2, 4])
+        ref, _ = orc.arm_bruteforce(D[[0, 2, 4]], 0.1, 0.5, max_size=6)
+        assert freq == {tuple([0, 2, 4][i] for i in s): c for s, c in ref.items()}
