@@ -280,3 +280,44 @@ def test_sparse_batch_capacity_and_errors():
             db.count_sparse_batch([[1, 4, 1]])             # a repeated variable
         with pytest.raises(L.FastcountError):
             db.count_sparse_batch([list(range(9))])        # more than 8 variables
+
+
+def test_sparse_batch_several_windows():
+    """A batch of more than 2^27 keys spans several windows (63 queries of
+    m = 2^21 + 5 instances each, the last window ragged).  Every query's pairs
+    are valid (counts sum to m, keys strictly increasing inside the key
+    space); every fifth query and those around window boundaries equal the
+    oracle's; a capacity one short of the total fails with the sizes set."""
+    from paper_1804_04640_amd import _lib as L
+    from paper_1804_04640_amd.api import flatten_queries
+    rng = synth.rng_for(91)
+    n, m = 12, (1 << 21) + 5
+    ar = rng.integers(2, 100, size=n).astype(np.uint8)
+    D = np.stack([rng.integers(0, a, size=m) for a in ar]).astype(np.uint8)
+    qs = [rng.choice(n, size=int(rng.integers(1, 9)), replace=False).astype(np.int32)
+          for _ in range(130)]
+    print("several windows: n=%d m=%d queries=%d" % (n, m, len(qs)), flush=True)
+    with Database(D, ar, bitvectors=False) as db:
+        keys, cnts, off = db.count_sparse_batch(qs)
+        keys, cnts = keys.cpu().numpy(), cnts.cpu().numpy()
+        assert off[0] == 0 and off[-1] == len(keys)
+        for i, q in enumerate(qs):
+            k, c = keys[off[i]:off[i + 1]], cnts[off[i]:off[i + 1]]
+            cells = int(np.prod(ar[q].astype(np.float64)))
+            assert c.sum() == m and c.min() >= 1
+            assert k[0] >= 0 and k[-1] < cells and np.all(np.diff(k) > 0)
+            if i % 5 == 0 or i in (61, 62, 63, 64, 125, 126, 127, 129):
+                rk, rc = orc.count_sparse(D, ar, q)
+                np.testing.assert_array_equal(k, rk)
+                np.testing.assert_array_equal(c, rc)
+        total = int(off[-1])
+        del keys, cnts
+        small_k = torch.empty(total - 1, dtype=torch.int64, device="cuda")
+        small_c = torch.empty(total - 1, dtype=torch.int32, device="cuda")
+        flat, voff = flatten_queries(qs)
+        hoff = np.zeros(len(qs) + 1, np.int64)
+        rc, t2 = L.fc_count_sparse_batch(db.handle, flat.ctypes.data, voff.ctypes.data, len(qs),
+                                         small_k.data_ptr(), small_c.data_ptr(), total - 1,
+                                         hoff.ctypes.data, torch.cuda.current_stream().cuda_stream)
+        assert rc == L.FC_ERR_RANGE and t2 == total
+        np.testing.assert_array_equal(hoff, off)
