@@ -209,9 +209,10 @@ int fc_count_sparse(fc_db *db, const int32_t *vars, int32_t k, int64_t *keys,
  * memory and hold `cap` entries (total_nnz <= nq * m always).  When the
  * total exceeds cap the call returns FC_ERR_RANGE with out_off and
  * *total_nnz set and keys/counts unspecified, so the caller can size and
- * call again.  Consecutive queries share one radix sort of
- * (query, key) composite keys (at most 2^26 keys per sort).  Synchronises
- * `stream`.
+ * call again.  Queries are grouped (ordered by key space within windows
+ * of consecutive queries); a group shares one radix sort of composite keys
+ * (its offset in the group plus the query's key, at most 2^26 keys per
+ * sort).  The grouping affects speed only.  Synchronises `stream`.
  */
 int fc_count_sparse_batch(fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
                           int64_t nq, int64_t *keys, int32_t *counts, int64_t cap,
