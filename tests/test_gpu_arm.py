@@ -321,3 +321,37 @@ def test_sparse_batch_several_windows():
                                          hoff.ctypes.data, torch.cuda.current_stream().cuda_stream)
         assert rc == L.FC_ERR_RANGE and t2 == total
         np.testing.assert_array_equal(hoff, off)
+
+
+def test_sparse_batch_more_queries_than_a_group_holds():
+    """70,000 queries over m = 3 instances: more queries than one group may
+    hold (65,535), so one window is cut into several groups; every query's
+    pairs equal the oracle's, with device and host outputs."""
+    from paper_1804_04640_amd import _lib as L
+    from paper_1804_04640_amd.api import flatten_queries
+    rng = synth.rng_for(93)
+    n, m = 20, 3
+    ar = rng.integers(2, 100, size=n).astype(np.uint8)
+    D = np.stack([rng.integers(0, a, size=m) for a in ar]).astype(np.uint8)
+    qs = [rng.choice(n, size=int(rng.integers(1, 9)), replace=False).astype(np.int32)
+          for _ in range(70000)]
+    with Database(D, ar, bitvectors=False) as db:
+        keys, cnts, off = db.count_sparse_batch(qs)
+        keys, cnts = keys.cpu().numpy(), cnts.cpu().numpy()
+        assert off[-1] == len(keys)
+        for i, q in enumerate(qs):
+            rk, rc = orc.count_sparse(D, ar, q)
+            np.testing.assert_array_equal(keys[off[i]:off[i + 1]], rk)
+            np.testing.assert_array_equal(cnts[off[i]:off[i + 1]], rc)
+        flat, voff = flatten_queries(qs)
+        total = int(off[-1])
+        hk = np.zeros(total, np.int64)
+        hc = np.zeros(total, np.int32)
+        hoff = np.zeros(len(qs) + 1, np.int64)
+        rc, t2 = L.fc_count_sparse_batch(db.handle, flat.ctypes.data, voff.ctypes.data, len(qs),
+                                         hk.ctypes.data, hc.ctypes.data, total, hoff.ctypes.data,
+                                         torch.cuda.current_stream().cuda_stream)
+        assert rc == L.FC_OK and t2 == total
+        np.testing.assert_array_equal(hoff, off)
+        np.testing.assert_array_equal(hk, keys)
+        np.testing.assert_array_equal(hc, cnts)
