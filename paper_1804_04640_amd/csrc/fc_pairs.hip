@@ -3,25 +3,30 @@
 //
 // The count of every pair Count(X_a = 1 AND X_b = 1) is one entry of the
 // Gram matrix A^T A of the m x n one-hot {0,1} instance-by-item matrix, a
-// dense contraction over the instances.  It runs on int8 MFMA with exact
-// int32 accumulation (counts < 2^31): the item bit-vectors of state 1 are
-// expanded to one byte per instance in registers, never materialised.
+// dense contraction over the instances.  It runs on the matrix cores with
+// e2m1 (FP4) operands: 0 and 1 are exact e2m1 values, so every product is
+// exact, and the fp32 accumulators stay exact while a sum is at most 2^24,
+// which holds because one workgroup covers at most 2^24 instances.  The
+// item bit-vectors of state 1 are expanded to one nibble per instance in
+// registers, never materialised.
 //  * a workgroup of 4 waves owns a 128 x 256 block of items (the blocks
 //    that reach the upper triangle; the matrix is symmetric) over one range
 //    of instances (split K); each wave holds a 128 x 64 part as an 8 x 4 grid
-//    of 16x16x64 i8 MFMA accumulators; partial blocks are summed into the
-//    output with int32 atomics;
+//    of 16x16x128 scaled-MFMA accumulators (e2m1 operands, unit scales);
+//    partial blocks are converted to int32 and summed into the output with
+//    int32 atomics;
 //  * the instances are taken 512 at a time (8 words of every item): a lane
 //    of K group g loads words 2g and 2g+1 of each of its items with one
 //    16-byte load (the 4 groups of an item read 64 contiguous bytes), and
-//    MFMA step h of the 8 feeds it the 16 bits h % 4 of word 2g + h / 4.
-//    Every instance is used exactly once, and A and B fragments come from
-//    the same function over the same instance groups, so their K order
-//    agrees whatever the hardware's order is;
-//  * a lane expands its 16 bits of an item to 16 bytes, the operand layout
-//    of the MFMA.  The 128 row items are shared by the 4 waves: each
-//    expands 2 of the 8 row fragments into an LDS panel (double buffered,
-//    one barrier per step); the 64 column items of a wave stay in registers;
+//    MFMA step h of the 4 feeds it dword h of those two words (32
+//    instances).  Every instance is used exactly once, and A and B
+//    fragments come from the same function over the same instance groups,
+//    so their K order agrees whatever the hardware's order is;
+//  * a lane expands its 32 bits of an item to 32 nibbles (16 bytes), the
+//    operand layout of the MFMA.  The 128 row items are shared by the 4
+//    waves: each expands 2 of the 8 row fragments into an LDS panel (double
+//    buffered, one barrier per step); the 64 column items of a wave stay in
+//    registers;
 //  * the words of the next 512 instances load during the current ones.
 #include <algorithm>
 #include <cmath>
@@ -34,6 +39,8 @@ namespace fc {
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int kGT = 128;  // row items per block
 constexpr int kGC = 256;  // column items per block (64 per wave)
@@ -41,22 +48,34 @@ constexpr int kGR = kGT / 16;  // row fragments
 constexpr int kGK = 4;         // column fragments per wave
 constexpr int kGS = 8;         // words per load step
 
-// 16 instance bits -> 16 bytes of 0/1 (instance order = byte order).
-__device__ __forceinline__ v4i expand16(uint32_t b) {
+// 32 instance bits -> 32 e2m1 values of 0 or 1.0 (0x2), 8 per dword.  In
+// dword t, bit i of byte t lands in nibble 2i and bit 4 + i in nibble 2i + 1
+// (the product's other terms fall outside the mask and never carry).
+__device__ __forceinline__ v4i expand32(uint32_t b) {
+    constexpr uint32_t kSpread = 0x00408102u;  // 2 + 2^8 + 2^15 + 2^22
     v4i r;
-    r[0] = (int)(((b & 0xFu) * 0x00204081u) & 0x01010101u);
-    r[1] = (int)((((b >> 4) & 0xFu) * 0x00204081u) & 0x01010101u);
-    r[2] = (int)((((b >> 8) & 0xFu) * 0x00204081u) & 0x01010101u);
-    r[3] = (int)((((b >> 12) & 0xFu) * 0x00204081u) & 0x01010101u);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const uint32_t lo = ((b >> (8 * t)) & 0xFu) * kSpread;
+        const uint32_t hi = ((b >> (8 * t + 4)) & 0xFu) * kSpread;
+        uint32_t c;  // (hi << 4) | lo, kept opaque so the shift stays out of the multiply
+        asm("v_lshl_or_b32 %0, %1, 4, %2" : "=v"(c) : "v"(hi), "v"(lo));
+        r[t] = (int)(c & 0x22222222u);
+    }
     return r;
 }
 
-// The 16 bits of MFMA step h in a lane's two words (x, y: low/high halves
-// of word 2g; z, w: of word 2g + 1).
+// The 32 bits of MFMA step h: dword h of a lane's two words.
 template <int H>
 __device__ __forceinline__ uint32_t bits_of(const uint4 &v) {
-    const uint32_t d = H < 2 ? v.x : H < 4 ? v.y : H < 6 ? v.z : v.w;
-    return (H & 1) ? d >> 16 : d & 0xFFFFu;
+    return H == 0 ? v.x : H == 1 ? v.y : H == 2 ? v.z : v.w;
+}
+
+__device__ __forceinline__ v4f mfma_fp4(const v4i &a, const v4i &b, const v4f &c) {
+    const v8i a8 = {a[0], a[1], a[2], a[3], 0, 0, 0, 0};
+    const v8i b8 = {b[0], b[1], b[2], b[3], 0, 0, 0, 0};
+    // formats 4/4: e2m1 operands; scales 127: 2^0
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a8, b8, c, 4, 4, 0, 127, 0, 127);
 }
 
 // A lane's 2 row items (its share of the panel) and 4 column items.
@@ -82,9 +101,9 @@ __device__ __forceinline__ void expand_step(const Words &x, const uint4 (&ma)[2]
                                             int lane, v4i (&b)[kGK]) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
-        panel[2 * wave + i][lane] = expand16(bits_of<H>(x.a[i]) & bits_of<H>(ma[i]));
+        panel[2 * wave + i][lane] = expand32(bits_of<H>(x.a[i]) & bits_of<H>(ma[i]));
 #pragma unroll
-    for (int j = 0; j < kGK; ++j) b[j] = expand16(bits_of<H>(x.b[j]) & bits_of<H>(mb[j]));
+    for (int j = 0; j < kGK; ++j) b[j] = expand32(bits_of<H>(x.b[j]) & bits_of<H>(mb[j]));
 }
 
 // One step: the 8 x 4 MFMAs of the current operands (row fragments from
@@ -97,19 +116,19 @@ __device__ __forceinline__ void gram_step(const Words &xn, const uint4 (&ma)[2],
                                           const uint4 (&mb)[kGK], v4i (*cur_panel)[64],
                                           v4i (*next_panel)[64], int wave, int lane,
                                           bool active, const v4i (&b)[kGK], v4i (&nb)[kGK],
-                                          v4i (&acc)[kGR][kGK]) {
+                                          v4f (&acc)[kGR][kGK]) {
     if (active) {
 #pragma unroll
         for (int i = 0; i < kGR; ++i) {
             const v4i a = cur_panel[i][lane];
 #pragma unroll
             for (int j = 0; j < kGK; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = mfma_fp4(a, b[j], acc[i][j]);
             if (i < 2)
                 next_panel[2 * wave + i][lane] =
-                    expand16(bits_of<HN>(xn.a[i]) & bits_of<HN>(ma[i]));
+                    expand32(bits_of<HN>(xn.a[i]) & bits_of<HN>(ma[i]));
             else if (i < 2 + kGK)
-                nb[i - 2] = expand16(bits_of<HN>(xn.b[i - 2]) & bits_of<HN>(mb[i - 2]));
+                nb[i - 2] = expand32(bits_of<HN>(xn.b[i - 2]) & bits_of<HN>(mb[i - 2]));
         }
     } else {
         expand_step<HN>(xn, ma, mb, next_panel, wave, lane, nb);
@@ -158,11 +177,11 @@ __global__ __launch_bounds__(256, 2) void k_gram(const uint64_t *__restrict__ bi
     const int64_t w0 = (int64_t)sp * tiles / splits * (kTileRows / 64);
     const int64_t w1 = (int64_t)(sp + 1) * tiles / splits * (kTileRows / 64);
 
-    v4i acc[kGR][kGK];
+    v4f acc[kGR][kGK];
 #pragma unroll
     for (int i = 0; i < kGR; ++i)
 #pragma unroll
-        for (int j = 0; j < kGK; ++j) acc[i][j] = v4i{0, 0, 0, 0};
+        for (int j = 0; j < kGK; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
     if (w0 < w1) {
         // (w1 - w0) is a multiple of 64 words; past the range the loads
         // repeat the last step's words (expanded, never multiplied)
@@ -176,10 +195,6 @@ __global__ __launch_bounds__(256, 2) void k_gram(const uint64_t *__restrict__ bi
             gram_step<1>(cur, ma, mb, panel[0], panel[1], wave, lane, active, b, nb, acc);
             gram_step<2>(cur, ma, mb, panel[1], panel[0], wave, lane, active, nb, b, acc);
             gram_step<3>(cur, ma, mb, panel[0], panel[1], wave, lane, active, b, nb, acc);
-            gram_step<4>(cur, ma, mb, panel[1], panel[0], wave, lane, active, nb, b, acc);
-            gram_step<5>(cur, ma, mb, panel[0], panel[1], wave, lane, active, b, nb, acc);
-            gram_step<6>(cur, ma, mb, panel[1], panel[0], wave, lane, active, nb, b, acc);
-            gram_step<7>(cur, ma, mb, panel[0], panel[1], wave, lane, active, b, nb, acc);
             gram_step<0>(nxt, ma, mb, panel[1], panel[0], wave, lane, active, nb, b, acc);
             cur = nxt;
         }
@@ -192,7 +207,7 @@ __global__ __launch_bounds__(256, 2) void k_gram(const uint64_t *__restrict__ bi
         for (int j = 0; j < kGK; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int32_t v = acc[i][j][e];
+                const int32_t v = (int32_t)acc[i][j][e];
                 if (v) {
                     const int64_t row = (int64_t)I * kGT + i * 16 + 4 * grp + e;
                     const int64_t cc = (int64_t)col0 + j * 16 + col;
@@ -342,6 +357,8 @@ extern "C" int fc_pairs(fc_db *db, const int32_t *items, int32_t ni, double mins
     // whole 64-word tiles each
     int64_t splits = 2 * (int64_t)db->cu_count / npairs;
     splits = std::min<int64_t>(splits, tiles);
+    // at most 4096 tiles (2^24 instances) per workgroup keeps the fp32 sums exact
+    splits = std::max<int64_t>(splits, (tiles + 4095) / 4096);
     if (splits < 1) splits = 1;
     if (db->m > 0) {
         const double ops = 2.0 * (double)db->m * (double)ni * (double)(ni + 1) / 2.0;

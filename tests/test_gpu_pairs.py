@@ -59,3 +59,26 @@ def test_rejects_non_binary():
     with Database(D, np.array([2, 3], np.uint8)) as db:
         with pytest.raises(_lib.FastcountError):
             db.pairs(0.1)
+
+
+def test_gram_beyond_2_24_instances():
+    """m = 2^25 + 4097 instances at 75% density: pair counts pass 2^24,
+    the most a single fp32 accumulator sums exactly, so the instance range
+    must be split.  The diagonal and 60 sampled pairs equal the oracle's
+    single-assignment counts; the Gram is symmetric."""
+    rng = synth.rng_for(95)
+    n, m = 24, (1 << 25) + 4097
+    D = (rng.random((n, m), dtype=np.float32) < 0.75).astype(np.uint8)
+    ar = np.full(n, 2, np.uint8)
+    print("gram beyond 2^24: n=%d m=%d" % (n, m), flush=True)
+    with Database(D, ar) as db:
+        _, G, _ = db.pairs(0.5, gram=True)
+        G = G.cpu().numpy()
+    assert np.array_equal(G, G.T)
+    assert G[np.triu_indices(n, 1)].min() > (1 << 24)
+    for a in range(n):
+        assert G[a, a] == orc.count_assignment(D, ar, [a], [1])
+    pairs = [(a, b) for a in range(n) for b in range(a + 1, n)]
+    for i in rng.choice(len(pairs), size=60, replace=False):
+        a, b = pairs[int(i)]
+        assert G[a, b] == orc.count_assignment(D, ar, [a, b], [1, 1]), (a, b)
