@@ -23,10 +23,10 @@
 //    fragments come from the same function over the same instance groups,
 //    so their K order agrees whatever the hardware's order is;
 //  * a lane expands its 32 bits of an item to 32 nibbles (16 bytes), the
-//    operand layout of the MFMA.  The 128 row items are shared by the 4
-//    waves: each expands 2 of the 8 row fragments into an LDS panel (double
-//    buffered, one barrier per step); the 64 column items of a wave stay in
-//    registers;
+//    operand layout of the MFMA: bit 4k + t goes to nibble k of dword t.
+//    The 128 row items are shared by the 4 waves: each expands 2 of the 8
+//    row fragments into an LDS panel (double buffered, one barrier per
+//    step); the 64 column items of a wave stay in registers;
 //  * the words of the next 512 instances load during the current ones.
 #include <algorithm>
 #include <cmath>
@@ -48,20 +48,14 @@ constexpr int kGR = kGT / 16;  // row fragments
 constexpr int kGK = 4;         // column fragments per wave
 constexpr int kGS = 8;         // words per load step
 
-// 32 instance bits -> 32 e2m1 values of 0 or 1.0 (0x2), 8 per dword.  In
-// dword t, bit i of byte t lands in nibble 2i and bit 4 + i in nibble 2i + 1
-// (the product's other terms fall outside the mask and never carry).
+// 32 instance bits -> 32 e2m1 values of 0 or 1.0 (0x2): bit 4k + t of b
+// becomes nibble k of dword t (a shift and a mask per 8 instances).
 __device__ __forceinline__ v4i expand32(uint32_t b) {
-    constexpr uint32_t kSpread = 0x00408102u;  // 2 + 2^8 + 2^15 + 2^22
     v4i r;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const uint32_t lo = ((b >> (8 * t)) & 0xFu) * kSpread;
-        const uint32_t hi = ((b >> (8 * t + 4)) & 0xFu) * kSpread;
-        uint32_t c;  // (hi << 4) | lo, kept opaque so the shift stays out of the multiply
-        asm("v_lshl_or_b32 %0, %1, 4, %2" : "=v"(c) : "v"(hi), "v"(lo));
-        r[t] = (int)(c & 0x22222222u);
-    }
+    r[0] = (int)((b << 1) & 0x22222222u);
+    r[1] = (int)(b & 0x22222222u);
+    r[2] = (int)((b >> 1) & 0x22222222u);
+    r[3] = (int)((b >> 2) & 0x22222222u);
     return r;
 }
 
