@@ -33,6 +33,8 @@ namespace fc {
 
 constexpr int kHistMaxCells = 40000;  // generic kernel: odd row stride * 4 B <= 160 KiB
 constexpr int32_t kPersistentLds = 64 * 64 * 4;  // groups up to this LDS share one launch
+constexpr int64_t kGramBlock = 256;     // Gram rows come in whole column blocks
+constexpr int64_t kGramMaxRows = 4096;  // state Gram at most 4096 x 4096 (64 MiB)
 
 __device__ __forceinline__ void map_block(int64_t b, int32_t nd, int32_t chunks, int32_t &d,
                                           int32_t &c) {
@@ -734,6 +736,29 @@ __global__ void k_zero_tables(const QDesc *__restrict__ descs, int32_t nd,
     }
 }
 
+// Tables of one- and two-variable queries from the Gram C of their
+// variables' state bit-vectors (valid on and above the diagonal): cell
+// (s0, s1) of query (v0, v1) is Count(X_v0 = s0 AND X_v1 = s1), entry
+// (pos[v0] + s0, pos[v1] + s1) read on its upper side; a one-variable table
+// is the diagonal.  One workgroup per query.
+__global__ void k_gram_tables(const QDesc *__restrict__ d, int64_t nd,
+                              const int32_t *__restrict__ pos, const uint8_t *__restrict__ arity,
+                              const int32_t *__restrict__ C, int64_t ldc,
+                              int32_t *__restrict__ tables) {
+    for (int64_t q = blockIdx.x; q < nd; q += gridDim.x) {
+        const QDesc x = d[q];
+        const int64_t p0 = pos[x.var[0]];
+        const int64_t p1 = x.k == 2 ? pos[x.var[1]] : p0;
+        const int32_t r1 = x.k == 2 ? arity[x.var[1]] : 1;
+        for (int32_t c = threadIdx.x; c < x.cells; c += blockDim.x) {
+            const int64_t i = x.k == 2 ? p0 + c / r1 : p0 + c;
+            const int64_t j = x.k == 2 ? p1 + c % r1 : p0 + c;
+            const int64_t a = i < j ? i : j, b = i < j ? j : i;
+            tables[x.table_off + c] = C[a * ldc + b];
+        }
+    }
+}
+
 // Single-assignment count: one path of the Alg. 1 tree (bit-vector rows).
 struct Rows8 {
     int32_t r[FC_MAX_VARS];
@@ -868,6 +893,13 @@ struct Plan {
     std::vector<Launch> launches;
     int64_t total_cells = 0;    // table buffer size in cells
     bool packed = true;         // tables back to back in query order
+    // one- and two-variable queries answered from the Gram of their
+    // variables' state bit-vectors: descriptors work[gram_first, +gram_count)
+    int64_t gram_first = 0, gram_count = 0;
+    int32_t gram_np = 0;               // Gram rows, padded to whole blocks
+    std::vector<int32_t> gram_rows;    // bit-vector row of each Gram row (-1: padding)
+    std::vector<int32_t> gram_pos;     // [n] Gram row of a variable's state 0
+    double gram_bytes = 0.0, gram_ops = 0.0;
 };
 
 // LDS size classes; every class but the last keeps its byte addresses below
@@ -990,6 +1022,8 @@ struct RangeStat {
     std::vector<int64_t> cnt, cur;
     std::vector<double> bytes;
     std::vector<int32_t> maxc;
+    int64_t nsmall = 0, gcur = 0;   // one- and two-variable queries; their cursor
+    std::vector<uint8_t> used;      // [n] variables of those queries
 };
 
 // Strategy of one query (validated), and its window size for partitions.
@@ -1101,6 +1135,7 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
     P.packed = table_off == nullptr;
     P.nq = nq;
     const int64_t total_cells_in = table_off ? table_off[nq] : 0;
+    const bool gram_allowed = forced == FC_STRAT_AUTO && db->d_bits && db->m > 0;
     unsigned hw = std::thread::hardware_concurrency();
     int64_t T = std::min<int64_t>(std::max<unsigned>(1u, std::min(16u, hw ? hw : 1u)),
                                   std::max<int64_t>(1, nq / 32768));
@@ -1111,6 +1146,7 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
         R[(size_t)t].cnt.assign(kBuckets, 0);
         R[(size_t)t].bytes.assign(kBuckets, 0.0);
         R[(size_t)t].maxc.assign(kBuckets, 0);
+        if (gram_allowed) R[(size_t)t].used.assign((size_t)db->n, 0);
     }
     // pass 1: validate, count descriptors per bucket
     parallel_ranges(R, [&](RangeStat &r) {
@@ -1134,6 +1170,10 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
             const int st = choose(db, forced, k, c, win);
             const bool small = c < (int64_t(1) << 24);
             r.cells_sum += c;
+            if (k <= 2 && gram_allowed) {
+                ++r.nsmall;
+                for (int64_t t = 0; t < k; ++t) r.used[(size_t)vars_flat[var_off[i] + t]] = 1;
+            }
             for (int64_t b0 = 0; b0 < c; b0 += win) {
                 const int64_t wc = std::min<int64_t>(win, c - b0);
                 const int b = st == S_BITMAP ? bucket_of(S_BITMAP, (int)k, 0, false)
@@ -1152,6 +1192,49 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
         }
     P.windows = false;
     for (auto &r : R) P.windows = P.windows || r.windows;
+    // Gram of the small queries' state bit-vectors instead of their own
+    // launches, when estimated at most half their cost: about 2e15 useful
+    // operations/s on the matrix cores plus a launch, against about 3e13
+    // query-instances/s for one- and two-variable counts
+    bool use_gram = false;
+    if (gram_allowed) {
+        int64_t nsmall = 0;
+        for (auto &r : R) nsmall += r.nsmall;
+        std::vector<uint8_t> used((size_t)db->n, 0);
+        for (auto &r : R)
+            for (int32_t v = 0; v < db->n; ++v) used[(size_t)v] |= r.used[(size_t)v];
+        int64_t states = 0;
+        for (int32_t v = 0; v < db->n; ++v)
+            if (used[(size_t)v]) states += db->arity[(size_t)v];
+        const int64_t np = (states + kGramBlock - 1) / kGramBlock * kGramBlock;
+        const double t_gram = (double)np * (double)np * (double)db->m / 2e15 + 20e-6;
+        const double t_small = (double)nsmall * (double)db->m * 3e-14;
+        if (nsmall > 0 && np <= kGramMaxRows && t_gram < 0.5 * t_small) {
+            use_gram = true;
+            P.gram_np = (int32_t)np;
+            P.gram_rows.assign((size_t)np, -1);
+            P.gram_pos.assign((size_t)db->n, -1);
+            int32_t row = 0;
+            for (int32_t v = 0; v < db->n; ++v)
+                if (used[(size_t)v]) {
+                    P.gram_pos[(size_t)v] = row;
+                    for (int32_t st = 0; st < db->arity[(size_t)v]; ++st)
+                        P.gram_rows[(size_t)row++] = db->state_off[(size_t)v] + st;
+                }
+            P.gram_ops = (double)db->m * (double)states * (double)(states + 1);
+            // their buckets (K = 1, 2) empty out: every such query is here
+            for (auto &r : R)
+                for (int st = 1; st <= 3; ++st)
+                    for (int K = 1; K <= 2; ++K)
+                        for (int cls = 0; cls < 7; ++cls)
+                            for (int sm = 0; sm < 2; ++sm) {
+                                const int b = bucket_of(st, K, cls, sm != 0);
+                                P.gram_bytes += r.bytes[(size_t)b];
+                                r.cnt[(size_t)b] = 0;
+                                r.bytes[(size_t)b] = 0.0;
+                            }
+        }
+    }
     // bucket starts (launch order) and per-range cursors
     std::vector<int64_t> start(kBuckets + 1, 0);
     for (int b = 0; b < kBuckets; ++b) {
@@ -1170,7 +1253,14 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
         }
     }
     const bool need_query = !P.packed || (reducers && P.windows);
-    P.work.resize((size_t)start[kBuckets]);
+    P.gram_first = start[kBuckets];
+    P.gram_count = 0;
+    if (use_gram)
+        for (auto &r : R) {
+            r.gcur = P.gram_first + P.gram_count;
+            P.gram_count += r.nsmall;
+        }
+    P.work.resize((size_t)(start[kBuckets] + P.gram_count));
     if (need_query) P.query.resize((size_t)nq);
     std::vector<int64_t> base((size_t)T, 0);
     for (int64_t t = 1; t < T; ++t) base[(size_t)t] = base[(size_t)t - 1] + R[(size_t)t - 1].cells_sum;
@@ -1197,6 +1287,10 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
             d.win_cells = (int32_t)c;
             d.tiles = (int32_t)(db->m_pad / kTileRows);
             if (need_query) P.query[(size_t)i] = d;
+            if (use_gram && k <= 2) {
+                P.work[(size_t)r.gcur++] = d;
+                continue;
+            }
             int64_t win;
             const int st = choose(db, forced, k, c, win);
             const bool small = c < (int64_t(1) << 24);
@@ -1421,6 +1515,8 @@ struct Image {
     double pbytes = 0.0;
     bool with_query = false;
     size_t off_query = 0, off_groups = 0, off_heads = 0, bytes = 0;
+    size_t off_gram_rows = 0, off_gram_pos = 0, off_gram_c = 0;
+    size_t dev_bytes = 0;  // bytes plus the device-only state Gram
 };
 
 static void make_image(const fc_db *db, const Plan &P, uint32_t reducers, Image &I) {
@@ -1454,7 +1550,15 @@ static void make_image(const fc_db *db, const Plan &P, uint32_t reducers, Image 
     b += sizeof(PGroup) * I.groups.size();
     I.off_heads = b;
     b += 64;
+    I.off_gram_rows = b;
+    b += sizeof(int32_t) * P.gram_rows.size();
+    I.off_gram_pos = b;
+    b += sizeof(int32_t) * P.gram_pos.size();
     I.bytes = b;
+    I.off_gram_c = (b + 255) & ~(size_t)255;
+    I.dev_bytes = P.gram_count ? I.off_gram_c + sizeof(int32_t) * (size_t)P.gram_np *
+                                                    (size_t)P.gram_np
+                               : I.bytes;
 }
 
 // memcpy split over host threads for large plans (pinned destination).
@@ -1480,6 +1584,10 @@ static void fill_image(const Plan &P, const Image &I, void *host) {
     if (I.with_query) std::memcpy(h + I.off_query, P.query.data(), sizeof(QDesc) * P.query.size());
     std::memcpy(h + I.off_groups, I.groups.data(), sizeof(PGroup) * I.groups.size());
     std::memset(h + I.off_heads, 0, 64);
+    if (!P.gram_rows.empty())
+        std::memcpy(h + I.off_gram_rows, P.gram_rows.data(), sizeof(int32_t) * P.gram_rows.size());
+    if (!P.gram_pos.empty())
+        std::memcpy(h + I.off_gram_pos, P.gram_pos.data(), sizeof(int32_t) * P.gram_pos.size());
 }
 
 // Every device step of a batch whose image is resident at `dimg`: zero the
@@ -1496,6 +1604,18 @@ static int enqueue_batch(fc_db *db, const Plan &P, const Image &I, void *dimg, i
         const int32_t nd = (int32_t)P.query.size();
         hipLaunchKernelGGL(k_zero_tables, dim3((unsigned)std::min<int32_t>(nd, 65536)), dim3(256),
                            0, s, dq, nd, tables);
+        FC_HIP(hipGetLastError());
+    }
+    if (db->m > 0 && P.gram_count > 0) {
+        const int32_t np = P.gram_np;
+        int32_t *C = (int32_t *)((char *)dimg + I.off_gram_c);
+        const int32_t *rows = (const int32_t *)((char *)dimg + I.off_gram_rows);
+        const int32_t *pos = (const int32_t *)((char *)dimg + I.off_gram_pos);
+        FC_HIP(fill_zero_i32(C, (int64_t)np * np, s));
+        FC_HIP(launch_gram(db, rows, np, C, np, "k_gram_states", P.gram_bytes, P.gram_ops, s));
+        const int64_t nd = P.gram_count;
+        hipLaunchKernelGGL(k_gram_tables, dim3((unsigned)std::min<int64_t>(nd, 65536)), dim3(64),
+                           0, s, dw + P.gram_first, nd, pos, db->d_arity, C, (int64_t)np, tables);
         FC_HIP(hipGetLastError());
     }
     if (db->m > 0) {
@@ -1546,7 +1666,7 @@ static int run_batch(fc_db *db, Plan &P, int32_t *tables, uint32_t reducers, dou
     ensure_attrs();
     Image I;
     make_image(db, P, reducers, I);
-    const size_t img = (I.bytes + 255) & ~(size_t)255;
+    const size_t img = (I.dev_bytes + 255) & ~(size_t)255;
     const size_t tbytes = tables ? 0 : sizeof(int32_t) * (size_t)std::max<int64_t>(P.total_cells, 1);
     Workspace *w = workspace_acquire(db, img + tbytes, s);
     if (!w) {
@@ -1782,6 +1902,8 @@ extern "C" int fc_batch_footprint(const fc_db *db, const int32_t *vars_flat,
     if ((rc = build_plan(db, vars_flat, var_off, nq, nullptr, flags, true, P))) return rc;
     *bytes = (int64_t)sizeof(int32_t) * P.total_cells +
              (int64_t)sizeof(QDesc) * (int64_t)(P.work.size() + P.query.size()) +
+             (int64_t)sizeof(int32_t) * ((int64_t)P.gram_np * P.gram_np + P.gram_np +
+                                         (int64_t)P.gram_pos.size()) +
              (int64_t)sizeof(float) * 2 * 4 * nq;
     return FC_OK;
 }
@@ -1826,30 +1948,60 @@ extern "C" int fc_db_set_tuning(fc_db *db, const fc_tuning *t) {
 
 namespace fc {
 
-// Device time of one batch under the current tuning (median of `reps`).
+// Time per batch under the current tuning: one warm-up call, then `reps`
+// calls back to back between two events, so the host's planning of a call
+// overlaps the device work of the one before it.
 static int time_batch(fc_db *db, const std::vector<int32_t> &flat,
                       const std::vector<int64_t> &off, uint32_t flags, int32_t *tables,
                       hipStream_t s, int reps, float &ms_out) {
     const int64_t nq = (int64_t)off.size() - 1;
+    int rc = fc_count_batch(db, flat.data(), off.data(), nq, tables, nullptr, flags, s);
+    if (rc) return rc;
+    FC_HIP(hipStreamSynchronize(s));
     hipEvent_t a, b;
     FC_HIP(hipEventCreate(&a));
-    FC_HIP(hipEventCreate(&b));
-    float best = 1e30f;
-    int rc = FC_OK;
-    for (int r = 0; r <= reps && rc == FC_OK; ++r) {  // first run warms up
-        (void)hipEventRecord(a, s);
-        rc = fc_count_batch(db, flat.data(), off.data(), nq, tables, nullptr, flags, s);
-        (void)hipEventRecord(b, s);
-        if (rc == FC_OK && hipEventSynchronize(b) == hipSuccess) {
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, a, b);
-            if (r > 0) best = std::min(best, ms);
-        }
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        set_error("hipEventCreate failed");
+        return FC_ERR_DEVICE;
     }
+    (void)hipEventRecord(a, s);
+    for (int r = 0; r < reps && rc == FC_OK; ++r)
+        rc = fc_count_batch(db, flat.data(), off.data(), nq, tables, nullptr, flags, s);
+    (void)hipEventRecord(b, s);
+    float ms = 0.f;
+    const hipError_t e = rc == FC_OK ? hipEventSynchronize(b) : hipSuccess;
+    if (rc == FC_OK && e == hipSuccess) (void)hipEventElapsedTime(&ms, a, b);
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     if (rc) return rc;
-    ms_out = best;
+    if (e != hipSuccess) {
+        set_error("hipEventSynchronize: %s", hipGetErrorString(e));
+        return FC_ERR_DEVICE;
+    }
+    ms_out = ms / (float)reps;
+    return FC_OK;
+}
+
+// The queries of a batch whose automatic plan counts them with bitmaps
+// (bitmap = true) or with histograms and partitions (false), in batch order.
+static int plan_subset(fc_db *db, const int32_t *vars_flat, const int64_t *var_off, int64_t nq,
+                       bool bitmap, std::vector<int32_t> &f, std::vector<int64_t> &o) {
+    Plan P;
+    const int rc = build_plan(db, vars_flat, var_off, nq, nullptr, FC_STRAT_AUTO, false, P);
+    if (rc) return rc;
+    std::vector<uint8_t> sel((size_t)nq, 0);
+    for (const Launch &L : P.launches)
+        if ((L.strat == S_BITMAP) == bitmap)
+            for (int64_t d = L.first; d < L.first + L.count; ++d)
+                sel[(size_t)P.work[(size_t)d].qid] = 1;
+    f.clear();
+    o.assign(1, 0);
+    for (int64_t i = 0; i < nq; ++i)
+        if (sel[(size_t)i]) {
+            f.insert(f.end(), vars_flat + var_off[i], vars_flat + var_off[i + 1]);
+            o.push_back((int64_t)f.size());
+        }
     return FC_OK;
 }
 
@@ -1876,14 +2028,21 @@ extern "C" int fc_autotune(fc_db *db, const int32_t *vars_flat, const int64_t *v
     std::vector<int64_t> off(var_off, var_off + nq + 1);
     const int64_t cand[] = {16384, 32768, 65536, 131072, 262144, 524288};
     auto sweep_chunks = [&](int which) -> int {
-        // the current value is kept unless another is at least 3% faster
+        // timed on the queries the setting affects (those the automatic plan
+        // counts with histograms, or with bitmaps); the current value is kept
+        // unless another is at least 3% faster
+        std::vector<int32_t> sf;
+        std::vector<int64_t> so;
+        int r = plan_subset(db, vars_flat, var_off, nq, which == 1, sf, so);
+        if (r) return r;
+        if (so.size() < 2) return FC_OK;
         const int64_t cur = which == 0 ? db->tune.chunk_rows : db->tune.bitmap_chunk_rows;
         int64_t best = cur;
         float best_ms = 1e30f, cur_ms = 1e30f;
         for (int64_t c : cand) {
             if (which == 0) db->tune.chunk_rows = c; else db->tune.bitmap_chunk_rows = c;
             float ms = 0.f;
-            int r = time_batch(db, flat, off, FC_STRAT_AUTO, tables, s, 5, ms);
+            r = time_batch(db, sf, so, FC_STRAT_AUTO, tables, s, 5, ms);
             if (r) return r;
             if (c == cur) cur_ms = ms;
             if (ms < best_ms) {
@@ -2089,7 +2248,7 @@ extern "C" int fc_graph_create(fc_db *db, const int32_t *vars_flat, const int64_
     } guard{g};
     if ((rc = build_plan(db, vars_flat, var_off, nq, table_off, flags, reducers != 0, g->P))) return rc;
     make_image(db, g->P, reducers, g->I);
-    FC_HIP(hipMalloc(&g->dimg, g->I.bytes));
+    FC_HIP(hipMalloc(&g->dimg, g->I.dev_bytes));
     std::vector<char> host(g->I.bytes);
     fill_image(g->P, g->I, host.data());
     FC_HIP(hipMemcpy(g->dimg, host.data(), g->I.bytes, hipMemcpyHostToDevice));

@@ -159,6 +159,16 @@ struct ProfScope {
 int count_reduce_device(fc_db *db, const int32_t *vars_flat, const int64_t *var_off, int64_t nq,
                         uint32_t reducers, double ess, float *scores, hipStream_t s);
 
+// Gram of bit-vector rows (fc_pairs.hip): C[i][j] = Count(row i AND row j)
+// for every i <= j of the np = rowidx entries (np a multiple of 256; -1 is
+// an all-zero padding row), over all instances, on the matrix cores.  C
+// (np x np int32, leading dimension ldc) must be zero on entry; entries
+// below the diagonal are unspecified.  name/alg_bytes/alg_ops label the
+// launch for profiling.
+hipError_t launch_gram(const fc_db *db, const int32_t *rowidx, int32_t np, int32_t *C,
+                       int64_t ldc, const char *name, double alg_bytes, double alg_ops,
+                       hipStream_t s);
+
 // Reducer launch (fc_reduce.hip).  descs: exactly one QDesc per query
 // (device, any order); scores[slot * nq + qid].
 hipError_t launch_reduce(const fc_db *db, const QDesc *descs, int64_t nd, int64_t nq,

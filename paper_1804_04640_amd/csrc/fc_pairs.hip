@@ -266,6 +266,30 @@ __global__ void k_mirror(const int32_t *__restrict__ C, int32_t ldc, int32_t ni,
 
 }  // namespace
 
+hipError_t launch_gram(const fc_db *db, const int32_t *rowidx, int32_t np, int32_t *C,
+                       int64_t ldc, const char *name, double alg_bytes, double alg_ops,
+                       hipStream_t s) {
+    if (db->m == 0 || np == 0) return hipSuccess;
+    const int32_t ncb = np / kGC, nrb = np / kGT;
+    int32_t npairs = 0;  // (row block, column block) pairs reaching the upper triangle
+    for (int32_t I = 0; I < nrb; ++I) npairs += ncb - I / 2;
+    const int64_t tiles = db->words / (kTileRows / 64);
+    // two workgroups per CU are resident: as many splits as fill them once,
+    // whole 64-word tiles each
+    int64_t splits = 2 * (int64_t)db->cu_count / npairs;
+    splits = std::min<int64_t>(splits, tiles);
+    // at most 4096 tiles (2^24 instances) per workgroup keeps the fp32 sums exact
+    splits = std::max<int64_t>(splits, (tiles + 4095) / 4096);
+    if (splits < 1) splits = 1;
+    ProfScope ps(name, s, alg_bytes, alg_ops);
+    hipLaunchKernelGGL(k_gram, dim3((unsigned)(npairs * splits)), dim3(256), 0, s, db->d_bits,
+                       db->words, db->pitch / 64, rowidx, nrb, ncb, npairs, (int32_t)splits, C,
+                       (int32_t)ldc);
+    const hipError_t e = hipGetLastError();
+    ps.end(s);
+    return e;
+}
+
 }  // namespace fc
 
 using namespace fc;
@@ -291,7 +315,6 @@ extern "C" int fc_pairs(fc_db *db, const int32_t *items, int32_t ni, double mins
     }
     const int32_t ncb = (ni + kGC - 1) / kGC;  // column blocks
     const int32_t np = ncb * kGC;              // items padded to whole blocks
-    const int32_t nrb = np / kGT;              // row blocks
     std::vector<int32_t> rowidx((size_t)np, -1);
     std::vector<uint8_t> seen((size_t)db->n, 0);
     for (int32_t i = 0; i < ni; ++i) {
@@ -344,26 +367,9 @@ extern "C" int fc_pairs(fc_db *db, const int32_t *items, int32_t ni, double mins
     FC_HIP(hipMemcpyAsync(d_row, rowidx.data(), sizeof(int32_t) * (size_t)np,
                           hipMemcpyHostToDevice, s));
     FC_HIP(fill_zero_i32(C, (int64_t)np * np, s));
-    int32_t npairs = 0;  // (row block, column block) pairs reaching the upper triangle
-    for (int32_t I = 0; I < nrb; ++I) npairs += ncb - I / 2;
-    const int64_t tiles = db->words / (kTileRows / 64);
-    // two workgroups per CU are resident: as many splits as fill them once,
-    // whole 64-word tiles each
-    int64_t splits = 2 * (int64_t)db->cu_count / npairs;
-    splits = std::min<int64_t>(splits, tiles);
-    // at most 4096 tiles (2^24 instances) per workgroup keeps the fp32 sums exact
-    splits = std::max<int64_t>(splits, (tiles + 4095) / 4096);
-    if (splits < 1) splits = 1;
-    if (db->m > 0) {
-        const double ops = 2.0 * (double)db->m * (double)ni * (double)(ni + 1) / 2.0;
-        ProfScope ps("k_gram", s, 0.0, ops);
-        hipLaunchKernelGGL(k_gram, dim3((unsigned)(npairs * splits)), dim3(256), 0, s,
-                           db->d_bits, db->words, db->pitch / 64, (const int32_t *)d_row, nrb, ncb,
-                           npairs,
-                           (int32_t)splits, C, (int32_t)ldc);
-        FC_HIP(hipGetLastError());
-        ps.end(s);
-    }
+    // algorithmic work: the upper triangle with the diagonal, 2 ops per pair and instance
+    const double ops = (double)db->m * (double)ni * (double)(ni + 1);
+    FC_HIP(launch_gram(db, d_row, np, C, ldc, "k_gram", 0.0, ops, s));
     // records: per-row counts -> offsets (host) -> ordered writes
     hipLaunchKernelGGL(k_pair_count, dim3((unsigned)((ni + 3) / 4)), dim3(256), 0, s, C,
                        (int32_t)ldc, ni, (int32_t)std::min<int64_t>(nmin, INT32_MAX),

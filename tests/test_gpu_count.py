@@ -488,3 +488,54 @@ def test_empty_database_then_appends():
         freq, _ = arm.mine(db, minsup=0.1, minconf=0.5, items=[0, 2, 4])
         ref, _ = orc.arm_bruteforce(D[[0, 2, 4]], 0.1, 0.5, max_size=6)
         assert freq == {tuple([0, 2, 4][i] for i in s): c for s, c in ref.items()}
+
+
+def test_small_queries_from_state_gram():
+    """A batch whose one- and two-variable queries outweigh the Gram of their
+    variables' state bit-vectors (15,000 BN-family queries, m = 10^6) takes
+    those tables from that Gram (automatic strategy; k_gram_states runs).
+    Every small query's table equals the oracle's; all tables equal the
+    forced histogram path's, packed and placed (reversed order with gaps);
+    fused scores equal the forced path's bitwise; a captured graph replays
+    to the same scores twice."""
+    w = synth.bn_family()
+    qs = w.queries()[:15000]
+    small = [i for i, q in enumerate(qs) if len(q) <= 2]
+    print("state gram: %d queries, %d small" % (len(qs), len(small)), flush=True)
+    with Database(w.D, w.arity) as db:
+        _lib.fc_profile_enable(True)
+        _lib.fc_profile_read(reset=True)
+        t_auto, toff = db.count_batch(qs)
+        torch.cuda.synchronize()
+        prof = _lib.fc_profile_read(reset=True)
+        _lib.fc_profile_enable(False)
+        assert "k_gram_states" in prof
+        t_hist, toff2 = db.count_batch(qs, strategy="hist")
+        assert np.array_equal(toff, toff2)
+        A, H = t_auto.cpu().numpy(), t_hist.cpu().numpy()
+        assert np.array_equal(A, H)
+        for i in small:
+            ref = orc.count(w.D, w.arity, qs[i])
+            assert np.array_equal(A[toff[i]:toff[i] + len(ref)], ref), (i, list(qs[i]))
+        cells = np.diff(toff)
+        placed = np.zeros(len(qs) + 1, np.int64)
+        pos = 0
+        for i in reversed(range(len(qs))):
+            placed[i] = pos
+            pos += int(cells[i]) + 3
+        placed[-1] = pos
+        buf = torch.full((pos,), -7, dtype=torch.int32, device="cuda")
+        db.count_batch(qs, tables=buf, table_off=placed)
+        B = buf.cpu().numpy()
+        for i in range(len(qs)):
+            assert np.array_equal(B[placed[i]:placed[i] + cells[i]], A[toff[i]:toff[i + 1]]), i
+        sa, _, _, _ = db.count_reduce(qs, ("mdl", "bdeu", "mi"))
+        sh, _, _, _ = db.count_reduce(qs, ("mdl", "bdeu", "mi"), strategy="hist")
+        for r in sa:
+            assert torch.equal(sa[r], sh[r]), r
+        g = db.graph(qs, ("mdl",))
+        for _ in range(2):
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(g.result()["mdl"], sa["mdl"])
+        g.close()
