@@ -1614,8 +1614,10 @@ static int enqueue_batch(fc_db *db, const Plan &P, const Image &I, void *dimg, i
         FC_HIP(fill_zero_i32(C, (int64_t)np * np, s));
         FC_HIP(launch_gram(db, rows, np, C, np, "k_gram_states", P.gram_bytes, P.gram_ops, s));
         const int64_t nd = P.gram_count;
+        ProfScope ps("k_gram_tables", s, 0.0, 0.0);
         hipLaunchKernelGGL(k_gram_tables, dim3((unsigned)std::min<int64_t>(nd, 65536)), dim3(64),
                            0, s, dw + P.gram_first, nd, pos, db->d_arity, C, (int64_t)np, tables);
+        ps.end(s);
         FC_HIP(hipGetLastError());
     }
     if (db->m > 0) {
