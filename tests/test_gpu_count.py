@@ -539,3 +539,31 @@ def test_small_queries_from_state_gram():
             torch.cuda.synchronize()
             assert torch.equal(g.result()["mdl"], sa["mdl"])
         g.close()
+
+
+def test_state_gram_ragged_and_after_appends():
+    """The state-Gram path at m = 10^6 + 37 (a ragged last 64-instance word)
+    and on a handle built from the first 600,011 instances with the rest
+    appended: every small query's table equals the oracle's, and the
+    appended handle's tables equal the fresh handle's."""
+    w = synth.bn_family(m=1_000_037, nq=15000)
+    qs = w.queries()
+    small = [i for i, q in enumerate(qs) if len(q) <= 2]
+    with Database(w.D, w.arity) as db:
+        _lib.fc_profile_enable(True)
+        _lib.fc_profile_read(reset=True)
+        t_fresh, toff = db.count_batch(qs)
+        torch.cuda.synchronize()
+        prof = _lib.fc_profile_read(reset=True)
+        _lib.fc_profile_enable(False)
+        assert "k_gram_states" in prof
+        A = t_fresh.cpu().numpy()
+    for i in small:
+        ref = orc.count(w.D, w.arity, qs[i])
+        assert np.array_equal(A[toff[i]:toff[i] + len(ref)], ref), (i, list(qs[i]))
+    m0 = 600_011
+    with Database(np.ascontiguousarray(w.D[:, :m0]), w.arity) as db:
+        db.append(np.ascontiguousarray(w.D[:, m0:]))
+        t_app, toff2 = db.count_batch(qs)
+        assert np.array_equal(toff, toff2)
+        assert np.array_equal(t_app.cpu().numpy(), A)
