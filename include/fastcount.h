@@ -65,7 +65,12 @@ typedef struct fc_db fc_db;
 #define FC_DB_BITVECTORS 1u     /* also build per-state bit-vectors        */
 #define FC_DB_DATA_ON_DEVICE 2u /* `data` is a device pointer              */
 
-/* Strategy field of the batch flags (low 4 bits). */
+/* Strategy field of the batch flags (low 4 bits).  FC_STRAT_AUTO chooses per
+ * query shape (tuning below); in a large batch on a handle with bit-vectors
+ * it may also count every one- and two-variable query at once as the Gram
+ * of their variables' state bit-vectors (Section 3.2's two-vector
+ * intersections on the matrix cores).  Every strategy yields identical
+ * counts. */
 #define FC_STRAT_AUTO 0u      /* per-query choice by the cost model / tuner */
 #define FC_STRAT_HIST 1u      /* joint key + LDS histogram (Section 3.3)    */
 #define FC_STRAT_BITMAP 2u    /* AND of bit-vectors + popcount (Sec. 3.2)   */
@@ -417,14 +422,16 @@ int fc_autotune(fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
  * every kernel launch with a pair of HIP events on the launch's stream and
  * attributes to it the algorithmic work it performs: bytes of state columns
  * a column scan must read (k bytes per query and instance) for counting
- * kernels, and 2 m n^2 integer operations for the co-occurrence Gram.
+ * kernels, and m n (n + 1) matrix-core operations (2 per item pair and
+ * instance over the upper triangle with the diagonal) for the co-occurrence
+ * Gram.
  */
 typedef struct fc_kernel_stat {
     char name[48];     /* kernel instance, e.g. "k_hist<3,1>"              */
     int64_t launches;  /* launches timed since the last reset              */
     double ms;         /* summed event-measured duration                   */
     double alg_bytes;  /* summed algorithmic bytes                         */
-    double alg_ops;    /* summed algorithmic integer operations            */
+    double alg_ops;    /* summed algorithmic matrix-core operations        */
 } fc_kernel_stat;
 
 /* Turn launch profiling on (1) or off (0) for the whole process. */
