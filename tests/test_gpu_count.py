@@ -567,3 +567,31 @@ def test_state_gram_ragged_and_after_appends():
         t_app, toff2 = db.count_batch(qs)
         assert np.array_equal(toff, toff2)
         assert np.array_equal(t_app.cpu().numpy(), A)
+
+
+def test_state_gram_edge_arities():
+    """The state-Gram path with single-state and 255-state variables (689
+    states: three 256-row blocks of the Gram), 30,000 one- and two-variable
+    queries at m = 2^18 + 3: every table equals the oracle's, including the
+    one-cell tables of single-state variables and tables of 65,025 cells."""
+    rng = synth.rng_for(97)
+    m = (1 << 18) + 3
+    ar = np.concatenate([rng.integers(1, 5, size=20), [255, 255, 128]]).astype(np.uint8)
+    ar[:2] = 1
+    n = len(ar)
+    D = np.stack([rng.integers(0, a, size=m) for a in ar]).astype(np.uint8)
+    qs = [rng.choice(n, size=int(rng.integers(1, 3)), replace=False).astype(np.int32)
+          for _ in range(30000)]
+    qs += [np.array([0], np.int32), np.array([1, 20], np.int32), np.array([20, 21], np.int32)]
+    with Database(D, ar) as db:
+        _lib.fc_profile_enable(True)
+        _lib.fc_profile_read(reset=True)
+        t, toff = db.count_batch(qs)
+        torch.cuda.synchronize()
+        prof = _lib.fc_profile_read(reset=True)
+        _lib.fc_profile_enable(False)
+        assert "k_gram_states" in prof
+        T = t.cpu().numpy()
+    for i, q in enumerate(qs):
+        ref = orc.count(D, ar, q)
+        assert np.array_equal(T[toff[i]:toff[i] + len(ref)], ref), (i, list(q))
