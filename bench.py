@@ -247,6 +247,8 @@ def bench_parents(args):
                       "tuning": tuning},
            "families_scored": stats["scored"], "families_pruned": stats["pruned"],
            "levels": stats["levels"], "gpu_kernel_s": gpu_ms / 1e3,
+           "kernels": {k: {"launches": v["launches"], "ms": v["ms"]}
+                       for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])[:12]},
            "query_rows_per_s": stats["scored"] * w.m / dt,
            "best_parents": {int(c): list(p) for c, (p, _) in sorted(best.items())}}
     db.close()

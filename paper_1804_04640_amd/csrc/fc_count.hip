@@ -129,7 +129,8 @@ __device__ __forceinline__ void hist_body(const uint8_t *__restrict__ cols, int6
         uint32_t sum = 0;
         for (int32_t p = 0; p < copies; ++p) sum += lds[p * cs + cell];
         if (cell == 0 && has_pad) sum -= (uint32_t)pad_rows;  // padding rows are key 0
-        if (sum) atomicAdd(&out[cell], (int32_t)sum);
+        if (chunks == 1) out[cell] = (int32_t)sum;  // the window's only workgroup
+        else if (sum) atomicAdd(&out[cell], (int32_t)sum);
     }
 }
 
@@ -158,8 +159,12 @@ __device__ __forceinline__ void zero_cols(uint32_t *lds, int32_t words) {
     }
 }
 
+// direct: this workgroup is the only one counting these cells (one row
+// chunk), so every cell is stored, zeros included, and the table needs no
+// zeroing first; otherwise non-zero partial counts are added atomically.
 __device__ __forceinline__ void flush_cols(const uint32_t *lds, int32_t cells, int32_t B,
-                                           bool has_pad, int32_t pad_rows, int32_t *out) {
+                                           bool has_pad, int32_t pad_rows, bool direct,
+                                           int32_t *out) {
     if (B >= 4) {
         const int32_t per = B / 4;  // threads per cell: 1, 2, 4, 8 or 16
         const int32_t total = cells * per;
@@ -175,7 +180,8 @@ __device__ __forceinline__ void flush_cols(const uint32_t *lds, int32_t cells, i
             if (i < total && (i & (per - 1)) == 0) {
                 const int32_t cell = i / per;
                 if (cell == 0 && has_pad) sum -= (uint32_t)pad_rows;  // padding rows are key 0
-                if (sum) atomicAdd(&out[cell], (int32_t)sum);
+                if (direct) out[cell] = (int32_t)sum;
+                else if (sum) atomicAdd(&out[cell], (int32_t)sum);
             }
         }
     } else {
@@ -183,7 +189,8 @@ __device__ __forceinline__ void flush_cols(const uint32_t *lds, int32_t cells, i
             uint32_t sum = 0;
             for (int32_t j = 0; j < B; ++j) sum += lds[cell * B + j];
             if (cell == 0 && has_pad) sum -= (uint32_t)pad_rows;
-            if (sum) atomicAdd(&out[cell], (int32_t)sum);
+            if (direct) out[cell] = (int32_t)sum;
+            else if (sum) atomicAdd(&out[cell], (int32_t)sum);
         }
     }
 }
@@ -256,7 +263,8 @@ __device__ __forceinline__ void hist16_body(const uint8_t *__restrict__ cols, in
         }
     }
     __syncthreads();
-    flush_cols(lds, cells, B, (r1 == tiles * kTileRows) && (r0 < r1), pad_rows, tables + q.table_off);
+    flush_cols(lds, cells, B, (r1 == tiles * kTileRows) && (r0 < r1), pad_rows, chunks == 1,
+               tables + q.table_off);
 }
 
 // LDS byte address of byte-key `i` of `key` (selector 0x0c0c0400 + i*256):
@@ -324,7 +332,8 @@ __device__ __forceinline__ void hist8_body(const uint8_t *__restrict__ cols, int
         }
     }
     __syncthreads();
-    flush_cols(lds, cells, B, (r1 == tiles * kTileRows) && (r0 < r1), pad_rows, tables + q.table_off);
+    flush_cols(lds, cells, B, (r1 == tiles * kTileRows) && (r0 < r1), pad_rows, chunks == 1,
+               tables + q.table_off);
 }
 
 // CAP: the launch group's largest table.  The histogram is a static LDS
@@ -415,7 +424,8 @@ __device__ __forceinline__ void hist8n_body(const uint8_t *__restrict__ nib, int
         }
     }
     __syncthreads();
-    flush_cols(lds, cells, B, (r1 == tiles * kTileRows) && (r0 < r1), pad_rows, tables + q.table_off);
+    flush_cols(lds, cells, B, (r1 == tiles * kTileRows) && (r0 < r1), pad_rows, chunks == 1,
+               tables + q.table_off);
 }
 
 template <int K, int CAP>
@@ -501,7 +511,8 @@ __device__ __forceinline__ void hist16n_body(const uint8_t *__restrict__ nib, in
         }
     }
     __syncthreads();
-    flush_cols(lds, cells, B, (r1 == tiles * kTileRows) && (r0 < r1), pad_rows, tables + q.table_off);
+    flush_cols(lds, cells, B, (r1 == tiles * kTileRows) && (r0 < r1), pad_rows, chunks == 1,
+               tables + q.table_off);
 }
 
 template <int K, bool WIDE>
@@ -900,6 +911,9 @@ struct Plan {
     std::vector<int32_t> gram_rows;    // bit-vector row of each Gram row (-1: padding)
     std::vector<int32_t> gram_pos;     // [n] Gram row of a variable's state 0
     double gram_bytes = 0.0, gram_ops = 0.0;
+    // every counting launch stores whole tables (or key windows) from one
+    // workgroup each: the tables need no zeroing first
+    bool direct = false;
 };
 
 // LDS size classes; every class but the last keeps its byte addresses below
@@ -1353,6 +1367,9 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
                         snprintf(L.name, sizeof L.name, "k_hist<%d,%d>", K, sm);
                     P.launches.push_back(L);
                 }
+    P.direct = db->m > 0;
+    for (const Launch &L : P.launches)
+        if (L.strat == S_BITMAP || L.chunks != 1) P.direct = false;
     return FC_OK;
 }
 
@@ -1598,7 +1615,9 @@ static int enqueue_batch(fc_db *db, const Plan &P, const Image &I, void *dimg, i
                          hipStream_t s) {
     const QDesc *dw = (const QDesc *)dimg;
     const QDesc *dq = (const QDesc *)((char *)dimg + I.off_query);
-    if (P.packed) {
+    if (P.direct) {
+        // every cell is stored by its counting launch
+    } else if (P.packed) {
         FC_HIP(fill_zero_i32(tables, P.total_cells, s));
     } else if (!P.query.empty()) {
         const int32_t nd = (int32_t)P.query.size();
