@@ -287,7 +287,8 @@ int fc_score_parent_sets(fc_db *db, int32_t child, const int32_t *cand,
 /*
  * All 2-itemset supports of binary items (association rule mining, Section
  * 4.3) from the co-occurrence Gram matrix A^T A of the one-hot instance x item
- * matrix, computed with int8 MFMA and exact int32 accumulation.  items lists
+ * matrix, computed exactly on the FP4 matrix cores (0/1 operands, fp32
+ * partial sums of at most 2^24 instances, int32 totals).  items lists
  * ni distinct variables of arity 2 (state 1 = item present); NULL means all
  * variables.  gram (nullable, ni*ni int32, row-major) receives the full
  * symmetric matrix.  Every pair a < b with n_ab / m > minsup is written to

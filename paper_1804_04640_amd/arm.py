@@ -2,7 +2,7 @@
 
 Items are binary variables; an instance contains item a when X_a = 1.  The
 level-wise search runs in the library (``fc_mine``): level 1 from the
-database marginals, level 2 from the co-occurrence Gram (int8 MFMA), and
+database marginals, level 2 from the co-occurrence Gram (FP4 matrix cores), and
 every level k >= 3 from candidates joined out of the frequent
 (k-1)-itemsets that share their first k-2 items, pruned by
 anti-monotonicity and counted as batched single-assignment queries

@@ -3,7 +3,7 @@
 //
 //   level 1   item supports from the database marginals;
 //   level 2   every pair support at once from the co-occurrence Gram
-//             (fc_pairs, int8 MFMA);
+//             (fc_pairs, FP4 matrix cores);
 //   level k   candidates joined from frequent (k-1)-itemsets that share their
 //             first k-2 items, kept when every (k-1)-subset is frequent
 //             (anti-monotonicity), counted in batches of single-assignment
