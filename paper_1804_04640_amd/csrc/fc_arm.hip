@@ -43,21 +43,33 @@ struct Level {
     std::vector<int64_t> count;  // n
     int64_t size() const { return (int64_t)count.size(); }
     const int32_t *at(int64_t i) const { return items.data() + i * k; }
+    // open-addressing index of the itemsets (built once the level is final)
+    std::vector<int64_t> slot;  // itemset index, -1 empty
+    uint64_t mask = 0;
+    static uint64_t hash(const int32_t *s, int32_t k) {
+        uint64_t h = 0x9E3779B97F4A7C15ull;
+        for (int32_t t = 0; t < k; ++t) {
+            h = (h ^ (uint32_t)s[t]) * 0xBF58476D1CE4E5B9ull;
+            h ^= h >> 31;
+        }
+        return h;
+    }
+    void index() {
+        uint64_t cap = 16;
+        while (cap < 2 * (uint64_t)size()) cap <<= 1;
+        slot.assign(cap, -1);
+        mask = cap - 1;
+        for (int64_t i = 0; i < size(); ++i) {
+            uint64_t h = hash(at(i), k) & mask;
+            while (slot[h] >= 0) h = (h + 1) & mask;
+            slot[h] = i;
+        }
+    }
     // index of the itemset equal to s (k items), or -1
     int64_t find(const int32_t *s) const {
-        int64_t lo = 0, hi = size();
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            const int c = cmp(at(mid), s);
-            if (c == 0) return mid;
-            if (c < 0) lo = mid + 1; else hi = mid;
-        }
+        for (uint64_t h = hash(s, k) & mask; slot[h] >= 0; h = (h + 1) & mask)
+            if (std::equal(s, s + k, at(slot[h]))) return slot[h];
         return -1;
-    }
-    int cmp(const int32_t *a, const int32_t *b) const {
-        for (int32_t t = 0; t < k; ++t)
-            if (a[t] != b[t]) return a[t] < b[t] ? -1 : 1;
-        return 0;
     }
 };
 
@@ -65,46 +77,51 @@ bool frequent(int64_t count, int64_t m, double minsup) {
     return m > 0 && (double)count / (double)m > minsup;
 }
 
-// Apriori join of `prev` (sorted (k-1)-itemsets): pairs a < b of a block that
-// shares the first k-2 items give prefix + {last_a, last_b}; a candidate is
-// kept when each of its (k-1)-subsets that drops one of the prefix items is
-// in `prev` (the two that drop a last item are the joined pair itself).
-// Blocks are split over host threads; the output stays lexicographic.
+// Apriori join of `prev` (sorted, indexed (k-1)-itemsets): pairs a < b of a
+// block that shares the first k-2 items give prefix + {last_a, last_b}; a
+// candidate is kept when each of its (k-1)-subsets that drops one of the
+// prefix items is in `prev` (the two that drop a last item are the joined
+// pair itself).  Rows a are split over host threads in contiguous ranges of
+// equal pair counts (one block can hold most of the pairs); concatenating
+// the ranges keeps the output lexicographic.
 std::vector<int32_t> candidates(const Level &prev) {
     const int32_t k1 = prev.k, k = k1 + 1;
     const int64_t n = prev.size();
-    std::vector<int64_t> blocks;  // block starts, plus n
+    std::vector<int64_t> bend((size_t)n), wsum((size_t)n + 1, 0);  // block end, pair prefix sums
     for (int64_t i = 0; i < n;) {
-        blocks.push_back(i);
         int64_t j = i + 1;
         while (j < n && std::equal(prev.at(i), prev.at(i) + (k1 - 1), prev.at(j))) ++j;
+        for (int64_t x = i; x < j; ++x) bend[(size_t)x] = j;
         i = j;
     }
-    blocks.push_back(n);
-    const int64_t nb = (int64_t)blocks.size() - 1;
+    for (int64_t a = 0; a < n; ++a) wsum[(size_t)a + 1] = wsum[(size_t)a] + (bend[(size_t)a] - a - 1);
+    const int64_t total = wsum[(size_t)n];
     unsigned hw = std::thread::hardware_concurrency();
-    const int64_t T = std::max<int64_t>(1, std::min<int64_t>({(int64_t)std::min(16u, hw ? hw : 1u),
-                                                             nb, n / 2048 + 1}));
+    const int64_t T = std::max<int64_t>(
+        1, std::min<int64_t>((int64_t)std::min(16u, hw ? hw : 1u), total / 8192 + 1));
+    auto first_row = [&](int64_t t) {  // first row of range t
+        if (t >= T) return n;
+        return (int64_t)(std::lower_bound(wsum.begin(), wsum.end() - 1, total * t / T) -
+                         wsum.begin());
+    };
     std::vector<std::vector<int32_t>> part((size_t)T);
     auto work = [&](int64_t t) {
         std::vector<int32_t> &out = part[(size_t)t];
-        std::vector<int32_t> cand((size_t)k), sub((size_t)k1);
-        for (int64_t bi = nb * t / T; bi < nb * (t + 1) / T; ++bi) {
-            const int64_t lo = blocks[(size_t)bi], hi = blocks[(size_t)bi + 1];
-            for (int64_t a = lo; a < hi; ++a)
-                for (int64_t b = a + 1; b < hi; ++b) {
-                    std::copy(prev.at(a), prev.at(a) + k1, cand.begin());
-                    cand[(size_t)k1] = prev.at(b)[k1 - 1];
-                    bool ok = true;
-                    for (int32_t x = 0; ok && x < k - 2; ++x) {
-                        int32_t u = 0;
-                        for (int32_t t2 = 0; t2 < k; ++t2)
-                            if (t2 != x) sub[(size_t)u++] = cand[(size_t)t2];
-                        ok = prev.find(sub.data()) >= 0;
-                    }
-                    if (ok) out.insert(out.end(), cand.begin(), cand.end());
+        int32_t cand[FC_MAX_VARS], sub[FC_MAX_VARS];
+        const int64_t ra = first_row(t), rb = first_row(t + 1);
+        for (int64_t a = ra; a < rb; ++a)
+            for (int64_t b = a + 1; b < bend[(size_t)a]; ++b) {
+                std::copy(prev.at(a), prev.at(a) + k1, cand);
+                cand[k1] = prev.at(b)[k1 - 1];
+                bool ok = true;
+                for (int32_t x = 0; ok && x < k - 2; ++x) {
+                    int32_t u = 0;
+                    for (int32_t t2 = 0; t2 < k; ++t2)
+                        if (t2 != x) sub[u++] = cand[t2];
+                    ok = prev.find(sub) >= 0;
                 }
-        }
+                if (ok) out.insert(out.end(), cand, cand + k);
+            }
     };
     if (T == 1) {
         work(0);
@@ -114,6 +131,9 @@ std::vector<int32_t> candidates(const Level &prev) {
         for (auto &x : th) x.join();
     }
     std::vector<int32_t> all;
+    size_t sz = 0;
+    for (auto &p : part) sz += p.size();
+    all.reserve(sz);
     for (auto &p : part) all.insert(all.end(), p.begin(), p.end());
     return all;
 }
@@ -177,6 +197,7 @@ extern "C" int fc_mine(fc_db *db, const int32_t *items, int32_t ni, double minsu
             }
         }
     }
+    L1.index();  // subset lookups of the next level and of the rules
     levels.push_back(std::move(L1));
 
     // level 2: the Gram's pair records over the frequent items
@@ -196,6 +217,7 @@ extern "C" int fc_mine(fc_db *db, const int32_t *items, int32_t ni, double minsu
             L2.items.push_back(p.items[(size_t)rec[(size_t)r].b]);
             L2.count.push_back(rec[(size_t)r].n_ab);
         }
+        L2.index();  // subset lookups of the next level and of the rules
         levels.push_back(std::move(L2));
     }
 
@@ -228,10 +250,21 @@ extern "C" int fc_mine(fc_db *db, const int32_t *items, int32_t ni, double minsu
                 }
         }
         if (L.size() == 0) break;
+        L.index();  // subset lookups of the next level and of the rules
         levels.push_back(std::move(L));
     }
 
     // itemsets, level by level
+    {
+        size_t ns = 0, nsi = 0;
+        for (const Level &L : levels) {
+            ns += (size_t)L.size();
+            nsi += (size_t)L.size() * (size_t)L.k;
+        }
+        R->set_items.reserve(nsi);
+        R->set_off.reserve(ns + 1);
+        R->set_count.reserve(ns);
+    }
     for (const Level &L : levels) {
         for (int64_t i = 0; i < L.size(); ++i) {
             R->set_items.insert(R->set_items.end(), L.at(i), L.at(i) + L.k);
@@ -344,6 +377,11 @@ extern "C" int fc_mine(fc_db *db, const int32_t *items, int32_t ni, double minsu
             std::sort(ord.begin() + start[(size_t)g], ord.begin() + start[(size_t)g + 1],
                       [&](int64_t a, int64_t b) { return cons_of(a) < cons_of(b); });
     const int64_t nr = (int64_t)rules.size();
+    {
+        size_t nri = 0;
+        for (const Rule &r : rules) nri += (size_t)levels[(size_t)r.li].k - 1;
+        R->rule_items.reserve(nri);
+    }
     R->rule_cons.resize((size_t)nr);
     R->rule_support.resize((size_t)nr);
     R->rule_conf.resize((size_t)nr);
