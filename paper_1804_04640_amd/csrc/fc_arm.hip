@@ -138,6 +138,62 @@ std::vector<int32_t> candidates(const Level &prev) {
     return all;
 }
 
+// Rule S - {X} => X of itemset i of level li (X = its item x): key is the
+// antecedent's index in level li - 1, replaced by the antecedent's rank in
+// tuple order once every level is known.
+struct Rule {
+    int64_t key;
+    int32_t li, i, x;
+    double conf;
+};
+
+// The rules of one level (itemsets of at least 2 items) against the level
+// below, on host threads, in itemset order.  False when an antecedent is
+// missing, which anti-monotonicity rules out for frequent itemsets.
+bool level_rules(const Level &L, const Level &below, int32_t li, double minconf,
+                 std::vector<Rule> &out) {
+    const int64_t n = L.size();
+    unsigned hw = std::thread::hardware_concurrency();
+    const int64_t T = std::max<int64_t>(
+        1, std::min<int64_t>((int64_t)std::min(16u, hw ? hw : 1u), n / 4096 + 1));
+    std::vector<std::vector<Rule>> part((size_t)T);
+    std::vector<char> bad((size_t)T, 0);
+    auto work = [&](int64_t t) {
+        int32_t ante[FC_MAX_VARS];
+        for (int64_t i = n * t / T; i < n * (t + 1) / T; ++i) {
+            const int32_t *sv = L.at(i);
+            const int64_t cnt = L.count[(size_t)i];
+            for (int32_t x = 0; x < L.k; ++x) {
+                int32_t u = 0;
+                for (int32_t t2 = 0; t2 < L.k; ++t2)
+                    if (t2 != x) ante[u++] = sv[t2];
+                const int64_t j = below.find(ante);
+                if (j < 0) {
+                    bad[(size_t)t] = 1;
+                    return;
+                }
+                const double conf = (double)cnt / (double)below.count[(size_t)j];
+                if (conf > minconf) part[(size_t)t].push_back({j, li, (int32_t)i, x, conf});
+            }
+        }
+    };
+    if (T == 1) {
+        work(0);
+    } else {
+        std::vector<std::thread> th;
+        for (int64_t t = 0; t < T; ++t) th.emplace_back(work, t);
+        for (auto &x : th) x.join();
+    }
+    size_t sz = 0;
+    for (int64_t t = 0; t < T; ++t) {
+        if (bad[(size_t)t]) return false;
+        sz += part[(size_t)t].size();
+    }
+    out.reserve(sz);
+    for (auto &p : part) out.insert(out.end(), p.begin(), p.end());
+    return true;
+}
+
 }  // namespace
 }  // namespace fc
 
@@ -182,6 +238,25 @@ extern "C" int fc_mine(fc_db *db, const int32_t *items, int32_t ni, double minsu
     } guard{R};
     const int64_t m = db->m;
     std::vector<Level> levels;
+    levels.reserve((size_t)max_size);  // rule threads hold references into it
+    // the rules of a level are generated on host threads while the device
+    // counts the next level
+    std::vector<std::vector<Rule>> lrules((size_t)max_size);
+    std::vector<char> lok((size_t)max_size, 1);
+    std::vector<std::thread> rtasks;
+    struct Join {
+        std::vector<std::thread> &t;
+        ~Join() {
+            for (auto &x : t)
+                if (x.joinable()) x.join();
+        }
+    } join_rules{rtasks};
+    auto start_rules = [&](int32_t li) {
+        const Level *L = &levels[(size_t)li], *below = &levels[(size_t)li - 1];
+        char *ok = &lok[(size_t)li];
+        std::vector<Rule> *out = &lrules[(size_t)li];
+        rtasks.emplace_back([=] { *ok = level_rules(*L, *below, li, minconf, *out) ? 1 : 0; });
+    };
 
     // level 1: supports from the marginals (state 1 of each item)
     Level L1;
@@ -219,6 +294,7 @@ extern "C" int fc_mine(fc_db *db, const int32_t *items, int32_t ni, double minsu
         }
         L2.index();  // subset lookups of the next level and of the rules
         levels.push_back(std::move(L2));
+        start_rules(1);
     }
 
     // levels 3..max_size: join, prune, count in batches, keep the frequent
@@ -252,6 +328,7 @@ extern "C" int fc_mine(fc_db *db, const int32_t *items, int32_t ni, double minsu
         if (L.size() == 0) break;
         L.index();  // subset lookups of the next level and of the rules
         levels.push_back(std::move(L));
+        start_rules((int32_t)levels.size() - 1);
     }
 
     // itemsets, level by level
@@ -306,57 +383,25 @@ extern "C" int fc_mine(fc_db *db, const int32_t *items, int32_t ni, double minsu
                     stack.push_back({li + 1, c});
         }
     }
-    // rules S - {X} => X of every frequent S with |S| >= 2, generated on host
-    // threads over the itemsets of each level
-    struct Rule {
-        int64_t key;  // rank of the antecedent
-        int32_t li, i, x;
-        double conf;
-    };
+    // rules S - {X} => X of every frequent S with |S| >= 2, level by level,
+    // each keyed by its antecedent's rank
+    for (auto &x : rtasks) x.join();
     std::vector<Rule> rules;
-    for (int32_t li = 1; li < nl; ++li) {
-        const Level &L = levels[(size_t)li], &below = levels[(size_t)li - 1];
-        const int64_t n = L.size();
-        unsigned hw = std::thread::hardware_concurrency();
-        const int64_t T = std::max<int64_t>(1, std::min<int64_t>((int64_t)std::min(16u, hw ? hw : 1u),
-                                                                 n / 4096 + 1));
-        std::vector<std::vector<Rule>> part((size_t)T);
-        std::vector<int> bad((size_t)T, 0);
-        auto work = [&](int64_t t) {
-            int32_t ante[FC_MAX_VARS];
-            for (int64_t i = n * t / T; i < n * (t + 1) / T; ++i) {
-                const int32_t *sv = L.at(i);
-                const int64_t cnt = L.count[(size_t)i];
-                for (int32_t x = 0; x < L.k; ++x) {
-                    int32_t u = 0;
-                    for (int32_t t2 = 0; t2 < L.k; ++t2)
-                        if (t2 != x) ante[u++] = sv[t2];
-                    const int64_t j = below.find(ante);
-                    if (j < 0) {  // anti-monotonicity makes this impossible
-                        bad[(size_t)t] = 1;
-                        return;
-                    }
-                    const double conf = (double)cnt / (double)below.count[(size_t)j];
-                    if (conf > minconf)
-                        part[(size_t)t].push_back({rank[(size_t)li - 1][(size_t)j], li, (int32_t)i, x,
-                                                   conf});
-                }
-            }
-        };
-        if (T == 1) {
-            work(0);
-        } else {
-            std::vector<std::thread> th;
-            for (int64_t t = 0; t < T; ++t) th.emplace_back(work, t);
-            for (auto &x : th) x.join();
-        }
-        for (int64_t t = 0; t < T; ++t) {
-            if (bad[(size_t)t]) {
+    {
+        size_t nrl = 0;
+        for (int32_t li = 1; li < nl; ++li) {
+            if (!lok[(size_t)li]) {
                 set_error("fc_mine: a subset of a frequent itemset is missing");
                 return FC_ERR_DEVICE;
             }
-            rules.insert(rules.end(), part[(size_t)t].begin(), part[(size_t)t].end());
+            nrl += lrules[(size_t)li].size();
         }
+        rules.reserve(nrl);
+        for (int32_t li = 1; li < nl; ++li)
+            for (Rule r : lrules[(size_t)li]) {
+                r.key = rank[(size_t)li - 1][(size_t)r.key];
+                rules.push_back(r);
+            }
     }
     // order: counting sort by antecedent rank, then by consequent within one
     // antecedent (a handful of rules each)
