@@ -251,9 +251,15 @@ double orc_mi(const int64_t *T, int64_t q, int32_t r)
         for (int32_t k = 0; k < r; ++k) {
             int64_t nijk = T[j * r + k];
             if (nijk > 0) {
-                double ratio = ((double)m * (double)nijk) /
-                               ((double)nij * (double)nk[k]);
-                acc_add(&a, ((double)nijk / (double)m) * log(ratio));
+                /* ln(m N_ijk / (N_ij N_k)) as ln(1 + x), x formed from the
+                 * exact integer difference m N_ijk - N_ij N_k (both below
+                 * 2^62): a ratio rounded first would carry an absolute
+                 * error near 1e-16 into every term, which is not small
+                 * against a mutual information close to 0 */
+                int64_t den = nij * nk[k];
+                int64_t num = m * nijk - den;
+                double x = (double)num / (double)den;
+                acc_add(&a, ((double)nijk / (double)m) * log1p(x));
             }
         }
     }

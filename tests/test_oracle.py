@@ -215,6 +215,47 @@ def test_mi_special_cases():
     assert orc.mi(np.array([5, 7, 9], np.int64), 3) == 0.0
 
 
+def decimal_mi(T, r, digits=50):
+    """MI of table T (child arity r) straight from its definition,
+    sum over non-zero cells of (N/m) ln(m N / (N_j N_k)), in 50-digit
+    decimal arithmetic (the exact value to far below binary64 rounding)."""
+    from decimal import Decimal, localcontext
+    Tq = np.asarray(T, np.int64).reshape(-1, r)
+    m = int(Tq.sum())
+    nj = [int(x) for x in Tq.sum(axis=1)]
+    nk = [int(x) for x in Tq.sum(axis=0)]
+    with localcontext() as ctx:
+        ctx.prec = digits
+        tot = Decimal(0)
+        for j in range(Tq.shape[0]):
+            for k in range(r):
+                n = int(Tq[j, k])
+                if n:
+                    tot += Decimal(n) / m * (Decimal(m * n) / (nj[j] * nk[k])).ln()
+        return float(tot)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_mi_of_nearly_independent_tables(seed):
+    """Near independence the terms of MI cancel to a value many orders of
+    magnitude below them; the oracle still matches the high-precision value
+    of the definition to 1e-9 relative (an evaluation that rounds each
+    ratio m N / (N_j N_k) before its logarithm is off by about 1e-6 here)."""
+    rng = np.random.default_rng(100 + seed)
+    q, r = int(rng.integers(2, 5)), int(rng.integers(2, 4))
+    # an exact product table plus a few unit moves keeping the margins close
+    rows = rng.integers(200_000, 1_200_000, size=q)
+    cols = rng.integers(2, 9, size=r)
+    Tq = np.outer(rows, cols).astype(np.int64)
+    for _ in range(3):
+        a, b = rng.integers(0, q), rng.integers(0, r)
+        Tq[a, b] += int(rng.integers(1, 40))
+    T = Tq.ravel()
+    ref = decimal_mi(T, r)
+    assert 0 < ref < 1e-7
+    assert orc.mi(T, r) == pytest.approx(ref, rel=1e-9)
+
+
 # ------------------------------------------------------------ pairs
 @pytest.mark.parametrize("seed", range(6))
 def test_gram_is_matmul(seed):

@@ -31,10 +31,10 @@ MUTANTS = [
     ("bdeu: dropped lnG(a_j)", "        acc_add(&a, lg_aj);\n", "\n"),
     ("bdeu: sign of lnG(a_j + N_ij)", "acc_add(&a, -lgamma(aj + (double)nij));",
      "acc_add(&a, lgamma(aj + (double)nij));"),
-    ("mi: weight N/N_ij", "acc_add(&a, ((double)nijk / (double)m) * log(ratio));",
-     "acc_add(&a, ((double)nijk / (double)nij) * log(ratio));"),
-    ("mi: ratio without m", "double ratio = ((double)m * (double)nijk) /",
-     "double ratio = ((double)nijk) /"),
+    ("mi: weight N/N_ij", "acc_add(&a, ((double)nijk / (double)m) * log1p(x));",
+     "acc_add(&a, ((double)nijk / (double)nij) * log1p(x));"),
+    ("mi: ratio without m", "int64_t num = m * nijk - den;",
+     "int64_t num = nijk - den;"),
     ("gram: no symmetric copy", "gram[(int64_t)b * n + a] = gram[(int64_t)a * n + b];", ";"),
     ("gram: diagonal dropped", "for (int32_t y = x; y < len[i]; ++y)",
      "for (int32_t y = x + 1; y < len[i]; ++y)"),
