@@ -336,8 +336,10 @@ extern "C" int fc_pairs(fc_db *db, const int32_t *items, int32_t ni, double mins
     }
     // smallest count whose support n/m exceeds minsup, decided in binary64
     const double m = (double)db->m;
-    int64_t nmin = (int64_t)std::floor(minsup * m) - 2;
-    if (nmin < 0) nmin = 0;
+    // no support exceeds 1: minsup >= 1 (however large) admits no pair, and
+    // the product below then stays within int64
+    const double start = std::floor(std::min(minsup, 1.0) * m) - 2.0;
+    int64_t nmin = start > 0.0 ? (int64_t)start : 0;
     while (!((double)nmin / m > minsup) && nmin <= db->m) ++nmin;
     if (db->m == 0) nmin = 1;  // no instance: no pair has support
     hipStream_t s = (hipStream_t)stream;

@@ -203,6 +203,24 @@ class CountServer:
             if not group:
                 break
             flat, off = merge(group)
+            if len(group) > 1:
+                # a merged batch's footprint is not the sum of its requests'
+                # (the plan may take another path for the whole batch): admit
+                # what the merged figure lets fit, return the rest
+                try:
+                    merged = self.backend.footprint(flat, off)
+                except Exception:
+                    merged = nbytes
+                while len(group) > 1 and self.mem_used + merged > self.mem_budget:
+                    r = group.pop()
+                    self.pending.appendleft(r)
+                    nq -= r.nq
+                    flat, off = merge(group)
+                    merged = self.backend.footprint(flat, off)
+                if self.mem_used + merged > self.mem_budget:
+                    self.pending.appendleft(group.pop())
+                    break                       # wait for memory to free up
+                nbytes = merged
             slot = self.free_slots.pop()
             now = self.clock()
             try:
@@ -231,8 +249,17 @@ class CountServer:
         for _ in range(count):
             if not self.pending or not self.free_slots:
                 break
-            r = self.pending.popleft()
-            need = self.backend.footprint(r.flat, r.off)
+            r = self.pending[0]
+            try:
+                need = self.backend.footprint(r.flat, r.off)
+            except Exception as e:
+                self.pending.popleft()
+                r.error, r.done = str(e), self.clock()
+                failed.append(r)
+                continue
+            if self.mem_used + need > self.mem_budget:
+                break                           # wait for memory to free up
+            self.pending.popleft()
             slot = self.free_slots.pop()
             try:
                 handle = self.backend.launch(slot, r.flat, r.off)
@@ -273,14 +300,17 @@ class PerQueryServer:
         torch = self.torch
         r = self.pending.popleft()
         r.admitted = self.clock()
-        dev = torch.empty(len(self.reducers) * r.nq, dtype=torch.float32, device=self.db.device)
+        # one contiguous row of len(reducers) scores per query (a call with
+        # one query writes its reducer slots side by side)
+        dev = torch.empty((r.nq, len(self.reducers)), dtype=torch.float32,
+                          device=self.db.device)
         with torch.cuda.stream(self.stream):
             for i in range(r.nq):
                 self.db.count_reduce([r.flat[r.off[i]:r.off[i + 1]]], self.reducers,
-                                     ess=self.ess, out=dev[i::r.nq], with_err=False,
+                                     ess=self.ess, out=dev[i], with_err=False,
                                      stream=self.stream)
         self.stream.synchronize()
-        r.scores = dev.cpu().numpy().reshape(len(self.reducers), r.nq)
+        r.scores = np.ascontiguousarray(dev.cpu().numpy().T)
         r.done = self.clock()
         return [r]
 

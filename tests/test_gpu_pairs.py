@@ -54,6 +54,18 @@ def test_all_pairs_reduced():
     check(w.D, 0.001)
 
 
+def test_minsup_at_or_above_one_admits_no_pair():
+    rng = synth.rng_for(96)
+    D = (rng.random((6, 5000)) < 0.9).astype(np.uint8)
+    D[:, :100] = 1                               # every item pair occurs
+    with Database(D, np.full(6, 2, np.uint8)) as db:
+        for minsup in (1.0, 7.5, 1e300):
+            recs, _, total = db.pairs(minsup)
+            assert total == 0 and len(recs) == 0
+        recs, _, total = db.pairs(0.0)           # every co-occurring pair
+        assert total == 15
+
+
 def test_rejects_non_binary():
     D = np.zeros((2, 10), np.uint8)
     with Database(D, np.array([2, 3], np.uint8)) as db:

@@ -7,8 +7,8 @@ import torch
 from oracle import oracle as orc
 from paper_1804_04640_amd import synth
 from paper_1804_04640_amd.api import Database
-from paper_1804_04640_amd.serving import (CountServer, GpuBackend, Request, poisson_arrivals,
-                                          run_load)
+from paper_1804_04640_amd.serving import (CountServer, GpuBackend, PerQueryServer, Request,
+                                          poisson_arrivals, run_load)
 
 pytestmark = pytest.mark.gpu
 
@@ -56,9 +56,29 @@ def test_mix_equals_alone_bit_for_bit(served):
         assert abs(float(done[0].scores[0, i]) - ref) <= 1e-6 * abs(ref)
 
 
+class _MeasuredBackend(GpuBackend):
+    """Records the library's own device footprint of every batch it launches
+    (the merged batch as launched, not the sum of its requests) and the
+    largest total in flight."""
+
+    def __init__(self, *a, **kw):
+        super().__init__(*a, **kw)
+        self.live, self.peak = {}, 0
+
+    def launch(self, slot, flat, off):
+        h = super().launch(slot, flat, off)
+        self.live[id(h)] = self.footprint(flat, off)
+        self.peak = max(self.peak, sum(self.live.values()))
+        return h
+
+    def result(self, handle, nq):
+        self.live.pop(id(handle))
+        return super().result(handle, nq)
+
+
 def test_memory_limited_admission(served):
     w, db = served
-    be = GpuBackend(db, ("mdl",), slots=4)
+    be = _MeasuredBackend(db, ("mdl",), slots=4)
     reqs = requests(w)
     biggest = max(be.footprint(r.flat, r.off) for r in reqs)
     srv = CountServer(be, mem_budget=int(biggest * 1.2))
@@ -70,6 +90,23 @@ def test_memory_limited_admission(served):
         peak = max(peak, srv.mem_used)
     assert len(done) == len(reqs) and all(r.error is None for r in done)
     assert peak <= srv.mem_budget
+    assert be.peak <= srv.mem_budget
+
+
+def test_per_query_server_with_two_reducers(served):
+    """The plain per-query path gives every reducer of every query the
+    batched path's score."""
+    w, db = served
+    r = max(requests(w), key=lambda x: x.nq)
+    n = min(40, r.nq)
+    r = Request(0, r.flat[:r.off[n]].copy(), r.off[:n + 1].copy(), arrival=0.0)
+    srv = PerQueryServer(db, ("mdl", "bdeu"))
+    srv.submit(r)
+    got = srv.poll()[0].scores
+    alone, _, _, _ = db.count_reduce((r.flat, r.off), ("mdl", "bdeu"), with_err=False)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(got[0], alone["mdl"].cpu().numpy())
+    np.testing.assert_array_equal(got[1], alone["bdeu"].cpu().numpy())
 
 
 def test_bad_request_fails_alone(served):

@@ -116,3 +116,45 @@ def test_run_load_with_poisson_arrivals():
     st = run_load(srv, batches, arr)
     assert st["requests"] == 50 and st["failed"] == 0
     assert st["p99_ms"] >= st["p50_ms"] >= 0.0
+
+
+class MergedCostBackend(FakeBackend):
+    """A batch of several requests costs more than its parts (as when the
+    planner picks another path for a merged batch); records, for every
+    launch, the footprint of exactly the batch launched."""
+
+    def __init__(self, **kw):
+        super().__init__(**kw)
+        self.live_bytes = {}
+        self.peak = 0
+
+    def footprint(self, flat, off):
+        nq = len(off) - 1
+        return super().footprint(flat, off) + (150 if nq > 1 else 0)
+
+    def launch(self, slot, flat, off):
+        h = super().launch(slot, flat, off)
+        self.live_bytes[h] = self.footprint(flat, off)
+        self.peak = max(self.peak, sum(self.live_bytes.values()))
+        return h
+
+    def result(self, h, nq):
+        self.live_bytes.pop(h)
+        return super().result(h, nq)
+
+
+def test_merged_footprint_is_admitted_not_the_sum_of_requests():
+    be = MergedCostBackend(slots=4, delay=3, bytes_per_query=100)
+    srv = CountServer(be, mem_budget=400)
+    qs = {i: [[i]] for i in range(10)}
+    for i in range(10):
+        srv.submit(req(i, qs[i]))
+    done = []
+    while not srv.idle():
+        done.extend(srv.poll())
+        assert srv.mem_used <= 400
+    # the device figure of what was really in flight never passed the budget
+    assert be.peak <= 400
+    assert len(done) == 10 and all(r.error is None for r in done)
+    for r in done:
+        np.testing.assert_array_equal(r.scores[0], expected(qs[r.rid]))
