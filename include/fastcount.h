@@ -265,6 +265,7 @@ int fc_count_reduce(fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
                     float *scores, float *err, int32_t *tables,
                     const int64_t *table_off, uint32_t flags, void *stream);
 
+
 /*
  * Exact parent-set search support (Section 4.2): the scores of every parent
  * set of `size` variables drawn from cand[0..ncand-1] (distinct, not the
@@ -402,7 +403,29 @@ typedef struct fc_tuning {
     int32_t packed_columns;    /* 1: histogram kernels read the 4-bit packed
                                   columns when the database has them, 0: the
                                   byte columns                            */
+    int32_t bitmap_order;      /* 1: the Bitmap tree walks a query's
+                                  variables by ascending marginal entropy
+                                  (Section 3.2; ties by lower variable
+                                  index), 0: in the query's order.  Either
+                                  order gives the same table.              */
+    int32_t derive_tables;     /* 1: an automatic plan sums the table of a
+                                  query of 3 or 4 variables out of the table
+                                  of another query of the batch whose
+                                  variables contain its own (or of an equal
+                                  query), instead of counting it from the
+                                  instances; 0: every query is counted.
+                                  The tables are the same.                 */
 } fc_tuning;
+
+/*
+ * How a batch would be answered, planned but not launched (flags as in
+ * fc_count_batch): out[0] queries counted by LDS-histogram kernels (whole
+ * or in key windows), out[1] by Bitmap tree walks (Alg. 1), out[2] from the
+ * Gram of the state bit-vectors, out[3] summed out of another query's
+ * table (derive_tables).  out[0..3] add up to nq.  Errors as fc_count_batch.
+ */
+int fc_plan_summary(const fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
+                    int64_t nq, uint32_t flags, int64_t *out);
 
 int fc_db_get_tuning(const fc_db *db, fc_tuning *t);
 

@@ -34,7 +34,7 @@ FC_RED_MI = 8
 EXPORTS = ("fc_db_create", "fc_db_append", "fc_db_destroy", "fc_db_trim", "fc_db_info", "fc_db_marginals", "fc_table_cells",
            "fc_count", "fc_count_assignment", "fc_count_assignments", "fc_count_sparse", "fc_count_sparse_batch", "fc_count_batch", "fc_count_reduce",
            "fc_score_parent_sets", "fc_pairs", "fc_mine", "fc_arm_sizes", "fc_arm_read", "fc_arm_free",
-           "fc_batch_footprint", "fc_graph_create", "fc_graph_launch", "fc_graph_destroy",
+           "fc_batch_footprint", "fc_plan_summary", "fc_graph_create", "fc_graph_launch", "fc_graph_destroy",
            "fc_db_get_tuning", "fc_db_set_tuning", "fc_autotune",
            "fc_profile_enable", "fc_profile_read", "fc_last_error")
 
@@ -53,14 +53,17 @@ class fc_tuning(ctypes.Structure):
     _fields_ = [("chunk_rows", ctypes.c_int64), ("bitmap_chunk_rows", ctypes.c_int64),
                 ("bitmap_words", ctypes.c_int32), ("persistent_max_queries", ctypes.c_int32),
                 ("bitmap_cells", (ctypes.c_uint8 * 6) * FC_MAX_VARS),
-                ("packed_columns", ctypes.c_int32)]
+                ("packed_columns", ctypes.c_int32), ("bitmap_order", ctypes.c_int32),
+                ("derive_tables", ctypes.c_int32)]
 
     def to_dict(self):
         return {"chunk_rows": int(self.chunk_rows), "bitmap_chunk_rows": int(self.bitmap_chunk_rows),
                 "bitmap_words": int(self.bitmap_words),
                 "persistent_max_queries": int(self.persistent_max_queries),
                 "bitmap_cells": [[int(x) for x in row] for row in self.bitmap_cells],
-                "packed_columns": int(self.packed_columns)}
+                "packed_columns": int(self.packed_columns),
+                "bitmap_order": int(self.bitmap_order),
+                "derive_tables": int(self.derive_tables)}
 
     @classmethod
     def from_dict(cls, d):
@@ -73,6 +76,8 @@ class fc_tuning(ctypes.Structure):
             for b, x in enumerate(row):
                 t.bitmap_cells[k][b] = int(x)
         t.packed_columns = int(d.get("packed_columns", 1))
+        t.bitmap_order = int(d.get("bitmap_order", 1))
+        t.derive_tables = int(d.get("derive_tables", 1))
         return t
 
 
@@ -126,6 +131,7 @@ def load():
             "fc_arm_read": (ctypes.c_int, [P, P, P, P, P, P, P, P, P]),
             "fc_arm_free": (None, [P]),
             "fc_batch_footprint": (ctypes.c_int, [P, P, P, i64, u32, P]),
+            "fc_plan_summary": (ctypes.c_int, [P, P, P, i64, u32, P]),
             "fc_graph_create": (ctypes.c_int, [P, P, P, i64, u32, P, P, P, P, P, u32, P, P]),
             "fc_graph_launch": (ctypes.c_int, [P, P]),
             "fc_graph_destroy": (None, [P]),
@@ -271,6 +277,13 @@ def fc_batch_footprint(db, vars_flat, var_off, nq, flags):
     b = ctypes.c_int64()
     check(load().fc_batch_footprint(db, vars_flat, var_off, nq, flags, ctypes.byref(b)))
     return b.value
+
+
+def fc_plan_summary(db, vars_flat, var_off, nq, flags):
+    out = (ctypes.c_int64 * 4)()
+    check(load().fc_plan_summary(db, vars_flat, var_off, nq, flags, out))
+    return {"hist": int(out[0]), "bitmap": int(out[1]), "gram": int(out[2]),
+            "derived": int(out[3])}
 
 
 def fc_graph_create(db, vars_flat, var_off, nq, reducers, params, scores, err, tables, table_off,

@@ -323,6 +323,13 @@ class Database:
         return an object whose replay() reruns all of its device work."""
         return BatchGraph(self, queries, reducers, ess, keep_tables, strategy, stream)
 
+    def plan_summary(self, queries, strategy: str = "auto") -> dict:
+        """How many queries of the batch each path answers (planned, not run):
+        {"hist", "bitmap", "gram", "derived"}."""
+        flat, off = flatten_queries(queries)
+        return L.fc_plan_summary(self.handle, _np_ptr(flat), _np_ptr(off), len(off) - 1,
+                                 STRATEGIES[strategy])
+
     def footprint(self, queries, strategy: str = "auto") -> int:
         flat, off = flatten_queries(queries)
         return L.fc_batch_footprint(self.handle, _np_ptr(flat), _np_ptr(off), len(off) - 1,

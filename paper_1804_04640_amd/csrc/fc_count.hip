@@ -25,7 +25,9 @@
 #include <atomic>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <thread>
+#include <vector>
 
 #include "fc_internal.h"
 
@@ -535,13 +537,16 @@ __global__ __launch_bounds__(kBlock) void k_hist16n(const uint8_t *__restrict__ 
 // once per word group into registers and reused under every prefix.
 constexpr int kLeafMax = 8;
 
+// Level L of the tree walks the variable at query position perm[L]; str[L]
+// is that variable's cell stride in the table (the product of the arities
+// after it in the query), so a leaf's cell is the same whatever the order.
 template <int L, int K, int W>
 struct Walk {
     __device__ __forceinline__ static void go(const uint64_t (&pre)[W], uint32_t cell,
                                               const uint64_t *__restrict__ bits, int64_t wpitch,
                                               int64_t w, const int32_t (&base)[K],
-                                              const int32_t (&rad)[K], bool cached,
-                                              const uint64_t (&leaf)[kLeafMax][W],
+                                              const int32_t (&rad)[K], const uint32_t (&str)[K],
+                                              bool cached, const uint64_t (&leaf)[kLeafMax][W],
                                               uint32_t *acc) {
         if constexpr (L == K - 1) {
             if (cached) {
@@ -551,7 +556,7 @@ struct Walk {
                         uint32_t pc = 0;
 #pragma unroll
                         for (int i = 0; i < W; ++i) pc += (uint32_t)__popcll(leaf[s][i] & pre[i]);
-                        acc[(cell * (uint32_t)rad[L] + (uint32_t)s) * kBlock] += pc;
+                        acc[(cell + (uint32_t)s * str[L]) * kBlock] += pc;
                     }
                 }
                 return;
@@ -562,7 +567,7 @@ struct Walk {
             uint64_t x[W];
 #pragma unroll
             for (int i = 0; i < W; ++i) x[i] = row[i] & pre[i];
-            const uint32_t c2 = cell * (uint32_t)rad[L] + (uint32_t)s;
+            const uint32_t c2 = cell + (uint32_t)s * str[L];
             if constexpr (L == K - 1) {
                 uint32_t pc = 0;
 #pragma unroll
@@ -573,7 +578,8 @@ struct Walk {
 #pragma unroll
                 for (int i = 0; i < W; ++i) any |= x[i];
                 if (__any(any != 0))
-                    Walk<L + 1, K, W>::go(x, c2, bits, wpitch, w, base, rad, cached, leaf, acc);
+                    Walk<L + 1, K, W>::go(x, c2, bits, wpitch, w, base, rad, str, cached, leaf,
+                                          acc);
             }
         }
     }
@@ -587,11 +593,22 @@ __device__ __forceinline__ void bitmap_body(const uint64_t *__restrict__ bits, i
                                             int32_t *__restrict__ tables,
                                             uint32_t *acc /* [cells][kBlock] */) {
     const int32_t cells = q.cells;
-    int32_t base[K], rad[K];
+    // walk order: level L takes query position (win_base >> 3L) & 7
+    int32_t ar[K];
+    uint32_t st[K];
 #pragma unroll
-    for (int t = 0; t < K; ++t) {
-        base[t] = soff[q.var[t]];
-        rad[t] = arity[q.var[t]];
+    for (int t = 0; t < K; ++t) ar[t] = arity[q.var[t]];
+    st[K - 1] = 1;
+#pragma unroll
+    for (int t = K - 2; t >= 0; --t) st[t] = st[t + 1] * (uint32_t)ar[t + 1];
+    int32_t base[K], rad[K];
+    uint32_t str[K];
+#pragma unroll
+    for (int L = 0; L < K; ++L) {
+        const int t = ((uint32_t)q.win_base >> (3 * L)) & 7u;
+        base[L] = soff[q.var[t]];
+        rad[L] = ar[t];
+        str[L] = st[t];
     }
     for (int32_t i = threadIdx.x; i < cells * kBlock; i += kBlock) acc[i] = 0;
     __syncthreads();
@@ -618,7 +635,8 @@ __device__ __forceinline__ void bitmap_body(const uint64_t *__restrict__ bits, i
                 }
             }
         }
-        Walk<0, K, W>::go(ones, 0u, bits, wpitch, w, base, rad, cached, leaf, acc + threadIdx.x);
+        Walk<0, K, W>::go(ones, 0u, bits, wpitch, w, base, rad, str, cached, leaf,
+                          acc + threadIdx.x);
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -882,6 +900,49 @@ __global__ __launch_bounds__(kBlock) void k_assign_batch_cols(
 // ------------------------------------------------------------------ planner
 enum Strat { S_HIST = 1, S_BITMAP = 2, S_PART = 3 };
 
+// A derived table: the table at dst_off (dst_cells cells) is the sum of the
+// counted table at src_off over the axes the derived query lacks.  Axis a
+// of the source (query order, last axis fastest) has src_rad[a] states and
+// stride dst_str[a] in the derived table (0: summed out).
+struct alignas(16) MDesc {
+    int64_t dst_off, src_off;
+    int32_t src_cells, dst_cells, src_k, pad;
+    int32_t src_rad[FC_MAX_VARS];
+    int32_t dst_str[FC_MAX_VARS];
+};
+static_assert(sizeof(MDesc) == 96, "MDesc layout");
+
+// One workgroup per derived table: every non-zero source cell is decoded
+// into its digits and added to the derived cell in LDS; the whole derived
+// table is then stored (no zeroing of the output needed).
+__global__ __launch_bounds__(kBlock) void k_marginal(const MDesc *__restrict__ md, int64_t nm,
+                                                     int32_t *__restrict__ tables) {
+    extern __shared__ uint32_t acc[];
+    for (int64_t g = blockIdx.x; g < nm; g += gridDim.x) {
+        const MDesc &d = md[g];
+        const int32_t dc = d.dst_cells, sc = d.src_cells, k = d.src_k;
+        for (int32_t j = threadIdx.x; j < dc; j += kBlock) acc[j] = 0;
+        __syncthreads();
+        const int32_t *src = tables + d.src_off;
+        for (int32_t i = threadIdx.x; i < sc; i += kBlock) {
+            const int32_t v = src[i];
+            if (v == 0) continue;
+            uint32_t rem = (uint32_t)i, idx = 0;
+            for (int a = k - 1; a >= 0; --a) {
+                const uint32_t r = (uint32_t)d.src_rad[a];
+                const uint32_t q = rem / r;
+                idx += (rem - q * r) * (uint32_t)d.dst_str[a];
+                rem = q;
+            }
+            atomicAdd(&acc[idx], (uint32_t)v);
+        }
+        __syncthreads();
+        int32_t *dst = tables + d.dst_off;
+        for (int32_t j = threadIdx.x; j < dc; j += kBlock) dst[j] = (int32_t)acc[j];
+        __syncthreads();
+    }
+}
+
 struct Launch {
     char name[32];    // kernel instance (profiling)
     double alg_bytes; // k bytes per query and instance, summed
@@ -914,6 +975,9 @@ struct Plan {
     // every counting launch stores whole tables (or key windows) from one
     // workgroup each: the tables need no zeroing first
     bool direct = false;
+    // tables summed out of a counted superset's table after counting
+    std::vector<MDesc> marg;
+    int32_t marg_max_cells = 0;
 };
 
 // LDS size classes; every class but the last keeps its byte addresses below
@@ -1105,6 +1169,236 @@ inline int64_t check_one(const fc_db *db, const int32_t *vars_flat, const int64_
     return c;
 }
 
+// ------------------------------------------------------- derived tables
+// A table is exactly the marginal of the table of any query whose variable
+// set contains its own (the count over a set of variables is the sum of the
+// counts of its extensions; Section 2).  In an automatic plan, a query of
+// three or four variables whose set lies inside another query of the batch
+// (or repeats one) is not counted from the instances: its table is summed
+// out of a counted superset's table after the counting launches.  Sources
+// are always counted queries: `src[i]` of a derived query resolves through
+// subset links and repeats to a query that no other query of the batch
+// contains (or one too costly to derive).
+constexpr int64_t kMargMaxCells = 16384;  // derived tables accumulate in 64 KiB of LDS
+
+namespace {
+inline uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// One partition of an open-addressing map from a variable-set key (never
+// 0) to a query index, keeping the entry that `better` prefers.
+struct SetMap {
+    std::vector<uint64_t> keys;
+    std::vector<int32_t> vals;
+    uint64_t mask = 0;
+    void init(size_t entries) {
+        size_t cap = 16;
+        while (cap < 2 * entries) cap <<= 1;
+        keys.assign(cap, 0);
+        vals.assign(cap, -1);
+        mask = cap - 1;
+    }
+    template <typename Better>
+    void put(uint64_t key, uint64_t h, int32_t v, Better better) {
+        for (uint64_t i = h & mask;; i = (i + 1) & mask) {
+            if (keys[i] == 0) {
+                keys[i] = key;
+                vals[i] = v;
+                return;
+            }
+            if (keys[i] == key) {
+                if (better(v, vals[i])) vals[i] = v;
+                return;
+            }
+        }
+    }
+    int32_t get(uint64_t key, uint64_t h) const {
+        if (keys.empty()) return -1;
+        for (uint64_t i = h & mask;; i = (i + 1) & mask) {
+            if (keys[i] == key) return vals[i];
+            if (keys[i] == 0) return -1;
+        }
+    }
+};
+}  // namespace
+
+// Fills src[i] (-1: counted from the instances) and returns the number of
+// derived queries.  Needs at most 255 variables (a key packs the sorted
+// variables + 1 as bytes); any malformed query disables derivation, and
+// validation reports it.
+static int64_t derive_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
+                           int64_t nq, std::vector<int32_t> &src) {
+    src.clear();
+    if (nq < 2 || db->n > 255 || db->m <= 0) return 0;
+    unsigned hw = std::thread::hardware_concurrency();
+    const int T = (int)std::min<int64_t>(std::max<unsigned>(1u, std::min(16u, hw ? hw : 1u)),
+                                         std::max<int64_t>(1, nq / 16384));
+    std::vector<uint64_t> key((size_t)nq, 0);
+    std::vector<int64_t> cells((size_t)nq, 0);
+    std::vector<uint8_t> kk((size_t)nq, 0);
+    // per (range, owner partition): (subset key, superset) and (own key, query)
+    std::vector<std::vector<std::pair<uint64_t, int32_t>>> sub((size_t)T * T), own((size_t)T * T);
+    std::atomic<bool> bad(false);
+    std::atomic<int64_t> enumerated(0);
+    auto run = [&](auto f) {
+        std::vector<std::thread> th;
+        for (int t = 1; t < T; ++t) th.emplace_back(f, t);
+        f(0);
+        for (auto &x : th) x.join();
+    };
+    // keys, cells, and every 3- and 4-variable subset of larger queries
+    run([&](int t) {
+        const int64_t lo = nq * t / T, hi = nq * (t + 1) / T;
+        int64_t cnt = 0;
+        for (int64_t i = lo; i < hi; ++i) {
+            const int64_t k = var_off[i + 1] - var_off[i];
+            if (k < 1 || k > FC_MAX_VARS) {
+                bad = true;
+                return;
+            }
+            uint8_t v[FC_MAX_VARS];
+            int64_t c = 1;
+            for (int64_t a = 0; a < k; ++a) {
+                const int32_t x = vars_flat[var_off[i] + a];
+                if (x < 0 || x >= db->n) {
+                    bad = true;
+                    return;
+                }
+                v[a] = (uint8_t)(x + 1);
+                c *= db->arity[x];
+                if (c > INT32_MAX) c = INT32_MAX;
+            }
+            std::sort(v, v + k);
+            uint64_t kv = 0;
+            for (int64_t a = 0; a < k; ++a) kv = (kv << 8) | v[a];
+            key[(size_t)i] = kv;
+            cells[(size_t)i] = c;
+            kk[(size_t)i] = (uint8_t)k;
+            if (k < 3) continue;
+            own[(size_t)t * T + (size_t)(mix64(kv) % (uint64_t)T)].push_back({kv, (int32_t)i});
+            if (k < 4) continue;
+            // sorted subsets of 3 and 4 of the sorted variables
+            for (int a = 0; a < k; ++a)
+                for (int b = a + 1; b < k; ++b)
+                    for (int d = b + 1; d < k; ++d) {
+                        const uint64_t s3 = ((uint64_t)v[a] << 16) | ((uint64_t)v[b] << 8) | v[d];
+                        sub[(size_t)t * T + (size_t)(mix64(s3) % (uint64_t)T)].push_back(
+                            {s3, (int32_t)i});
+                        ++cnt;
+                        if (k < 5) continue;
+                        for (int e = d + 1; e < k; ++e) {
+                            const uint64_t s4 = (s3 << 8) | v[e];
+                            sub[(size_t)t * T + (size_t)(mix64(s4) % (uint64_t)T)].push_back(
+                                {s4, (int32_t)i});
+                            ++cnt;
+                        }
+                    }
+        }
+        enumerated += cnt;
+    });
+    if (bad) return 0;
+    // the partitions: own keys keep the lowest query index, subset keys the
+    // superset with the fewest cells
+    std::vector<SetMap> m0((size_t)T), m1((size_t)T);
+    run([&](int o) {
+        size_t n0 = 0, n1 = 0;
+        for (int t = 0; t < T; ++t) {
+            n0 += own[(size_t)t * T + o].size();
+            n1 += sub[(size_t)t * T + o].size();
+        }
+        m0[(size_t)o].init(n0);
+        m1[(size_t)o].init(n1);
+        for (int t = 0; t < T; ++t) {
+            for (auto &e : own[(size_t)t * T + o])
+                m0[(size_t)o].put(e.first, mix64(e.first) >> 8, e.second,
+                                  [](int32_t a, int32_t b) { return a < b; });
+            for (auto &e : sub[(size_t)t * T + o])
+                m1[(size_t)o].put(e.first, mix64(e.first) >> 8, e.second, [&](int32_t a, int32_t b) {
+                    return cells[(size_t)a] != cells[(size_t)b] ? cells[(size_t)a] < cells[(size_t)b]
+                                                                : a < b;
+                });
+        }
+    });
+    auto find = [&](const std::vector<SetMap> &m, uint64_t kv) {
+        const uint64_t h = mix64(kv);
+        return m[(size_t)(h % (uint64_t)T)].get(kv, h >> 8);
+    };
+    src.assign((size_t)nq, -1);
+    // The chain of query i: its representative (lowest index with the same
+    // variable set), then the representatives of successive smallest
+    // supersets while the set has 3 or 4 variables.  The top of a chain is
+    // counted; a member below it is derived when a counted member above can
+    // serve it (at most kMargMaxCells cells to accumulate, and the source's
+    // cells cheap against the instances), else counted.  Every query of a
+    // chain computes the same decisions, so sources are always counted.
+    const int64_t m = db->m;
+    auto serves = [&](int32_t from, int32_t to) {
+        return cells[(size_t)to] <= kMargMaxCells && cells[(size_t)from] * 32 <= m * kk[(size_t)to];
+    };
+    run([&](int t) {
+        const int64_t lo = nq * t / T, hi = nq * (t + 1) / T;
+        for (int64_t i = lo; i < hi; ++i) {
+            if (kk[(size_t)i] < 3 || cells[(size_t)i] > kMargMaxCells) continue;
+            int32_t ch[FC_MAX_VARS + 1];
+            int L = 0;
+            const int32_t r0 = find(m0, key[(size_t)i]);
+            ch[L++] = r0 >= 0 ? r0 : (int32_t)i;
+            while (L < FC_MAX_VARS + 1) {
+                const int32_t r = ch[L - 1];
+                const int kr = kk[(size_t)r];
+                const int32_t up = (kr == 3 || kr == 4) ? find(m1, key[(size_t)r]) : -1;
+                if (up < 0) break;
+                const int32_t ru = find(m0, key[(size_t)up]);
+                ch[L++] = ru >= 0 ? ru : up;
+            }
+            bool counted[FC_MAX_VARS + 1];
+            counted[L - 1] = true;
+            for (int j = L - 2; j >= 0; --j) {
+                counted[j] = true;
+                for (int l = j + 1; l < L && counted[j]; ++l)
+                    if (counted[l] && serves(ch[l], ch[j])) counted[j] = false;
+            }
+            // the lowest counted member (other than i) that serves i
+            for (int l = 0; l < L; ++l)
+                if (ch[l] != (int32_t)i && counted[l] && serves(ch[l], (int32_t)i)) {
+                    src[(size_t)i] = ch[l];
+                    break;
+                }
+        }
+    });
+    // a source must itself be counted: one that is derived by the rule above
+    // (only possible through the cost bound) makes its dependants counted
+    int64_t n = 0;
+    for (int64_t i = 0; i < nq; ++i) {
+        const int32_t r = src[(size_t)i];
+        if (r >= 0 && src[(size_t)r] >= 0) src[(size_t)i] = -1;
+        if (src[(size_t)i] >= 0) ++n;
+    }
+    (void)enumerated;
+    return n;
+}
+
+// Order in which a Bitmap tree walks the variables of descriptor d, three
+// bits per level (level L walks query position (code >> 3L) & 7): ascending
+// marginal entropy, ties by lower variable index (Section 3.2: a
+// low-entropy variable first leaves fewer non-empty prefixes to extend), or
+// the query's own order when the tuning says so.
+static uint32_t walk_order(const fc_db *db, const QDesc &d) {
+    int32_t perm[FC_MAX_VARS];
+    for (int32_t t = 0; t < d.k; ++t) perm[t] = t;
+    if (db->tune.bitmap_order)
+        std::stable_sort(perm, perm + d.k, [&](int32_t a, int32_t b) {
+            const float ea = db->entropy[(size_t)d.var[a]], eb = db->entropy[(size_t)d.var[b]];
+            return ea != eb ? ea < eb : d.var[a] < d.var[b];
+        });
+    uint32_t code = 0;
+    for (int32_t L = 0; L < d.k; ++L) code |= (uint32_t)perm[L] << (3 * L);
+    return code;
+}
+
 template <typename F>
 void parallel_ranges(std::vector<RangeStat> &R, F f) {
     if (R.size() == 1) {
@@ -1162,6 +1456,10 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
         R[(size_t)t].maxc.assign(kBuckets, 0);
         if (gram_allowed) R[(size_t)t].used.assign((size_t)db->n, 0);
     }
+    // tables derivable from a counted superset's table (automatic plans)
+    std::vector<int32_t> dsrc;
+    const bool derive = forced == FC_STRAT_AUTO && db->tune.derive &&
+                        derive_plan(db, vars_flat, var_off, nq, dsrc) > 0;
     // pass 1: validate, count descriptors per bucket
     parallel_ranges(R, [&](RangeStat &r) {
         for (int64_t i = r.lo; i < r.hi; ++i) {
@@ -1184,6 +1482,7 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
             const int st = choose(db, forced, k, c, win);
             const bool small = c < (int64_t(1) << 24);
             r.cells_sum += c;
+            if (derive && dsrc[(size_t)i] >= 0) continue;  // summed out of another table
             if (k <= 2 && gram_allowed) {
                 ++r.nsmall;
                 for (int64_t t = 0; t < k; ++t) r.used[(size_t)vars_flat[var_off[i] + t]] = 1;
@@ -1266,7 +1565,7 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
             }
         }
     }
-    const bool need_query = !P.packed || (reducers && P.windows);
+    const bool need_query = !P.packed || (reducers && P.windows) || derive;
     P.gram_first = start[kBuckets];
     P.gram_count = 0;
     if (use_gram)
@@ -1301,6 +1600,7 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
             d.win_cells = (int32_t)c;
             d.tiles = (int32_t)(db->m_pad / kTileRows);
             if (need_query) P.query[(size_t)i] = d;
+            if (derive && dsrc[(size_t)i] >= 0) continue;
             if (use_gram && k <= 2) {
                 P.work[(size_t)r.gcur++] = d;
                 continue;
@@ -1315,6 +1615,7 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
                 QDesc w = d;
                 w.win_base = (int32_t)b0;
                 w.win_cells = (int32_t)wc;
+                if (st == S_BITMAP) w.win_base = (int32_t)walk_order(db, d);
                 P.work[(size_t)r.cur[(size_t)b]++] = w;
             }
         }
@@ -1346,8 +1647,8 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
                            : cls < kHist16Classes           ? HK_HIST16
                                                             : HK_GENERIC;
                     L.wide = cls < kHist16nWide;
-                    if (L.hk == HK_HIST8N || L.hk == HK_HIST16N)
-                        bytes *= 0.5;  // half a byte per state
+                    // algorithmic bytes: k per (query, instance) whichever
+                    // column store or strategy the launch reads
                     L.lds_bytes = st == S_BITMAP ? (int32_t)(maxc * kBlock * 4) : kClassLds[cls];
                     L.alg_bytes = bytes;
                     if (st == S_BITMAP)
@@ -1370,6 +1671,33 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
     P.direct = db->m > 0;
     for (const Launch &L : P.launches)
         if (L.strat == S_BITMAP || L.chunks != 1) P.direct = false;
+    if (derive) {
+        for (int64_t i = 0; i < nq; ++i) {
+            const int32_t j = dsrc[(size_t)i];
+            if (j < 0) continue;
+            const QDesc &dq = P.query[(size_t)i], &sq = P.query[(size_t)j];
+            MDesc m;
+            std::memset(&m, 0, sizeof m);
+            m.dst_off = dq.table_off;
+            m.src_off = sq.table_off;
+            m.dst_cells = dq.cells;
+            m.src_cells = sq.cells;
+            m.src_k = sq.k;
+            for (int32_t a = 0; a < sq.k; ++a) {
+                m.src_rad[a] = db->arity[(size_t)sq.var[a]];
+                int32_t stride = 1;
+                for (int32_t t = dq.k - 1; t >= 0; --t) {
+                    if (dq.var[t] == sq.var[a]) {
+                        m.dst_str[a] = stride;
+                        break;
+                    }
+                    stride *= db->arity[(size_t)dq.var[t]];
+                }
+            }
+            P.marg.push_back(m);
+            P.marg_max_cells = std::max(P.marg_max_cells, dq.cells);
+        }
+    }
     return FC_OK;
 }
 
@@ -1532,7 +1860,7 @@ struct Image {
     double pbytes = 0.0;
     bool with_query = false;
     size_t off_query = 0, off_groups = 0, off_heads = 0, bytes = 0;
-    size_t off_gram_rows = 0, off_gram_pos = 0, off_gram_c = 0;
+    size_t off_gram_rows = 0, off_gram_pos = 0, off_gram_c = 0, off_marg = 0;
     size_t dev_bytes = 0;  // bytes plus the device-only state Gram
 };
 
@@ -1571,6 +1899,9 @@ static void make_image(const fc_db *db, const Plan &P, uint32_t reducers, Image 
     b += sizeof(int32_t) * P.gram_rows.size();
     I.off_gram_pos = b;
     b += sizeof(int32_t) * P.gram_pos.size();
+    b = (b + 15) & ~(size_t)15;
+    I.off_marg = b;
+    b += sizeof(MDesc) * P.marg.size();
     I.bytes = b;
     I.off_gram_c = (b + 255) & ~(size_t)255;
     I.dev_bytes = P.gram_count ? I.off_gram_c + sizeof(int32_t) * (size_t)P.gram_np *
@@ -1605,6 +1936,8 @@ static void fill_image(const Plan &P, const Image &I, void *host) {
         std::memcpy(h + I.off_gram_rows, P.gram_rows.data(), sizeof(int32_t) * P.gram_rows.size());
     if (!P.gram_pos.empty())
         std::memcpy(h + I.off_gram_pos, P.gram_pos.data(), sizeof(int32_t) * P.gram_pos.size());
+    if (!P.marg.empty())
+        std::memcpy(h + I.off_marg, P.marg.data(), sizeof(MDesc) * P.marg.size());
 }
 
 // Every device step of a batch whose image is resident at `dimg`: zero the
@@ -1663,6 +1996,16 @@ static int enqueue_batch(fc_db *db, const Plan &P, const Image &I, void *dimg, i
             ProfScope ps(L->name, s, L->alg_bytes, 0.0);
             FC_HIP(launch_count(db, *L, dw, tables, s));
             ps.end(s);
+        }
+        if (!P.marg.empty()) {
+            const MDesc *md = (const MDesc *)((char *)dimg + I.off_marg);
+            const int64_t nm = (int64_t)P.marg.size();
+            ProfScope ps("k_marginal", s, 0.0, 0.0);
+            hipLaunchKernelGGL(k_marginal, dim3((unsigned)std::min<int64_t>(nm, 65536)),
+                               dim3(kBlock), sizeof(uint32_t) * (size_t)P.marg_max_cells, s, md,
+                               nm, tables);
+            ps.end(s);
+            FC_HIP(hipGetLastError());
         }
     }
     if (reducers && P.nq > 0) {
@@ -1930,6 +2273,32 @@ extern "C" int fc_batch_footprint(const fc_db *db, const int32_t *vars_flat,
 }
 
 // ------------------------------------------------------------------ tuning
+extern "C" int fc_plan_summary(const fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
+                               int64_t nq, uint32_t flags, int64_t *out) {
+    clear_error();
+    if (!out) {
+        set_error("fc_plan_summary: out is NULL");
+        return FC_ERR_INVALID;
+    }
+    Plan P;
+    const int rc = build_plan(db, vars_flat, var_off, nq, nullptr, flags, false, P);
+    if (rc) return rc;
+    std::vector<uint8_t> seen((size_t)nq, 0);
+    int64_t hist = 0, bitmap = 0;
+    for (const Launch &L : P.launches)
+        for (int64_t d = L.first; d < L.first + L.count; ++d) {
+            const int32_t q = P.work[(size_t)d].qid;
+            if (seen[(size_t)q]) continue;  // key windows of one query
+            seen[(size_t)q] = 1;
+            if (L.strat == S_BITMAP) ++bitmap; else ++hist;
+        }
+    out[0] = hist;
+    out[1] = bitmap;
+    out[2] = P.gram_count;
+    out[3] = (int64_t)P.marg.size();
+    return FC_OK;
+}
+
 extern "C" int fc_db_get_tuning(const fc_db *db, fc_tuning *t) {
     clear_error();
     if (!db || !t) {
@@ -1942,6 +2311,8 @@ extern "C" int fc_db_get_tuning(const fc_db *db, fc_tuning *t) {
     t->persistent_max_queries = db->tune.persistent_max_queries;
     std::memcpy(t->bitmap_cells, db->tune.bitmap_cells, sizeof t->bitmap_cells);
     t->packed_columns = db->tune.packed_columns;
+    t->bitmap_order = db->tune.bitmap_order;
+    t->derive_tables = db->tune.derive;
     return FC_OK;
 }
 
@@ -1953,9 +2324,11 @@ extern "C" int fc_db_set_tuning(fc_db *db, const fc_tuning *t) {
     }
     if (t->chunk_rows < kTileRows || t->bitmap_chunk_rows < kTileRows ||
         (t->bitmap_words != 1 && t->bitmap_words != 2 && t->bitmap_words != 4) ||
-        (t->packed_columns != 0 && t->packed_columns != 1)) {
+        (t->packed_columns != 0 && t->packed_columns != 1) ||
+        (t->bitmap_order != 0 && t->bitmap_order != 1) ||
+        (t->derive_tables != 0 && t->derive_tables != 1)) {
         set_error("fc_db_set_tuning: chunk rows must be >= %lld, bitmap_words 1, 2 or 4, "
-                  "packed_columns 0 or 1", (long long)kTileRows);
+                  "packed_columns, bitmap_order and derive_tables 0 or 1", (long long)kTileRows);
         return FC_ERR_INVALID;
     }
     db->tune.chunk_rows = t->chunk_rows;
@@ -1964,6 +2337,8 @@ extern "C" int fc_db_set_tuning(fc_db *db, const fc_tuning *t) {
     db->tune.persistent_max_queries = t->persistent_max_queries < 0 ? 0 : t->persistent_max_queries;
     std::memcpy(db->tune.bitmap_cells, t->bitmap_cells, sizeof t->bitmap_cells);
     db->tune.packed_columns = t->packed_columns;
+    db->tune.bitmap_order = t->bitmap_order;
+    db->tune.derive = t->derive_tables;
     return FC_OK;
 }
 

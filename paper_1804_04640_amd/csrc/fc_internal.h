@@ -29,7 +29,8 @@ struct alignas(16) QDesc {
     int32_t var[FC_MAX_VARS];
     int32_t cells;      // cells of the whole table
     int32_t k;          // variables in the query
-    int32_t win_base;   // first key of the window (0 when not partitioned)
+    int32_t win_base;   // first key of the window (0 when not partitioned); for a
+                        // Bitmap descriptor, its tree-walk order (3 bits per level)
     int32_t win_cells;  // keys in the window
     int32_t qid;        // query index in the caller's batch
     int32_t tiles;      // kTileRows tiles scanned: the padded extent m_pad / kTileRows
@@ -42,6 +43,8 @@ struct Tuning {
     int bitmap_words = 2;               // 64-row words per thread per tree walk
     int persistent_max_queries = 256;   // small batches: one persistent launch
     int packed_columns = 1;             // histograms read the 4-bit columns when present
+    int bitmap_order = 1;               // 1: bitmap trees walk variables by ascending entropy
+    int derive = 1;                     // 1: automatic plans sum tables out of supersets
     // bitmap_cells[k-1][b]: bitmap for k variables and <= 2^(b+2) cells
     uint8_t bitmap_cells[FC_MAX_VARS][6] = {};
     Tuning() {

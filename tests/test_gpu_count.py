@@ -160,6 +160,103 @@ def test_marginals_and_assignment():
                                                                            [0, 0])
 
 
+def test_entropies_match_scipy():
+    """fc_db_marginals' entropies (bits) equal scipy's entropy of the state
+    histogram, and survive an append."""
+    from scipy.stats import entropy
+    w = synth.batched_uneven(m=60_013, nq=4)
+    D = w.D.copy()
+    D[3, :] = 0                                   # a constant variable: entropy 0
+    with Database(D[:, :40_000].copy(), w.arity) as db:
+        _, ent = db.marginals()
+        for v in range(w.n):
+            ref = entropy(np.bincount(D[v, :40_000], minlength=w.arity[v]), base=2)
+            assert abs(float(ent[v]) - ref) <= 1e-5 * max(1.0, ref), v
+        assert ent[3] == 0.0
+        db.append(D[:, 40_000:].copy())
+        _, ent = db.marginals()
+        for v in range(w.n):
+            ref = entropy(np.bincount(D[v], minlength=w.arity[v]), base=2)
+            assert abs(float(ent[v]) - ref) <= 1e-5 * max(1.0, ref), v
+
+
+def test_bitmap_walk_order_does_not_change_tables():
+    """The Bitmap tree walked by ascending entropy and in the query's order
+    gives the oracle's tables (Section 3.2: the order only prunes)."""
+    w = synth.bn_family(m=70_001, nq=600)
+    with Database(w.D, w.arity) as db:
+        for order in (1, 0):
+            t = db.tuning()
+            t["bitmap_order"] = order
+            t["bitmap_cells"] = [[1] * 6 for _ in range(8)]     # tables up to 128 cells
+            db.set_tuning(t)
+            for strategy in ("bitmap", "auto"):
+                tables, toff = db.count_batch((w.vars_flat, w.var_off), strategy=strategy)
+                check_tables(w, tables, toff)
+
+
+def _nested_queries(w, rng, nsup=80):
+    """Supersets of 4..6 variables (some with the largest arities, so their
+    tables need key windows), subsets of 3 and 4 of their variables in
+    shuffled order, repeats, chains (3 in 4 in 5) and unrelated queries."""
+    qs = []
+    big = np.argsort(w.arity)[::-1][:6]
+    for s in range(nsup):
+        k = int(rng.integers(4, 7))
+        sup = big.copy() if s % 16 == 0 else rng.choice(w.n, k, replace=False)
+        qs.append(rng.permutation(sup).astype(np.int32))
+        mid = rng.choice(sup, 4, replace=False) if len(sup) > 4 else sup
+        qs.append(rng.permutation(mid).astype(np.int32))
+        for _ in range(3):
+            qs.append(rng.permutation(rng.choice(mid, 3, replace=False)).astype(np.int32))
+        if s % 3 == 0:
+            qs.append(rng.permutation(sup).astype(np.int32))            # a repeat
+    for _ in range(200):
+        qs.append(rng.choice(w.n, int(rng.integers(1, 7)), replace=False).astype(np.int32))
+    order = rng.permutation(len(qs))
+    return [qs[i] for i in order]
+
+
+def test_derived_tables_equal_counted_ones():
+    """Tables summed out of a superset's table (derive_tables) equal the
+    oracle's and those counted from the instances, in dense and caller-offset
+    layouts, with reducers and in a replayed graph."""
+    w = synth.batched_uneven(m=90_007, nq=2)
+    rng = np.random.default_rng(11)
+    qs = _nested_queries(w, rng)
+    flat, off = synth.flatten(qs)
+    wq = synth.Workload("nested", w.D, w.arity, flat, off)
+    print("derived tables: %d queries" % wq.nq, flush=True)
+    with Database(w.D, w.arity) as db:
+        summ = db.plan_summary(qs)
+        assert summ["derived"] >= 200 and sum(summ.values()) == wq.nq, summ
+        tables, toff = db.count_batch(qs)
+        check_tables(wq, tables, toff)
+        # caller offsets with gaps between the tables
+        gap = np.zeros(wq.nq + 1, np.int64)
+        gap[1:] = np.cumsum(np.diff(toff) + 3)
+        t2, _ = db.count_batch(qs, table_off=gap)
+        T2 = t2.cpu().numpy()
+        for i in range(wq.nq):
+            np.testing.assert_array_equal(T2[gap[i]:gap[i] + toff[i + 1] - toff[i]],
+                                          tables[toff[i]:toff[i + 1]].cpu().numpy())
+        sc_on, _, tab_on, _ = db.count_reduce(qs, ("bdeu", "mi"), keep_tables=True)
+        g = db.graph(qs, ("bdeu", "mi"))
+        for _ in range(3):
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(g.scores[:2 * wq.nq], torch.cat([sc_on["bdeu"], sc_on["mi"]]))
+        g.close()
+        t = db.tuning()
+        t["derive_tables"] = 0
+        db.set_tuning(t)
+        assert db.plan_summary(qs)["derived"] == 0
+        sc_off, _, tab_off, _ = db.count_reduce(qs, ("bdeu", "mi"), keep_tables=True)
+        assert torch.equal(tab_on, tab_off)
+        for r in ("bdeu", "mi"):
+            assert torch.equal(sc_on[r], sc_off[r])
+
+
 @pytest.mark.parametrize("persistent", [0, 100000])
 def test_persistent_and_solo_launches_agree(persistent):
     w = synth.batched_uneven(m=50_001, nq=300)
