@@ -6,9 +6,12 @@ upload, count every query's contingency table (bitmap / histogram /
 partition kernels), stream the tables into the fused reducers, scores left
 on the device.  The database is resident in HBM before timing starts.
 
-Default workload: BN-family scoring -- n=37 variables with arities U{2,3,4},
-m=1,000,000 instances forward-sampled from a random DAG (in-degree <= 4,
-Dirichlet(1) CPTs), 50,000 family queries (child + 0..4 parents), fused MDL.
+Default workload: batched uneven queries -- n=100 variables with arities
+min(8, 2+Geometric(0.4)), m=4,000,000 instances forward-sampled from a random
+DAG (in-degree <= 3, Dirichlet(0.5) CPTs), 200,000 queries of 1..6 variables,
+fused BDeu (ess 1) and mutual information.  Its 400 MB column store is larger
+than the 256 MB MALL.  `--workload bn-family` (m=10^6, 50,000 families, MDL)
+runs from the caches: its bandwidth figures are labelled cache-resident.
 
 The JSON line carries query-rows/s (sum over queries of m per second), the
 batched vs per-query comparison, p50/p99 latencies, the dominant kernel's
@@ -35,6 +38,10 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP4_PEAK_TFLOPS = 10100.0       # MI355X dense fp4 (e2m1) MFMA
 CLOCK_HZ = 2.4e9               # MI355X peak engine clock
 N_CU = 256                     # MI355X compute units
+# VALU issue: a CU's four SIMDs each take a 64-lane instruction every four
+# clocks, so one 64-lane VALU instruction per clock per CU
+VALU_PEAK_TOPS = N_CU * 64 * CLOCK_HZ / 1e12       # 39.32 T lane-operations/s
+CACHE_RESIDENT = {"plain-small", "bn-family"}      # databases well inside the MALL
 
 
 def src_hash(files=None) -> str:
@@ -99,12 +106,33 @@ def percentile(xs, p):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), p)) if len(xs) else None
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def usable_cores() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        return os.cpu_count() or 1
+
+
 def cpu_baseline(w, reducers, budget_s: float, gpu_scores=None, gpu_err=None):
-    """The CPU oracle, as it stands, on a bounded sample of the same queries,
-    one query per thread (query-level parallelism).  With the GPU's scores
-    (float32, [reducer][query]) it also reports their largest relative error
-    against the oracle's binary64 scores over the sample, and whether every
-    error lies within the GPU's own per-result estimate."""
+    """The CPU oracle, as it stands, on bounded samples of the same queries:
+    one leg on a single thread, one with query-level threads (the paper's
+    solver runs concurrent queries on OpenMP threads).  The thread count is
+    the cores this process may use, at most 16 (the host share one GPU
+    comes with).  With the GPU's scores (float32, [reducer][query]) it also
+    reports their largest relative error against the oracle's binary64
+    scores over the threaded sample, and whether every error lies within the
+    GPU's own per-result estimate."""
     from oracle import oracle as orc
 
     def one(i):
@@ -113,13 +141,18 @@ def cpu_baseline(w, reducers, budget_s: float, gpu_scores=None, gpu_err=None):
         r = int(w.arity[q[-1]])
         return [orc.score(name, T, r, w.ess) for name in reducers]
 
+    # single thread: queries in order until half the budget is spent
     t0 = time.perf_counter()
-    probe = 8
-    for i in range(probe):
-        one(i)
-    per_q = (time.perf_counter() - t0) / probe
-    threads = max(1, min(16, os.cpu_count() or 1))
-    sample = int(min(w.nq, max(64, budget_s / max(per_q, 1e-6))))
+    n1 = 0
+    while n1 < w.nq and (n1 < 8 or time.perf_counter() - t0 < 0.5 * budget_s):
+        one(n1)
+        n1 += 1
+    dt1 = time.perf_counter() - t0
+    rate1 = n1 * w.m / dt1
+    # threaded: a sample sized for about the other half of the budget
+    nproc = usable_cores()
+    threads = max(1, min(16, nproc))
+    sample = int(min(w.nq, max(64, 0.5 * budget_s * threads * n1 / dt1)))
     ids = list(range(sample))
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(max_workers=threads) as ex:
@@ -128,7 +161,11 @@ def cpu_baseline(w, reducers, budget_s: float, gpu_scores=None, gpu_err=None):
     out = {"value": sample * w.m / dt, "unit": "query-rows/s", "cores": threads,
            "kind": "oracle",
            "sample": "first %d of %d queries (m=%d), count + %s, %d threads, %.1f s wall"
-                     % (sample, w.nq, w.m, "+".join(reducers), threads, dt)}
+                     % (sample, w.nq, w.m, "+".join(reducers), threads, dt),
+           "single_thread": {"value": rate1, "unit": "query-rows/s",
+                             "sample": "first %d queries, 1 thread, %.1f s" % (n1, dt1)},
+           "thread_speedup": (sample * w.m / dt) / rate1,
+           "nproc": os.cpu_count(), "usable_cores": nproc, "cpu_model": cpu_model()}
     if gpu_scores is not None:
         worst, within = {}, True
         for slot, name in enumerate(reducers):
@@ -522,12 +559,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="bn-family", choices=["plain-small", "bn-family", "batched-uneven", "all-pairs", "serving"])
+    ap.add_argument("--workload", default="batched-uneven", choices=["plain-small", "bn-family", "batched-uneven", "all-pairs", "serving"])
     ap.add_argument("--strategy", default="auto", choices=["auto", "hist", "bitmap", "partition"])
     ap.add_argument("--per-query", type=int, default=2000,
                     help="queries timed on the plain per-query path (0: skip)")
-    ap.add_argument("--cpu-budget", type=float, default=15.0,
-                    help="seconds of single-thread oracle work in the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-budget", type=float, default=20.0,
+                    help="seconds of oracle work in the CPU baseline, half on one thread, half "
+                         "threaded (0: skip)")
     ap.add_argument("--autotune", type=int, default=1,
                     help="run the device autotuner on a sample of the batch before timing")
     ap.add_argument("--tune", default=None,
@@ -615,6 +653,8 @@ def main():
             print("# autotuned on %d queries in %.1fs: %s" % (nq, time.time() - t0,
                                                               json.dumps(tuning)),
                   file=sys.stderr, flush=True)
+
+        plan = db.plan_summary(q, strategy=args.strategy)
 
         def step():
             db.count_reduce(q, reducers, ess=w.ess, strategy=args.strategy, out=scores,
@@ -728,25 +768,28 @@ def main():
     dom_name, dom = max((counting or prof).items(), key=lambda kv: kv[1]["ms"])
     c_ms = sum(v["ms"] for v in counting.values())
     c_bytes = sum(v["alg_bytes"] for v in counting.values())
-    # histogram kernels add one LDS counter per (query, instance): their
-    # algorithmic bytes are K per unit, K/2 for the packed-column kernels
+    # histogram kernels add one LDS counter per (query, instance); their
+    # algorithmic bytes are K per unit
     h_units, h_ms = 0.0, 0.0
     for name, v in counting.items():
         if name.startswith("k_hist"):
             kk = int(name.split("<")[1].split(",")[0].rstrip(">"))
-            per = kk / 2.0 if name.split("<")[0].endswith("n") else float(kk)
-            h_units += v["alg_bytes"] / per
+            h_units += v["alg_bytes"] / kk
             h_ms += v["ms"]
-    achieved = dom["alg_bytes"] / (dom["ms"] * 1e-3) / 1e9 if dom["ms"] > 0 else 0.0
+    launch_s = dom["ms"] * 1e-3 / dom["launches"] if dom["launches"] else 0.0
+    alg_per_launch = dom["alg_bytes"] / dom["launches"] if dom["launches"] else 0.0
+    # algorithmic work of a counting launch: k digit steps per (query,
+    # instance) -- one per query variable, the O(|Pa| m) of Radix -- the same
+    # count as its k algorithmic bytes per query-row
+    achieved = alg_per_launch / launch_s / 1e12 if launch_s > 0 else 0.0
     traffic = counter_traffic(args.workload, dom_name)
     # the issue rate the kernel reaches: its counted VALU wave instructions
-    # per launch over the live launch time, against one wave instruction per
-    # clock per CU (four SIMDs, each issuing a 64-lane instruction over four
-    # clocks) at 2.4 GHz on 256 CUs
-    cf = counter_figures(args.workload, dom_name)
-    launch_s = dom["ms"] * 1e-3 / dom["launches"] if dom["launches"] else 0.0
-    valu_frac = (cf["valu_inst_per_launch"] / (launch_s * CLOCK_HZ * N_CU)
-                 if cf and launch_s > 0 else None)
+    # per launch over the live launch time, against one 64-lane instruction
+    # per clock per CU at 2.4 GHz on 256 CUs
+    cfig = counter_figures(args.workload, dom_name)
+    valu_frac = (cfig["valu_inst_per_launch"] / (launch_s * CLOCK_HZ * N_CU)
+                 if cfig and launch_s > 0 else None)
+    cache_resident = args.workload in CACHE_RESIDENT
     out = {
         "metric": "exact query-rows counted/s + HBM GB/s frac; batched vs per-query; p50/p99 ms",
         "value": value,
@@ -762,10 +805,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "desc": w.desc, "queries": nq, "m": w.m, "n": w.n,
                    "reducers": list(reducers), "strategy": args.strategy, "tuning": tuning,
+                   "column_store_bytes": int(w.n) * int(w.m), "cache_resident": cache_resident,
                    "parallelism": "single GPU"},
         "batched": {"p50_ms": percentile(step_ms, 50), "p99_ms": percentile(step_ms, 99),
+                    "plan": plan,
                     "effective_GBps": alg_bytes / (ms * 1e-3) / 1e9,
-                    "effective_hbm_frac": alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "effective_over_hbm_peak": alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                     "counting_kernels_GBps": c_bytes / (c_ms * 1e-3) / 1e9 if c_ms else None,
                     "histogram_lds_adds_per_s": h_units / (h_ms * 1e-3) if h_ms else None,
                     "kernels": {k: {"launches": v["launches"], "avg_us": 1e3 * v["ms"] / v["launches"],
@@ -778,13 +823,25 @@ def main():
         "forced_strategies": strategies,
         "per_query": per_query,
         "batched_vs_per_query": (value / per_query["value"]) if per_query else None,
-        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "avg_launch_us": 1e3 * dom["ms"] / dom["launches"],
-                     "alg_bytes_per_launch": dom["alg_bytes"] / dom["launches"],
+        "roofline": {"bound": "alu", "kernel": dom_name, "achieved": achieved,
+                     "peak": VALU_PEAK_TOPS, "unit": "Tops/s", "frac": achieved / VALU_PEAK_TOPS,
                      "traffic": traffic,
+                     "work": "k digit steps per (query, instance) = k algorithmic bytes "
+                             "per query-row; peak = one 64-lane VALU instruction per clock "
+                             "per CU x 256 CUs x 2.4 GHz",
+                     "avg_launch_us": 1e6 * launch_s,
+                     "alg_ops_per_launch": alg_per_launch,
                      "valu_issue_frac": valu_frac,
-                     "lds_inst_per_launch": cf["lds_inst_per_launch"] if cf else None},
+                     "valu_lane_ops_per_alg_op": (64 * cfig["valu_inst_per_launch"] / alg_per_launch
+                                                  if cfig and alg_per_launch else None),
+                     "lds_inst_per_launch": cfig["lds_inst_per_launch"] if cfig else None,
+                     "alg_GBps": achieved * 1e3,
+                     "alg_GBps_over_hbm_peak": achieved * 1e3 / HBM_PEAK_GBS,
+                     "cache_resident": cache_resident,
+                     "traffic_note": "FETCH_SIZE + WRITE_SIZE bytes per launch (copy-calibrated): "
+                                     "L2-miss traffic served by the MALL or HBM; no counter of "
+                                     "this platform separates the two, so HBM bytes are at most "
+                                     "this"},
         "cpu_baseline": None,
     }
     if args.cpu_budget > 0:
