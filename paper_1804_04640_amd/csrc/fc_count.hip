@@ -679,18 +679,21 @@ struct PGroup {
     int32_t chunks;
     int32_t kind;     // PK_* << 4 | K
 };
-enum { PK_HIST16 = 1, PK_HIST_S = 2, PK_HIST_B = 3, PK_BITMAP = 4, PK_HIST8 = 5 };
+enum { PK_HIST16 = 1, PK_HIST_S = 2, PK_HIST_B = 3, PK_BITMAP = 4, PK_HIST8 = 5, PK_HIST8N = 6 };
 
 template <int K, int W>
-__device__ __forceinline__ void persistent_case(int type, const uint8_t *cols, int64_t pitch,
-                                                const uint64_t *bits, int64_t wpitch,
-                                                const int32_t *soff, const uint8_t *arity,
-                                                const QDesc &q, int32_t c, int32_t chunks,
-                                                int32_t lds_words, int32_t pad, int32_t *tables,
-                                                uint32_t *lds) {
+__device__ __forceinline__ void persistent_case(int type, const uint8_t *cols, const uint8_t *nib,
+                                                int64_t pitch, const uint64_t *bits,
+                                                int64_t wpitch, const int32_t *soff,
+                                                const uint8_t *arity, const QDesc &q, int32_t c,
+                                                int32_t chunks, int32_t lds_words, int32_t pad,
+                                                int32_t *tables, uint32_t *lds) {
     switch (type) {
         case PK_HIST8:
             hist8_body<K, 64>(cols, pitch, arity, q, c, chunks, pad, tables, lds);
+            break;
+        case PK_HIST8N:
+            hist8n_body<K, 64>(nib, pitch, arity, q, c, chunks, pad, tables, lds);
             break;
         case PK_HIST16:
             hist16_body<K>(cols, pitch, arity, q, c, chunks, lds_words, pad, tables, lds);
@@ -709,9 +712,10 @@ __device__ __forceinline__ void persistent_case(int type, const uint8_t *cols, i
 
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_count_persistent(
-    const uint8_t *__restrict__ cols, int64_t pitch, const uint64_t *__restrict__ bits,
-    int64_t wpitch, const int32_t *__restrict__ soff, const uint8_t *__restrict__ arity,
-    const QDesc *__restrict__ descs, const PGroup *__restrict__ groups, int32_t ngroups,
+    const uint8_t *__restrict__ cols, const uint8_t *__restrict__ nib, int64_t pitch,
+    const uint64_t *__restrict__ bits, int64_t wpitch, const int32_t *__restrict__ soff,
+    const uint8_t *__restrict__ arity, const QDesc *__restrict__ descs,
+    const PGroup *__restrict__ groups, int32_t ngroups,
     int64_t total_v, uint32_t *__restrict__ heads, int32_t lds_words, int32_t pad_rows,
     int32_t *__restrict__ tables) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
@@ -744,14 +748,14 @@ __global__ __launch_bounds__(kBlock) void k_count_persistent(
         const QDesc &q = descs[G.first + di];
         const int type = G.kind >> 4;
         switch (G.kind & 15) {
-            case 1: persistent_case<1, W>(type, cols, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
-            case 2: persistent_case<2, W>(type, cols, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
-            case 3: persistent_case<3, W>(type, cols, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
-            case 4: persistent_case<4, W>(type, cols, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
-            case 5: persistent_case<5, W>(type, cols, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
-            case 6: persistent_case<6, W>(type, cols, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
-            case 7: persistent_case<7, W>(type, cols, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
-            default: persistent_case<8, W>(type, cols, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+            case 1: persistent_case<1, W>(type, cols, nib, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+            case 2: persistent_case<2, W>(type, cols, nib, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+            case 3: persistent_case<3, W>(type, cols, nib, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+            case 4: persistent_case<4, W>(type, cols, nib, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+            case 5: persistent_case<5, W>(type, cols, nib, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+            case 6: persistent_case<6, W>(type, cols, nib, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+            case 7: persistent_case<7, W>(type, cols, nib, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
+            default: persistent_case<8, W>(type, cols, nib, pitch, bits, wpitch, soff, arity, q, c, G.chunks, lds_words, pad_rows, tables, lds); break;
         }
     }
 }
@@ -1843,7 +1847,8 @@ static hipError_t launch_persistent_w(const fc_db *db, const PGroup *d_groups, i
     grid = std::min<int64_t>(grid, vtotal);
     grid = std::max<int64_t>(grid, 1);
     hipLaunchKernelGGL((k_count_persistent<W>), dim3((unsigned)grid), dim3(kBlock), lds, s,
-                       db->d_cols, db->pitch, db->d_bits, db->pitch / 64, db->d_soff, db->d_arity, dw,
+                       db->d_cols, db->d_nib, db->pitch, db->d_bits, db->pitch / 64, db->d_soff,
+                       db->d_arity, dw,
                        d_groups, ngroups, vtotal, heads, lds / 4, (int32_t)(db->m_pad - db->m),
                        tables);
     return hipGetLastError();
@@ -1865,7 +1870,23 @@ struct Image {
 };
 
 static void make_image(const fc_db *db, const Plan &P, uint32_t reducers, Image &I) {
-    for (const Launch &L : P.launches) {
+    // Groups of the persistent launch in decreasing cost of one work unit
+    // (longest processing time first: the dearest units are claimed first
+    // and the cheap ones fill in at the end): rows scanned per unit times
+    // the key digits per row, plus the zeroing and flush of the table.
+    std::vector<const Launch *> order;
+    for (const Launch &L : P.launches) order.push_back(&L);
+    if (P.nq <= db->tune.persistent_max_queries) {
+        auto unit_cost = [&](const Launch *L) {
+            const double rows = (double)db->m_pad / (double)std::max<int32_t>(L->chunks, 1);
+            return rows * (double)(L->K + 1) + (double)L->lds_bytes;
+        };
+        std::stable_sort(order.begin(), order.end(), [&](const Launch *a, const Launch *b) {
+            return unit_cost(a) > unit_cost(b);
+        });
+    }
+    for (const Launch *Lp : order) {
+        const Launch &L = *Lp;
         if (P.nq <= db->tune.persistent_max_queries &&
             L.lds_bytes <= kPersistentLds) {
             PGroup g;
@@ -1874,8 +1895,11 @@ static void make_image(const fc_db *db, const Plan &P, uint32_t reducers, Image 
             g.first = (int32_t)L.first;
             g.nd = L.count;
             g.chunks = L.chunks;
+            // tables of these groups fit 16 KiB of LDS: the byte-key classes
+            // (packed columns or bytes), Bitmap walks, or generic keys
             const int type = L.strat == S_BITMAP ? PK_BITMAP
-                           : (L.hk == HK_HIST8 || L.hk == HK_HIST8N) ? PK_HIST8
+                           : L.hk == HK_HIST8N ? PK_HIST8N
+                           : L.hk == HK_HIST8 ? PK_HIST8
                            : (L.hk == HK_HIST16 || L.hk == HK_HIST16N) ? PK_HIST16
                            : L.small ? PK_HIST_S : PK_HIST_B;
             g.kind = (type << 4) | L.K;
