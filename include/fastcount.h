@@ -265,6 +265,34 @@ int fc_count_reduce(fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
                     float *scores, float *err, int32_t *tables,
                     const int64_t *table_off, uint32_t flags, void *stream);
 
+/*
+ * For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * fc_count_reduce with the tables consumed, allocating no device or pinned
+ * host memory.  The plan image and the tables live in one statically sized
+ * device array of FC_NOALLOC_SCRATCH_BYTES per GPU, which the library holds
+ * from its first use on that GPU until the process ends.
+ *
+ * Arguments are those of fc_count_reduce without tables/table_off; scores
+ * ([slot][nq] floats) and err (same layout, may be NULL) must be device
+ * memory.  Results are bitwise those of fc_count_reduce for the same batch
+ * and tuning.  Asynchronous on `stream`.  The plan image is copied from
+ * pageable host memory, so the host thread waits for that copy.
+ *
+ * Errors: those of fc_count_reduce; FC_ERR_INVALID for host-memory scores
+ * or err; FC_ERR_RANGE when the batch needs more scratch than
+ * FC_NOALLOC_SCRATCH_BYTES (plan image plus 4 bytes per table cell; the
+ * message gives the figure), before anything is launched.
+ *
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (different streams or host threads without ordering) race and give
+ * wrong results.  Calls on one stream are ordered and safe.
+ */
+#define FC_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int fc_count_reduce_noalloc(fc_db *db, const int32_t *vars_flat,
+                            const int64_t *var_off, int64_t nq, uint32_t reducers,
+                            const fc_reduce_params *p, float *scores, float *err,
+                            uint32_t flags, void *stream);
 
 /*
  * Exact parent-set search support (Section 4.2): the scores of every parent

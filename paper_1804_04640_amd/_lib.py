@@ -32,7 +32,7 @@ FC_RED_MI = 8
 
 # every symbol the header declares
 EXPORTS = ("fc_db_create", "fc_db_append", "fc_db_destroy", "fc_db_trim", "fc_db_info", "fc_db_marginals", "fc_table_cells",
-           "fc_count", "fc_count_assignment", "fc_count_assignments", "fc_count_sparse", "fc_count_sparse_batch", "fc_count_batch", "fc_count_reduce",
+           "fc_count", "fc_count_assignment", "fc_count_assignments", "fc_count_sparse", "fc_count_sparse_batch", "fc_count_batch", "fc_count_reduce", "fc_count_reduce_noalloc",
            "fc_score_parent_sets", "fc_pairs", "fc_mine", "fc_arm_sizes", "fc_arm_read", "fc_arm_free",
            "fc_batch_footprint", "fc_plan_summary", "fc_graph_create", "fc_graph_launch", "fc_graph_destroy",
            "fc_db_get_tuning", "fc_db_set_tuning", "fc_autotune",
@@ -123,6 +123,7 @@ def load():
             "fc_count_sparse_batch": (ctypes.c_int, [P, P, P, i64, P, P, i64, P, P, P]),
             "fc_count_batch": (ctypes.c_int, [P, P, P, i64, P, P, u32, P]),
             "fc_count_reduce": (ctypes.c_int, [P, P, P, i64, u32, P, P, P, P, P, u32, P]),
+            "fc_count_reduce_noalloc": (ctypes.c_int, [P, P, P, i64, u32, P, P, P, u32, P]),
             "fc_score_parent_sets": (ctypes.c_int, [P, i32, P, i32, i32, u32, P, ctypes.c_double,
                                                     P, i64, P]),
             "fc_pairs": (ctypes.c_int, [P, P, i32, ctypes.c_double, P, P, i64, P, P]),
@@ -236,6 +237,12 @@ def fc_count_reduce(db, vars_flat, var_off, nq, reducers, params, scores, err, t
                     flags, stream):
     return check(load().fc_count_reduce(db, vars_flat, var_off, nq, reducers, params, scores, err,
                                         tables, table_off, flags, stream))
+
+
+def fc_count_reduce_noalloc(db, vars_flat, var_off, nq, reducers, params, scores, err, flags,
+                            stream):
+    return check(load().fc_count_reduce_noalloc(db, vars_flat, var_off, nq, reducers, params,
+                                                scores, err, flags, stream))
 
 
 def fc_score_parent_sets(db, child, cand, ncand, size, reducers, params, prune_mdl, scores,

@@ -2228,6 +2228,91 @@ extern "C" int fc_count_reduce(fc_db *db, const int32_t *vars_flat, const int64_
     return FC_OK;
 }
 
+// ------------------------------------------------- no-allocation variant
+// One statically sized device array per GPU holds the plan image and the
+// consumed tables of fc_count_reduce_noalloc.  The array's name is a host
+// stand-in in host code; its device address comes from hipGetSymbolAddress,
+// taken once per device with that device current, and only that address is
+// passed to copies and kernels.
+namespace fc {
+static __device__ __align__(256) unsigned char scratch[FC_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// Device address of this device's scratch array (the device must be
+// current), or NULL with the error set.
+static void *scratch_address(int device) {
+    if (device < 0 || device >= kMaxDevices) {
+        set_error("fc_count_reduce_noalloc: device %d out of range", device);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_error("fc_count_reduce_noalloc: scratch address of device %d: %s", device,
+                      hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_ptr[device] = ptr;
+    }
+    return g_scratch_ptr[device];
+}
+}  // namespace fc
+
+extern "C" int fc_count_reduce_noalloc(fc_db *db, const int32_t *vars_flat,
+                                       const int64_t *var_off, int64_t nq, uint32_t reducers,
+                                       const fc_reduce_params *p, float *scores, float *err,
+                                       uint32_t flags, void *stream) {
+    clear_error();
+    if (reducers == 0 || (reducers & ~(uint32_t)(FC_RED_LL | FC_RED_MDL | FC_RED_BDEU | FC_RED_MI))) {
+        set_error("fc_count_reduce_noalloc: reducer mask %#x is empty or unknown", reducers);
+        return FC_ERR_INVALID;
+    }
+    const double ess = p ? p->ess : 1.0;
+    if (!(ess > 0.0)) {
+        set_error("fc_count_reduce_noalloc: ess must be > 0");
+        return FC_ERR_INVALID;
+    }
+    Plan P;
+    int rc = build_plan(db, vars_flat, var_off, nq, nullptr, flags, true, P);
+    if (rc) return rc;
+    if (nq == 0) return FC_OK;
+    if (!scores || !is_device_ptr(scores) || (err && !is_device_ptr(err))) {
+        set_error("fc_count_reduce_noalloc: scores (and err, when given) must be device memory");
+        return FC_ERR_INVALID;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    FC_HIP(hipSetDevice(db->device));
+    ensure_attrs();
+    Image I;
+    make_image(db, P, reducers, I);
+    const size_t img = (I.dev_bytes + 255) & ~(size_t)255;
+    const size_t need = img + sizeof(int32_t) * (size_t)std::max<int64_t>(P.total_cells, 1);
+    if (need > (size_t)FC_NOALLOC_SCRATCH_BYTES) {
+        set_error("fc_count_reduce_noalloc: the batch needs %zu bytes of scratch (plan %zu + "
+                  "tables of %lld cells), more than the %lld the library holds; split the batch",
+                  need, img, (long long)P.total_cells, (long long)FC_NOALLOC_SCRATCH_BYTES);
+        return FC_ERR_RANGE;
+    }
+    char *base = (char *)scratch_address(db->device);
+    if (!base) return FC_ERR_DEVICE;
+    // the plan image goes through pageable host memory: the copy has read it
+    // when hipMemcpyAsync returns, so the buffer is reused by the next call
+    static thread_local std::vector<char> host;
+    if (host.size() < I.bytes) host.resize(I.bytes);
+    fill_image(P, I, host.data());
+    hipError_t e = hipMemcpyAsync(base, host.data(), I.bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+        set_error("fc_count_reduce_noalloc: plan upload failed: %s", hipGetErrorString(e));
+        return FC_ERR_DEVICE;
+    }
+    return enqueue_batch(db, P, I, base, (int32_t *)(base + img), reducers, ess, scores, err, s);
+}
+
 extern "C" int fc_count_assignment(fc_db *db, const int32_t *vars, const uint8_t *states,
                                    int32_t k, int64_t *count, void *stream) {
     clear_error();
