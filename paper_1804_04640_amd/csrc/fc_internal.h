@@ -172,6 +172,20 @@ hipError_t launch_gram(const fc_db *db, const int32_t *rowidx, int32_t np, int32
                        int64_t ldc, const char *name, double alg_bytes, double alg_ops,
                        hipStream_t s);
 
+// Sorted distinct keys and their counts (fc_msd.hip): keys[0, nk) (clobbered,
+// as is alt[0, nk)) with only bits below end_bit set give uniq[0, *nruns)
+// ascending and cnt[i] = occurrences of uniq[i]; *nruns is written on the
+// device.  scratch: msd_scratch_bytes(nk, sizeof(K)) bytes.  With
+// top_given, the 256 words at msd_top_hist(scratch, ...) already hold the
+// histogram of the keys' top digit (bits [max(end_bit - 8, 0), end_bit)),
+// which the caller took while forming the keys.  Everything is enqueued on
+// s; the host does not wait.
+size_t msd_scratch_bytes(int64_t nk, size_t key_bytes);
+uint32_t *msd_top_hist(void *scratch, int64_t nk, size_t key_bytes);
+template <typename K>
+int msd_sort_rle(const fc_db *db, K *keys, K *alt, int64_t nk, unsigned end_bit, K *uniq,
+                 uint32_t *cnt, uint32_t *nruns, void *scratch, bool top_given, hipStream_t s);
+
 // Reducer launch (fc_reduce.hip).  descs: exactly one QDesc per query
 // (device, any order); scores[slot * nq + qid].
 hipError_t launch_reduce(const fc_db *db, const QDesc *descs, int64_t nd, int64_t nq,

@@ -19,9 +19,6 @@
 #include <cstring>
 #include <numeric>
 
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_run_length_encode.hpp>
-
 #include "fc_internal.h"
 
 namespace fc {
@@ -47,10 +44,15 @@ template <typename K>
 __global__ __launch_bounds__(256) void k_keys_batch(const uint8_t *__restrict__ cols, int64_t m,
                                                     int64_t pitch,
                                                     const BatchSpec *__restrict__ specs,
-                                                    K *__restrict__ keys) {
+                                                    K *__restrict__ keys, int top_lo, int top_width,
+                                                    uint32_t *__restrict__ top_hist) {
+    __shared__ uint32_t hist[256];
+    hist[threadIdx.x] = 0u;
+    __syncthreads();
     const int32_t j = blockIdx.y;
     const BatchSpec q = specs[j];
     K *out = keys + (int64_t)j * m;
+    const uint32_t dmask = (1u << top_width) - 1u;
     const int64_t groups = (m + kKeysPerThread - 1) / kKeysPerThread;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < groups;
          g += (int64_t)gridDim.x * blockDim.x) {
@@ -71,13 +73,20 @@ __global__ __launch_bounds__(256) void k_keys_batch(const uint8_t *__restrict__ 
                     key[e] += ((w[t] >> (8 * e)) & 0xFF) * st;
             }
         }
-        if (p0 + kKeysPerThread <= m) {
+        const int ne = (int)min((int64_t)kKeysPerThread, m - p0);
+#pragma unroll
+        for (int e = 0; e < kKeysPerThread; ++e)
+            if (e < ne) atomicAdd(&hist[(uint32_t)(key[e] >> top_lo) & dmask], 1u);
+        if (ne == kKeysPerThread) {
 #pragma unroll
             for (int e = 0; e < kKeysPerThread; ++e) out[p0 + e] = (K)key[e];
         } else {
-            for (int e = 0; e < kKeysPerThread && p0 + e < m; ++e) out[p0 + e] = (K)key[e];
+            for (int e = 0; e < ne; ++e) out[p0 + e] = (K)key[e];
         }
     }
+    __syncthreads();
+    const uint32_t c = hist[threadIdx.x];
+    if (c) atomicAdd(&top_hist[threadIdx.x], c);
 }
 
 // Runs of each query of a group: [run_lo, run_hi) of the group's run list,
@@ -229,27 +238,22 @@ struct Window {
 };
 
 // Estimated microseconds of one group's sort and run-length encoding on
-// MI355X (rocPRIM onesweep, 8-bit digits: a launch overhead plus a cost per
-// key and pass that depends on the key width).  Used only to choose groups.
+// MI355X by the MSD partition (fc_msd.hip): a fixed cost per 8-bit level
+// (its eight launches run whether or not the level has segments) plus a
+// cost per key that depends on the key width, measured on the high-arity
+// workload.  Used only to choose groups.
 double group_cost_us(int64_t nk, unsigned end_bit, bool wide) {
-    const double passes = (double)((end_bit + 7) / 8);
-    const double ns = wide ? 0.0117 + 0.0051 * passes : 0.0054 + 0.0044 * passes;
-    return 100.0 + 1e-3 * ns * (double)nk;
+    const double levels = (double)((end_bit + 7) / 8);
+    const double ns = wide ? 0.048 : 0.036;
+    return 30.0 + 40.0 * levels + 1e-3 * ns * (double)nk;
 }
 
 template <typename K>
 size_t sort_tmp_bytes(int64_t nk, unsigned end_bit, hipStream_t s, int *rc) {
-    size_t t_sort = 0, t_rle = 0;
-    hipError_t e = rocprim::radix_sort_keys(nullptr, t_sort, (K *)nullptr, (K *)nullptr,
-                                            (size_t)nk, 0u, end_bit, s);
-    if (e == hipSuccess)
-        e = rocprim::run_length_encode(nullptr, t_rle, (K *)nullptr, (unsigned)nk, (K *)nullptr,
-                                       (uint32_t *)nullptr, (uint32_t *)nullptr, s);
-    if (e != hipSuccess) {
-        set_error("rocPRIM size query: %s", hipGetErrorString(e));
-        *rc = FC_ERR_DEVICE;
-    }
-    return std::max(t_sort, t_rle);
+    (void)end_bit;
+    (void)s;
+    (void)rc;
+    return msd_scratch_bytes(nk, sizeof(K));
 }
 
 // Retained runs of one group: unique keys, counts, run count.
@@ -287,6 +291,11 @@ int sparse_group(fc_db *db, const Group &g, double col_bytes, const WindowBufs &
     Runs<K> R;
     R.carve(c, nk);
     const char *kname = sizeof(K) == 8 ? "k_keys_batch<u64>" : "k_keys_batch<u32>";
+    // the keys' top-digit histogram (the partition's first level) is taken
+    // as they are formed
+    uint32_t *top_hist = msd_top_hist(B.tmp, nk, sizeof(K));
+    const int top_lo = std::max((int)g.end_bit - 8, 0), top_width = (int)g.end_bit - top_lo;
+    FC_HIP(fill_zero_i32((int32_t *)top_hist, 256, s));
     {
         // algorithmic bytes: the group's columns read, its keys written
         ProfScope ps(kname, s, col_bytes + (double)sizeof(K) * (double)nk, 0.0);
@@ -294,19 +303,18 @@ int sparse_group(fc_db *db, const Group &g, double col_bytes, const WindowBufs &
         const int64_t bx = std::max<int64_t>(
             1, std::min<int64_t>((per_q + 255) / 256, (8 * (int64_t)db->cu_count + g.G - 1) / g.G));
         hipLaunchKernelGGL(k_keys_batch<K>, dim3((unsigned)bx, (unsigned)g.G), dim3(256), 0, s,
-                           db->d_cols, m, db->pitch, B.specs + g.q0, kin);
+                           db->d_cols, m, db->pitch, B.specs + g.q0, kin, top_lo, top_width,
+                           top_hist);
         FC_HIP(hipGetLastError());
         ps.end(s);
     }
     {
         // algorithmic bytes: the keys read and written once
-        ProfScope ps("sort+rle", s, 2.0 * (double)sizeof(K) * (double)nk, 0.0);
-        size_t tb = g.tmp_bytes;
-        FC_HIP(rocprim::radix_sort_keys(B.tmp, tb, kin, ksort, (size_t)nk, 0u, g.end_bit, s));
-        tb = g.tmp_bytes;
-        FC_HIP(rocprim::run_length_encode(B.tmp, tb, ksort, (unsigned)nk, R.uniq, R.cnt, R.nruns,
-                                          s));
+        ProfScope ps("msd sort+rle", s, 2.0 * (double)sizeof(K) * (double)nk, 0.0);
+        const int rc = msd_sort_rle<K>(db, kin, ksort, nk, g.end_bit, R.uniq, R.cnt, R.nruns,
+                                       B.tmp, true, s);
         ps.end(s);
+        if (rc != FC_OK) return rc;
     }
     hipLaunchKernelGGL(k_group_runs<K>, dim3((unsigned)((g.G + 255) / 256)), dim3(256), 0, s,
                        R.uniq, R.nruns, B.specs + g.q0, g.G, B.run_lo, B.run_hi);

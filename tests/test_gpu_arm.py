@@ -109,6 +109,39 @@ def test_sparse_tables():
         assert len(keys) == 5 and nnz > 5
 
 
+def test_sparse_tables_skewed_keys():
+    """Keys that pile up: one configuration holds 90% of the instances and a
+    few hundred share most of the rest, so the partition meets buckets that
+    stay large down to the last digit, and leaves of every size; plus a
+    uniform column set and a table of one configuration."""
+    rng = synth.rng_for(78)
+    m = (1 << 20) + 333
+    ar = np.array([97, 89, 83, 79, 71, 67, 2, 1], np.uint8)
+    D = np.zeros((8, m), np.uint8)
+    hot = rng.random(m) < 0.9
+    warm = rng.integers(0, 300, size=m)
+    for v in range(8):
+        a = int(ar[v])
+        common = rng.integers(0, a, size=300)
+        D[v] = np.where(hot, a // 2, np.where(rng.random(m) < 0.8, common[warm],
+                                              rng.integers(0, a, size=m))).astype(np.uint8)
+    D[7] = 0
+    print("skewed sparse keys: m=%d" % m, flush=True)
+    with Database(D, ar, bitvectors=False) as db:
+        qs = [[0, 1, 2, 3, 4, 5], [5, 4, 3, 2, 1, 0, 6], [0, 1], [7], [7, 6, 0],
+              [2, 3, 4, 5, 6, 7, 0, 1]]
+        keys, cnts, off = db.count_sparse_batch(qs)
+        keys, cnts = keys.cpu().numpy(), cnts.cpu().numpy()
+        for i, q in enumerate(qs):
+            rk, rc = orc.count_sparse(D, ar, q)
+            np.testing.assert_array_equal(keys[off[i]:off[i + 1]], rk, err_msg=str(q))
+            np.testing.assert_array_equal(cnts[off[i]:off[i + 1]], rc, err_msg=str(q))
+            k1, c1, n1 = db.count_sparse(q)
+            assert n1 == len(rk)
+            np.testing.assert_array_equal(k1, rk)
+            np.testing.assert_array_equal(c1, rc)
+
+
 @pytest.mark.parametrize("score", ["mdl", "bdeu"])
 def test_parent_set_assignment_is_exact(score):
     import itertools
