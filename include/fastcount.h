@@ -74,8 +74,11 @@ typedef struct fc_db fc_db;
 #define FC_STRAT_AUTO 0u      /* per-query choice by the cost model / tuner */
 #define FC_STRAT_HIST 1u      /* joint key + LDS histogram (Section 3.3)    */
 #define FC_STRAT_BITMAP 2u    /* AND of bit-vectors + popcount (Sec. 3.2)   */
-#define FC_STRAT_PARTITION 3u /* MSD partition by the top key digits, each  */
-                              /* part counted in LDS (Section 3.3)          */
+#define FC_STRAT_PARTITION 3u /* MSD partition by the top key digits: keys */
+                              /* formed in one pass and moved to their      */
+                              /* parts, each part counted in LDS (Section   */
+                              /* 3.3); beyond 2^25 cells, key windows that  */
+                              /* each rescan the columns                    */
 #define FC_STRAT_SORT FC_STRAT_PARTITION
 #define FC_STRAT_MASK 0xFu
 
@@ -443,12 +446,17 @@ typedef struct fc_tuning {
                                   query), instead of counting it from the
                                   instances; 0: every query is counted.
                                   The tables are the same.                 */
+    int32_t one_pass_partition; /* 1: tables beyond the LDS classes (up to
+                                  2^25 cells) are counted by the one-pass
+                                  partition (columns read once, keys moved
+                                  to their parts); 0: by key windows, each
+                                  a scan of the columns.  Same tables.     */
 } fc_tuning;
 
 /*
  * How a batch would be answered, planned but not launched (flags as in
- * fc_count_batch): out[0] queries counted by LDS-histogram kernels (whole
- * or in key windows), out[1] by Bitmap tree walks (Alg. 1), out[2] from the
+ * fc_count_batch): out[0] queries counted by LDS-histogram kernels (whole,
+ * in key windows or by the one-pass partition), out[1] by Bitmap tree walks (Alg. 1), out[2] from the
  * Gram of the state bit-vectors, out[3] summed out of another query's
  * table (derive_tables).  out[0..3] add up to nq.  Errors as fc_count_batch.
  */

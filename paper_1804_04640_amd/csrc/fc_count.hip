@@ -17,8 +17,11 @@
 //    Alg. 1 prunes a zero intersection.  The tree is walked on chip for a
 //    few 64-row words per thread at a time, never stored.
 //  * PARTITION: tables too large for LDS are split by their top key digits
-//    into windows that fit (the MSD partition of Section 3.3); each window is
-//    an LDS histogram of the rows whose key falls in it.
+//    into parts that fit (the MSD partition of Section 3.3): one pass over
+//    the columns forms every key and histograms its part, the keys are moved
+//    to their parts, and each part is an LDS histogram.  Tables beyond 2^25
+//    cells (or whose scratch would not fit) fall back to key windows, each
+//    an LDS histogram of a full scan that keeps the keys falling in it.
 // Partial tables of row chunks are summed into the output with int32
 // atomics, which is exact and order independent.
 #include <algorithm>
@@ -146,6 +149,253 @@ __global__ __launch_bounds__(kBlock) void k_hist(const uint8_t *__restrict__ col
     int32_t di, c;
     map_block(blockIdx.x, nd, chunks, di, c);
     hist_body<K, SMALL>(cols, pitch, arity, descs[di], c, chunks, lds_words, pad_rows, tables, lds);
+}
+
+// One-pass partition (Section 3.3, Alg. 3's buckets) for tables beyond the
+// LDS classes: the query's columns are read once to form every instance's
+// key, which goes to a key buffer while its part (key >> kPartBits) is
+// histogrammed; the parts are laid out by a scan, the keys moved to their
+// part as 16-bit offsets within it, and each part is then counted in LDS,
+// 2^kPartBits cells at a time.  Per query the scratch holds PartQ's arrays.
+constexpr int kPartBits = 13;                  // cells per part (32 KiB of LDS counters)
+constexpr int32_t kPartCells = 1 << kPartBits;
+constexpr int32_t kPartMax = 4096;             // parts per query: tables up to 2^25 cells
+constexpr int64_t kPartUnit = 65536;           // keys per counting work unit
+constexpr int64_t kPartTile = kBlock * 16;     // rows per workgroup step (16 per thread)
+constexpr size_t kPartBudget = size_t(512) << 20;  // scratch of one slice of queries
+
+struct PartQ {
+    uint32_t *cnt, *start, *cursor, *ustart;  // [kPartMax] each, ustart [kPartMax + 1]
+    uint32_t *keys;                           // [m]
+    uint16_t *low;                            // [m]
+};
+
+__host__ __device__ inline size_t part_qbytes(int64_t m) {
+    const size_t head = sizeof(uint32_t) * (4 * (size_t)kPartMax + 4);
+    return ((head + 4 * (size_t)m + 255) & ~(size_t)255) + ((2 * (size_t)m + 255) & ~(size_t)255);
+}
+
+__device__ __forceinline__ PartQ part_slots(char *q, int64_t m) {
+    PartQ P;
+    P.cnt = (uint32_t *)q;
+    P.start = P.cnt + kPartMax;
+    P.cursor = P.start + kPartMax;
+    P.ustart = P.cursor + kPartMax;
+    const size_t head = sizeof(uint32_t) * (4 * (size_t)kPartMax + 4);
+    P.keys = (uint32_t *)(q + head);
+    P.low = (uint16_t *)(q + ((head + 4 * (size_t)m + 255) & ~(size_t)255));
+    return P;
+}
+
+// Keys of every instance (the query's columns read once) and the parts'
+// sizes.  Grid: (workgroups per query, queries of the slice).
+__global__ __launch_bounds__(kBlock) void k_part_keys(const uint8_t *__restrict__ cols,
+                                                      int64_t pitch,
+                                                      const uint8_t *__restrict__ arity,
+                                                      const QDesc *__restrict__ descs, int64_t m,
+                                                      char *__restrict__ scratch, size_t qstride) {
+    __shared__ uint32_t h[kPartMax];
+    const QDesc q = descs[blockIdx.y];
+    const PartQ P = part_slots(scratch + blockIdx.y * qstride, m);
+    const int32_t nparts = (q.cells + kPartCells - 1) >> kPartBits;
+    uint32_t stride[FC_MAX_VARS];
+    Col colp[FC_MAX_VARS];
+    {
+        uint32_t sacc = 1;
+#pragma unroll
+        for (int t = FC_MAX_VARS - 1; t >= 0; --t) {
+            if (t < q.k) {
+                const int32_t v = q.var[t];
+                stride[t] = sacc;
+                sacc *= arity[v];
+                colp[t] = make_col(cols + (int64_t)v * pitch, pitch);
+            } else {
+                stride[t] = 0;
+                colp[t] = make_col(cols, 0);
+            }
+        }
+    }
+    for (int32_t i = threadIdx.x; i < nparts; i += kBlock) h[i] = 0;
+    __syncthreads();
+    for (int64_t r0 = (int64_t)blockIdx.x * kPartTile + threadIdx.x * 16; r0 < m;
+         r0 += (int64_t)gridDim.x * kPartTile) {
+        uint32_t key[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) key[i] = 0;
+#pragma unroll
+        for (int t = 0; t < FC_MAX_VARS; ++t) {
+            if (t < q.k) {
+                const uint4 v = load16(colp[t], (uint32_t)r0);
+#pragma unroll
+                for (int i = 0; i < 16; ++i) key[i] += byte_of(v, i) * stride[t];
+            }
+        }
+        if (r0 + 16 <= m) {
+            uint4 *o = reinterpret_cast<uint4 *>(P.keys + r0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                o[i] = make_uint4(key[4 * i], key[4 * i + 1], key[4 * i + 2], key[4 * i + 3]);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) atomicAdd(&h[key[i] >> kPartBits], 1u);
+        } else {
+            for (int i = 0; i < 16; ++i)
+                if (r0 + i < m) {
+                    P.keys[r0 + i] = key[i];
+                    atomicAdd(&h[key[i] >> kPartBits], 1u);
+                }
+        }
+    }
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < nparts; i += kBlock)
+        if (h[i]) atomicAdd(&P.cnt[i], h[i]);
+}
+
+// Per query (one workgroup): part starts, scatter cursors, and the first
+// counting unit of every part (kPartUnit keys per unit).
+__global__ __launch_bounds__(kBlock) void k_part_scan(const QDesc *__restrict__ descs, int64_t m,
+                                                      char *__restrict__ scratch, size_t qstride) {
+    __shared__ uint32_t sk[kBlock], su[kBlock];
+    const QDesc q = descs[blockIdx.x];
+    const PartQ P = part_slots(scratch + blockIdx.x * qstride, m);
+    const int32_t nparts = (q.cells + kPartCells - 1) >> kPartBits;
+    const int32_t per = (nparts + kBlock - 1) / kBlock;
+    const int32_t a = min(nparts, (int32_t)threadIdx.x * per), b = min(nparts, a + per);
+    uint32_t k = 0, u = 0;
+    for (int32_t i = a; i < b; ++i) {
+        k += P.cnt[i];
+        u += (uint32_t)((P.cnt[i] + kPartUnit - 1) / kPartUnit);
+    }
+    sk[threadIdx.x] = k;
+    su[threadIdx.x] = u;
+    __syncthreads();
+    for (int o = 1; o < kBlock; o <<= 1) {
+        const uint32_t xk = threadIdx.x >= (unsigned)o ? sk[threadIdx.x - o] : 0u;
+        const uint32_t xu = threadIdx.x >= (unsigned)o ? su[threadIdx.x - o] : 0u;
+        __syncthreads();
+        sk[threadIdx.x] += xk;
+        su[threadIdx.x] += xu;
+        __syncthreads();
+    }
+    k = sk[threadIdx.x] - k;
+    u = su[threadIdx.x] - u;
+    for (int32_t i = a; i < b; ++i) {
+        const uint32_t c = P.cnt[i];
+        P.start[i] = k;
+        P.cursor[i] = k;
+        P.ustart[i] = u;
+        k += c;
+        u += (uint32_t)((c + kPartUnit - 1) / kPartUnit);
+    }
+    if (threadIdx.x == kBlock - 1) P.ustart[nparts] = su[kBlock - 1];
+}
+
+// Every key to its part, as its offset within the part.  A workgroup step
+// ranks its keys per part in LDS, stages them there in part order, takes one
+// cursor atomic per part, and writes each part's keys as one contiguous run
+// (neighbouring threads, neighbouring addresses).
+__global__ __launch_bounds__(kBlock) void k_part_scatter(const QDesc *__restrict__ descs,
+                                                         int64_t m, char *__restrict__ scratch,
+                                                         size_t qstride) {
+    __shared__ uint32_t h[kPartMax], tstart[kPartMax];
+    __shared__ uint32_t stage[kPartTile];
+    __shared__ uint32_t wsum[kBlock / 64];
+    const QDesc q = descs[blockIdx.y];
+    const PartQ P = part_slots(scratch + blockIdx.y * qstride, m);
+    const int32_t nparts = (q.cells + kPartCells - 1) >> kPartBits;
+    const int32_t per = (nparts + kBlock - 1) / kBlock;  // parts per thread in the scan
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int64_t t0 = (int64_t)blockIdx.x * kPartTile; t0 < m; t0 += (int64_t)gridDim.x * kPartTile) {
+        for (int32_t i = threadIdx.x; i < nparts; i += kBlock) h[i] = 0;
+        __syncthreads();
+        const int64_t r0 = t0 + threadIdx.x * 16;
+        uint32_t key[16], rank[16];
+        if (r0 + 16 <= m) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(P.keys + r0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint4 v = src[i];
+                key[4 * i] = v.x;
+                key[4 * i + 1] = v.y;
+                key[4 * i + 2] = v.z;
+                key[4 * i + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) key[i] = r0 + i < m ? P.keys[r0 + i] : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            rank[i] = r0 + i < m ? atomicAdd(&h[key[i] >> kPartBits], 1u) : 0u;
+        __syncthreads();
+        // the tile's part starts (exclusive scan of h) and the global bases
+        const int32_t a = min(nparts, (int32_t)threadIdx.x * per), b = min(nparts, a + per);
+        uint32_t sum = 0;
+        for (int32_t i = a; i < b; ++i) sum += h[i];
+        uint32_t incl = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t x = __shfl_up(incl, o);
+            if (lane >= o) incl += x;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        uint32_t run = incl - sum;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) run += w < wave ? wsum[w] : 0u;
+        for (int32_t i = a; i < b; ++i) {
+            const uint32_t c = h[i];
+            tstart[i] = run;
+            h[i] = c ? atomicAdd(&P.cursor[i], c) : 0u;  // becomes the part's global base
+            run += c;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (r0 + i < m) stage[tstart[key[i] >> kPartBits] + rank[i]] = key[i];
+        __syncthreads();
+        const int32_t nt = (int32_t)min((int64_t)kPartTile, m - t0);
+        for (int32_t j = threadIdx.x; j < nt; j += kBlock) {
+            const uint32_t k = stage[j];
+            const uint32_t p = k >> kPartBits;
+            P.low[h[p] + (uint32_t)j - tstart[p]] = (uint16_t)(k & (kPartCells - 1));
+        }
+        __syncthreads();
+    }
+}
+
+// Counts the parts in LDS: workgroups stride over the query's counting units
+// (unit j of part p: its keys [j * kPartUnit, (j + 1) * kPartUnit)), and add
+// each unit's non-zero cells to the (zeroed) table.
+__global__ __launch_bounds__(kBlock) void k_part_count(const QDesc *__restrict__ descs, int64_t m,
+                                                       char *__restrict__ scratch, size_t qstride,
+                                                       int32_t *__restrict__ tables) {
+    __shared__ uint32_t win[kPartCells];
+    const QDesc q = descs[blockIdx.y];
+    const PartQ P = part_slots(scratch + blockIdx.y * qstride, m);
+    const int32_t nparts = (q.cells + kPartCells - 1) >> kPartBits;
+    const uint32_t units = P.ustart[nparts];
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+        int32_t lo = 0, hi = nparts - 1;  // the last part whose first unit is <= u
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (P.ustart[mid] <= u) lo = mid; else hi = mid - 1;
+        }
+        const int32_t p = lo;
+        const int64_t a = (int64_t)P.start[p] + (int64_t)(u - P.ustart[p]) * kPartUnit;
+        const int64_t b = min((int64_t)P.start[p] + (int64_t)P.cnt[p], a + kPartUnit);
+        for (int32_t i = threadIdx.x; i < kPartCells; i += kBlock) win[i] = 0;
+        __syncthreads();
+        for (int64_t i = a + threadIdx.x; i < b; i += kBlock) atomicAdd(&win[P.low[i]], 1u);
+        __syncthreads();
+        const int32_t c0 = p << kPartBits;
+        const int32_t nc = min(kPartCells, q.cells - c0);
+        int32_t *out = tables + q.table_off + c0;
+        for (int32_t i = threadIdx.x; i < nc; i += kBlock) {
+            const uint32_t v = win[i];
+            if (v) atomicAdd(&out[i], (int32_t)v);
+        }
+        __syncthreads();
+    }
 }
 
 // Lane-column histograms: every cell owns B consecutive LDS words (B a power
@@ -982,6 +1232,10 @@ struct Plan {
     // tables summed out of a counted superset's table after counting
     std::vector<MDesc> marg;
     int32_t marg_max_cells = 0;
+    // tables beyond the LDS classes counted by the one-pass partition:
+    // descriptors work[part_first, +part_count), k bytes per instance each
+    int64_t part_first = 0, part_count = 0;
+    double part_bytes = 0.0;
 };
 
 // LDS size classes; every class but the last keeps its byte addresses below
@@ -1106,7 +1360,17 @@ struct RangeStat {
     std::vector<int32_t> maxc;
     int64_t nsmall = 0, gcur = 0;   // one- and two-variable queries; their cursor
     std::vector<uint8_t> used;      // [n] variables of those queries
+    int64_t npart = 0, pcur = 0;    // one-pass partition queries; their cursor
+    double pbytes = 0.0;
 };
+
+// Whether a partitioned query takes the one-pass partition (its parts fit
+// the part table and one query's scratch fits the slice budget); else key
+// windows, each a scan of the columns.
+inline bool one_pass(const fc_db *db, int64_t c) {
+    return db->tune.one_pass && db->m > 0 && c <= (int64_t)kPartMax * kPartCells &&
+           part_qbytes(db->m) <= kPartBudget;
+}
 
 // Strategy of one query (validated), and its window size for partitions.
 inline int choose(const fc_db *db, uint32_t forced, int64_t k, int64_t c, int64_t &win) {
@@ -1490,6 +1754,10 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
             if (k <= 2 && gram_allowed) {
                 ++r.nsmall;
                 for (int64_t t = 0; t < k; ++t) r.used[(size_t)vars_flat[var_off[i] + t]] = 1;
+            } else if (st == S_PART && one_pass(db, c)) {
+                ++r.npart;
+                r.pbytes += (double)k * (double)db->m;
+                continue;
             }
             for (int64_t b0 = 0; b0 < c; b0 += win) {
                 const int64_t wc = std::min<int64_t>(win, c - b0);
@@ -1577,7 +1845,15 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
             r.gcur = P.gram_first + P.gram_count;
             P.gram_count += r.nsmall;
         }
-    P.work.resize((size_t)(start[kBuckets] + P.gram_count));
+    P.part_first = start[kBuckets] + P.gram_count;
+    P.part_count = 0;
+    P.part_bytes = 0.0;
+    for (auto &r : R) {
+        r.pcur = P.part_first + P.part_count;
+        P.part_count += r.npart;
+        P.part_bytes += r.pbytes;
+    }
+    P.work.resize((size_t)(P.part_first + P.part_count));
     if (need_query) P.query.resize((size_t)nq);
     std::vector<int64_t> base((size_t)T, 0);
     for (int64_t t = 1; t < T; ++t) base[(size_t)t] = base[(size_t)t - 1] + R[(size_t)t - 1].cells_sum;
@@ -1612,6 +1888,10 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
             int64_t win;
             const int st = choose(db, forced, k, c, win);
             const bool small = c < (int64_t(1) << 24);
+            if (st == S_PART && one_pass(db, c) && !(k <= 2 && gram_allowed)) {
+                P.work[(size_t)r.pcur++] = d;  // as counted in pass 1
+                continue;
+            }
             for (int64_t b0 = 0; b0 < c; b0 += win) {
                 const int64_t wc = std::min<int64_t>(win, c - b0);
                 const int b = st == S_BITMAP ? bucket_of(S_BITMAP, (int)k, 0, false)
@@ -1672,7 +1952,7 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
                         snprintf(L.name, sizeof L.name, "k_hist<%d,%d>", K, sm);
                     P.launches.push_back(L);
                 }
-    P.direct = db->m > 0;
+    P.direct = db->m > 0;  // the partition zeroes its own tables
     for (const Launch &L : P.launches)
         if (L.strat == S_BITMAP || L.chunks != 1) P.direct = false;
     if (derive) {
@@ -1866,7 +2146,9 @@ struct Image {
     bool with_query = false;
     size_t off_query = 0, off_groups = 0, off_heads = 0, bytes = 0;
     size_t off_gram_rows = 0, off_gram_pos = 0, off_gram_c = 0, off_marg = 0;
-    size_t dev_bytes = 0;  // bytes plus the device-only state Gram
+    size_t dev_bytes = 0;  // bytes plus the device-only state Gram and partition scratch
+    size_t off_part = 0, part_qstride = 0;
+    int64_t part_slice = 0;  // partition queries per slice (they share the scratch)
 };
 
 static void make_image(const fc_db *db, const Plan &P, uint32_t reducers, Image &I) {
@@ -1931,6 +2213,13 @@ static void make_image(const fc_db *db, const Plan &P, uint32_t reducers, Image 
     I.dev_bytes = P.gram_count ? I.off_gram_c + sizeof(int32_t) * (size_t)P.gram_np *
                                                     (size_t)P.gram_np
                                : I.bytes;
+    if (P.part_count) {
+        I.part_qstride = part_qbytes(db->m);
+        I.part_slice = std::max<int64_t>(
+            1, std::min<int64_t>(P.part_count, (int64_t)(kPartBudget / I.part_qstride)));
+        I.off_part = (I.dev_bytes + 255) & ~(size_t)255;
+        I.dev_bytes = I.off_part + I.part_qstride * (size_t)I.part_slice;
+    }
 }
 
 // memcpy split over host threads for large plans (pinned destination).
@@ -1962,6 +2251,62 @@ static void fill_image(const Plan &P, const Image &I, void *host) {
         std::memcpy(h + I.off_gram_pos, P.gram_pos.data(), sizeof(int32_t) * P.gram_pos.size());
     if (!P.marg.empty())
         std::memcpy(h + I.off_marg, P.marg.data(), sizeof(MDesc) * P.marg.size());
+}
+
+// The one-pass partition queries, a slice at a time (a slice's queries
+// share the scratch; the slices follow each other on the stream).
+__global__ void k_part_zero(char *scratch, size_t qstride) {
+    uint32_t *cnt = (uint32_t *)(scratch + blockIdx.x * qstride);
+    for (int32_t i = threadIdx.x; i < kPartMax; i += blockDim.x) cnt[i] = 0u;
+}
+
+static hipError_t enqueue_partition(const fc_db *db, const Plan &P, const Image &I,
+                                    const QDesc *dw, char *scratch, int32_t *tables,
+                                    hipStream_t s) {
+    const int64_t m = db->m;
+    const int cus = db->cu_count > 0 ? db->cu_count : 256;
+    for (int64_t s0 = 0; s0 < P.part_count; s0 += I.part_slice) {
+        const int64_t n = std::min<int64_t>(I.part_slice, P.part_count - s0);
+        const QDesc *d = dw + P.part_first + s0;
+        double bytes = 0.0;
+        for (int64_t i = 0; i < n; ++i)
+            bytes += (double)P.work[(size_t)(P.part_first + s0 + i)].k * (double)m;
+        const int64_t tiles = (m + kPartTile - 1) / kPartTile;
+        const unsigned gx = (unsigned)std::max<int64_t>(
+            1, std::min<int64_t>(tiles, (8 * (int64_t)cus + n - 1) / n));
+        const int64_t units_max = (m + kPartUnit - 1) / kPartUnit + kPartMax;
+        const unsigned gc = (unsigned)std::max<int64_t>(
+            1, std::min<int64_t>(units_max, (8 * (int64_t)cus + n - 1) / n));
+        hipLaunchKernelGGL(k_part_zero, dim3((unsigned)n), dim3(256), 0, s, scratch,
+                           I.part_qstride);
+        if (P.direct)  // the other tables are stored whole; these are added to
+            hipLaunchKernelGGL(k_zero_tables, dim3((unsigned)n), dim3(256), 0, s, d, (int32_t)n,
+                               tables);
+        {
+            // algorithmic bytes: k per (query, instance), the columns read once
+            ProfScope ps("k_part_keys", s, bytes, 0.0);
+            hipLaunchKernelGGL(k_part_keys, dim3(gx, (unsigned)n), dim3(kBlock), 0, s, db->d_cols,
+                               db->pitch, db->d_arity, d, m, scratch, I.part_qstride);
+            ps.end(s);
+        }
+        hipLaunchKernelGGL(k_part_scan, dim3((unsigned)n), dim3(kBlock), 0, s, d, m, scratch,
+                           I.part_qstride);
+        {
+            ProfScope ps("k_part_scatter", s, 0.0, 0.0);
+            hipLaunchKernelGGL(k_part_scatter, dim3(gx, (unsigned)n), dim3(kBlock), 0, s, d, m,
+                               scratch, I.part_qstride);
+            ps.end(s);
+        }
+        {
+            ProfScope ps("k_part_count", s, 0.0, 0.0);
+            hipLaunchKernelGGL(k_part_count, dim3(gc, (unsigned)n), dim3(kBlock), 0, s, d, m,
+                               scratch, I.part_qstride, tables);
+            ps.end(s);
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // Every device step of a batch whose image is resident at `dimg`: zero the
@@ -2021,6 +2366,7 @@ static int enqueue_batch(fc_db *db, const Plan &P, const Image &I, void *dimg, i
             FC_HIP(launch_count(db, *L, dw, tables, s));
             ps.end(s);
         }
+        if (P.part_count) FC_HIP(enqueue_partition(db, P, I, dw, (char *)dimg + I.off_part, tables, s));
         if (!P.marg.empty()) {
             const MDesc *md = (const MDesc *)((char *)dimg + I.off_marg);
             const int64_t nm = (int64_t)P.marg.size();
@@ -2401,7 +2747,7 @@ extern "C" int fc_plan_summary(const fc_db *db, const int32_t *vars_flat, const 
             seen[(size_t)q] = 1;
             if (L.strat == S_BITMAP) ++bitmap; else ++hist;
         }
-    out[0] = hist;
+    out[0] = hist + P.part_count;
     out[1] = bitmap;
     out[2] = P.gram_count;
     out[3] = (int64_t)P.marg.size();
@@ -2422,6 +2768,7 @@ extern "C" int fc_db_get_tuning(const fc_db *db, fc_tuning *t) {
     t->packed_columns = db->tune.packed_columns;
     t->bitmap_order = db->tune.bitmap_order;
     t->derive_tables = db->tune.derive;
+    t->one_pass_partition = db->tune.one_pass;
     return FC_OK;
 }
 
@@ -2435,9 +2782,11 @@ extern "C" int fc_db_set_tuning(fc_db *db, const fc_tuning *t) {
         (t->bitmap_words != 1 && t->bitmap_words != 2 && t->bitmap_words != 4) ||
         (t->packed_columns != 0 && t->packed_columns != 1) ||
         (t->bitmap_order != 0 && t->bitmap_order != 1) ||
-        (t->derive_tables != 0 && t->derive_tables != 1)) {
+        (t->derive_tables != 0 && t->derive_tables != 1) ||
+        (t->one_pass_partition != 0 && t->one_pass_partition != 1)) {
         set_error("fc_db_set_tuning: chunk rows must be >= %lld, bitmap_words 1, 2 or 4, "
-                  "packed_columns, bitmap_order and derive_tables 0 or 1", (long long)kTileRows);
+                  "packed_columns, bitmap_order, derive_tables and one_pass_partition 0 or 1",
+                  (long long)kTileRows);
         return FC_ERR_INVALID;
     }
     db->tune.chunk_rows = t->chunk_rows;
@@ -2448,6 +2797,7 @@ extern "C" int fc_db_set_tuning(fc_db *db, const fc_tuning *t) {
     db->tune.packed_columns = t->packed_columns;
     db->tune.bitmap_order = t->bitmap_order;
     db->tune.derive = t->derive_tables;
+    db->tune.one_pass = t->one_pass_partition;
     return FC_OK;
 }
 

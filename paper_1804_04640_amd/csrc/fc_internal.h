@@ -45,6 +45,7 @@ struct Tuning {
     int packed_columns = 1;             // histograms read the 4-bit columns when present
     int bitmap_order = 1;               // 1: bitmap trees walk variables by ascending entropy
     int derive = 1;                     // 1: automatic plans sum tables out of supersets
+    int one_pass = 1;                   // 1: one-pass partition for tables beyond LDS
     // bitmap_cells[k-1][b]: bitmap for k variables and <= 2^(b+2) cells
     uint8_t bitmap_cells[FC_MAX_VARS][6] = {};
     Tuning() {

@@ -71,7 +71,7 @@ def test_batched_uneven_small_and_host_output():
 
 
 def test_large_table_partition_path():
-    # 6 variables of arity 8: 262144 cells > LDS, so the MSD partition runs
+    # 6 variables of arity 8: 262144 cells > LDS, so the one-pass partition runs (32 parts)
     rng = np.random.default_rng(7)
     m = 70_001
     ar = np.full(6, 8, np.uint8)
@@ -80,6 +80,51 @@ def test_large_table_partition_path():
         for vs in ([0, 1, 2, 3, 4, 5], [5, 3, 1, 0, 2, 4]):
             got = db.count(vs).cpu().numpy()
             np.testing.assert_array_equal(got, orc.count(D, ar, vs))
+
+
+def test_partition_one_pass_slices_and_ragged_parts():
+    """Tables of 119,070 to 1.66M cells (parts of 8,192 cells, the last one
+    ragged) over m = 2,000,003 instances: 45 queries take the one-pass
+    partition in two slices of the shared scratch (42 and 3)."""
+    rng = np.random.default_rng(21)
+    m = 2_000_003
+    ar = np.array([7, 9, 11, 13, 7, 9, 11, 13, 5, 6], np.uint8)
+    D = np.stack([rng.integers(0, a, size=m) for a in ar]).astype(np.uint8)
+    # a skewed column: most instances in one state
+    D[3] = np.where(rng.random(m) < 0.7, 12, D[3]).astype(np.uint8)
+    import itertools
+    combos = list(itertools.combinations(range(10), 6))   # distinct sets: none derived
+    qs = [rng.permutation(combos[j]).astype(np.int32)
+          for j in rng.choice(len(combos), 45, replace=False)]
+    print("one-pass partition: m=%d queries=%d" % (m, len(qs)), flush=True)
+    with Database(D, ar) as db:
+        summ = db.plan_summary(qs)
+        assert summ["hist"] == len(qs), summ
+        tables, toff = db.count_batch(qs)
+        T = tables.cpu().numpy()
+        for i, q in enumerate(qs):
+            np.testing.assert_array_equal(T[toff[i]:toff[i + 1]], orc.count(D, ar, q),
+                                          err_msg=str(q))
+        # the key windows give the same tables
+        t = db.tuning()
+        t["one_pass_partition"] = 0
+        db.set_tuning(t)
+        t2, _ = db.count_batch(qs[:6])
+        np.testing.assert_array_equal(t2.cpu().numpy(), T[:toff[6]])
+
+
+def test_partition_beyond_the_part_table_uses_key_windows():
+    """62.7M cells (7 variables of arity 13) exceed the one-pass partition's
+    2^25 cells: the key windows count it, equal to the oracle."""
+    rng = np.random.default_rng(22)
+    m = 20_011
+    ar = np.full(7, 13, np.uint8)
+    D = rng.integers(0, 13, size=(7, m)).astype(np.uint8)
+    q = [6, 0, 5, 1, 4, 2, 3]
+    print("key windows: cells=%d m=%d" % (13 ** 7, m), flush=True)
+    with Database(D, ar) as db:
+        got = db.count(q).cpu().numpy()
+        np.testing.assert_array_equal(got, orc.count(D, ar, q))
 
 
 def test_batch_equals_alone():
