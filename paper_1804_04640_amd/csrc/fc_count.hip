@@ -1503,24 +1503,18 @@ static int64_t derive_plan(const fc_db *db, const int32_t *vars_flat, const int6
     if (nq < 2 || db->n > 255 || db->m <= 0) return 0;
     unsigned hw = std::thread::hardware_concurrency();
     const int T = (int)std::min<int64_t>(std::max<unsigned>(1u, std::min(16u, hw ? hw : 1u)),
-                                         std::max<int64_t>(1, nq / 16384));
+                                         std::max<int64_t>(1, nq / 2048));
     std::vector<uint64_t> key((size_t)nq, 0);
     std::vector<int64_t> cells((size_t)nq, 0);
     std::vector<uint8_t> kk((size_t)nq, 0);
-    // per (range, owner partition): (subset key, superset) and (own key, query)
-    std::vector<std::vector<std::pair<uint64_t, int32_t>>> sub((size_t)T * T), own((size_t)T * T);
+    // per (range, owner partition): (own key, query) of queries of 3+ variables
+    std::vector<std::vector<std::pair<uint64_t, int32_t>>> own((size_t)T * T);
     std::atomic<bool> bad(false);
-    std::atomic<int64_t> enumerated(0);
-    auto run = [&](auto f) {
-        std::vector<std::thread> th;
-        for (int t = 1; t < T; ++t) th.emplace_back(f, t);
-        f(0);
-        for (auto &x : th) x.join();
-    };
-    // keys, cells, and every 3- and 4-variable subset of larger queries
+    auto run = [&](auto f) { parallel_for(T, [&](int t) { f(t); }); };
+    // keys (sorted variables + 1 as bytes), cells
     run([&](int t) {
         const int64_t lo = nq * t / T, hi = nq * (t + 1) / T;
-        int64_t cnt = 0;
+        for (int o = 0; o < T; ++o) own[(size_t)t * T + o].reserve((size_t)((hi - lo) / T + 16));
         for (int64_t i = lo; i < hi; ++i) {
             const int64_t k = var_off[i + 1] - var_off[i];
             if (k < 1 || k > FC_MAX_VARS) {
@@ -1545,55 +1539,57 @@ static int64_t derive_plan(const fc_db *db, const int32_t *vars_flat, const int6
             key[(size_t)i] = kv;
             cells[(size_t)i] = c;
             kk[(size_t)i] = (uint8_t)k;
-            if (k < 3) continue;
-            own[(size_t)t * T + (size_t)(mix64(kv) % (uint64_t)T)].push_back({kv, (int32_t)i});
+            if (k >= 3) own[(size_t)t * T + (size_t)(mix64(kv) % (uint64_t)T)].push_back({kv, (int32_t)i});
+        }
+    });
+    if (bad) return 0;
+    // representatives: every variable set of 3+ variables to its lowest query
+    std::vector<SetMap> m0((size_t)T);
+    run([&](int o) {
+        size_t n0 = 0;
+        for (int t = 0; t < T; ++t) n0 += own[(size_t)t * T + o].size();
+        m0[(size_t)o].init(n0);
+        for (int t = 0; t < T; ++t)
+            for (auto &e : own[(size_t)t * T + o])
+                m0[(size_t)o].put(e.first, mix64(e.first) >> 8, e.second,
+                                  [](int32_t a, int32_t b) { return a < b; });
+    });
+    auto find = [&](uint64_t kv) {
+        const uint64_t h = mix64(kv);
+        return m0[(size_t)(h % (uint64_t)T)].get(kv, h >> 8);
+    };
+    // the smallest superset (fewest cells, then lowest index) of every
+    // represented set of 3 or 4 variables: each query of 4+ variables looks
+    // its sorted 3- and 4-variable subsets up and offers itself to those
+    // that some query has
+    std::vector<std::atomic<uint64_t>> best((size_t)nq);
+    for (auto &x : best) x.store(~0ull, std::memory_order_relaxed);
+    run([&](int t) {
+        const int64_t lo = nq * t / T, hi = nq * (t + 1) / T;
+        for (int64_t i = lo; i < hi; ++i) {
+            const int k = kk[(size_t)i];
             if (k < 4) continue;
-            // sorted subsets of 3 and 4 of the sorted variables
+            uint8_t v[FC_MAX_VARS];
+            for (int a = 0; a < k; ++a) v[a] = (uint8_t)(key[(size_t)i] >> (8 * (k - 1 - a)));
+            const uint64_t mine = ((uint64_t)cells[(size_t)i] << 32) | (uint64_t)i;
+            auto offer = [&](uint64_t sk) {
+                const int32_t r = find(sk);
+                if (r < 0) return;
+                std::atomic<uint64_t> &slot = best[(size_t)r];
+                uint64_t cur = slot.load(std::memory_order_relaxed);
+                while (mine < cur && !slot.compare_exchange_weak(cur, mine, std::memory_order_relaxed)) {
+                }
+            };
             for (int a = 0; a < k; ++a)
                 for (int b = a + 1; b < k; ++b)
                     for (int d = b + 1; d < k; ++d) {
                         const uint64_t s3 = ((uint64_t)v[a] << 16) | ((uint64_t)v[b] << 8) | v[d];
-                        sub[(size_t)t * T + (size_t)(mix64(s3) % (uint64_t)T)].push_back(
-                            {s3, (int32_t)i});
-                        ++cnt;
+                        offer(s3);
                         if (k < 5) continue;
-                        for (int e = d + 1; e < k; ++e) {
-                            const uint64_t s4 = (s3 << 8) | v[e];
-                            sub[(size_t)t * T + (size_t)(mix64(s4) % (uint64_t)T)].push_back(
-                                {s4, (int32_t)i});
-                            ++cnt;
-                        }
+                        for (int e = d + 1; e < k; ++e) offer((s3 << 8) | v[e]);
                     }
         }
-        enumerated += cnt;
     });
-    if (bad) return 0;
-    // the partitions: own keys keep the lowest query index, subset keys the
-    // superset with the fewest cells
-    std::vector<SetMap> m0((size_t)T), m1((size_t)T);
-    run([&](int o) {
-        size_t n0 = 0, n1 = 0;
-        for (int t = 0; t < T; ++t) {
-            n0 += own[(size_t)t * T + o].size();
-            n1 += sub[(size_t)t * T + o].size();
-        }
-        m0[(size_t)o].init(n0);
-        m1[(size_t)o].init(n1);
-        for (int t = 0; t < T; ++t) {
-            for (auto &e : own[(size_t)t * T + o])
-                m0[(size_t)o].put(e.first, mix64(e.first) >> 8, e.second,
-                                  [](int32_t a, int32_t b) { return a < b; });
-            for (auto &e : sub[(size_t)t * T + o])
-                m1[(size_t)o].put(e.first, mix64(e.first) >> 8, e.second, [&](int32_t a, int32_t b) {
-                    return cells[(size_t)a] != cells[(size_t)b] ? cells[(size_t)a] < cells[(size_t)b]
-                                                                : a < b;
-                });
-        }
-    });
-    auto find = [&](const std::vector<SetMap> &m, uint64_t kv) {
-        const uint64_t h = mix64(kv);
-        return m[(size_t)(h % (uint64_t)T)].get(kv, h >> 8);
-    };
     src.assign((size_t)nq, -1);
     // The chain of query i: its representative (lowest index with the same
     // variable set), then the representatives of successive smallest
@@ -1612,14 +1608,16 @@ static int64_t derive_plan(const fc_db *db, const int32_t *vars_flat, const int6
             if (kk[(size_t)i] < 3 || cells[(size_t)i] > kMargMaxCells) continue;
             int32_t ch[FC_MAX_VARS + 1];
             int L = 0;
-            const int32_t r0 = find(m0, key[(size_t)i]);
+            const int32_t r0 = find(key[(size_t)i]);
             ch[L++] = r0 >= 0 ? r0 : (int32_t)i;
             while (L < FC_MAX_VARS + 1) {
                 const int32_t r = ch[L - 1];
                 const int kr = kk[(size_t)r];
-                const int32_t up = (kr == 3 || kr == 4) ? find(m1, key[(size_t)r]) : -1;
-                if (up < 0) break;
-                const int32_t ru = find(m0, key[(size_t)up]);
+                const uint64_t bu = (kr == 3 || kr == 4) ? best[(size_t)r].load(std::memory_order_relaxed)
+                                                         : ~0ull;
+                if (bu == ~0ull) break;
+                const int32_t up = (int32_t)(bu & 0xFFFFFFFFull);
+                const int32_t ru = find(key[(size_t)up]);
                 ch[L++] = ru >= 0 ? ru : up;
             }
             bool counted[FC_MAX_VARS + 1];
@@ -1645,7 +1643,6 @@ static int64_t derive_plan(const fc_db *db, const int32_t *vars_flat, const int6
         if (r >= 0 && src[(size_t)r] >= 0) src[(size_t)i] = -1;
         if (src[(size_t)i] >= 0) ++n;
     }
-    (void)enumerated;
     return n;
 }
 
@@ -1669,14 +1666,7 @@ static uint32_t walk_order(const fc_db *db, const QDesc &d) {
 
 template <typename F>
 void parallel_ranges(std::vector<RangeStat> &R, F f) {
-    if (R.size() == 1) {
-        f(R[0]);
-        return;
-    }
-    std::vector<std::thread> th;
-    th.reserve(R.size());
-    for (auto &r : R) th.emplace_back([&f, &r] { f(r); });
-    for (auto &t : th) t.join();
+    parallel_for((int)R.size(), [&](int t) { f(R[(size_t)t]); });
 }
 }  // namespace
 
@@ -2231,12 +2221,10 @@ static void parallel_copy(void *dst, const void *src, size_t bytes) {
         std::memcpy(dst, src, bytes);
         return;
     }
-    std::vector<std::thread> th;
-    for (size_t t = 0; t < T; ++t) {
-        const size_t lo = bytes * t / T, hi = bytes * (t + 1) / T;
-        th.emplace_back([=] { std::memcpy((char *)dst + lo, (const char *)src + lo, hi - lo); });
-    }
-    for (auto &x : th) x.join();
+    parallel_for((int)T, [&](int t) {
+        const size_t lo = bytes * (size_t)t / T, hi = bytes * (size_t)(t + 1) / T;
+        std::memcpy((char *)dst + lo, (const char *)src + lo, hi - lo);
+    });
 }
 
 static void fill_image(const Plan &P, const Image &I, void *host) {

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <mutex>
 #include <string>
+#include <functional>
 #include <vector>
 
 #include "fastcount.h"
@@ -172,6 +173,10 @@ int count_reduce_device(fc_db *db, const int32_t *vars_flat, const int64_t *var_
 hipError_t launch_gram(const fc_db *db, const int32_t *rowidx, int32_t np, int32_t *C,
                        int64_t ldc, const char *name, double alg_bytes, double alg_ops,
                        hipStream_t s);
+
+// Host fork-join (fc_pool.hip): f(0) on the calling thread, f(1) ..
+// f(T - 1) on persistent workers; returns when all have returned.
+void parallel_for(int T, const std::function<void(int)> &f);
 
 // Sorted distinct keys and their counts (fc_msd.hip): keys[0, nk) (clobbered,
 // as is alt[0, nk)) with only bits below end_bit set give uniq[0, *nruns)
