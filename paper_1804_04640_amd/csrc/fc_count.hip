@@ -1510,6 +1510,13 @@ static int64_t derive_plan(const fc_db *db, const int32_t *vars_flat, const int6
     // per (range, owner partition): (own key, query) of queries of 3+ variables
     std::vector<std::vector<std::pair<uint64_t, int32_t>>> own((size_t)T * T);
     std::atomic<bool> bad(false);
+    // a bit per hashed variable set of 3 or 4 variables present in the batch
+    // (2^20 bits): most subsets of the larger queries are absent and are
+    // turned away here without a probe of the map
+    constexpr int kFiltBits = 20;
+    std::vector<std::atomic<uint64_t>> filt((size_t)1 << (kFiltBits - 6));
+    for (auto &x : filt) x.store(0, std::memory_order_relaxed);
+    auto filt_bit = [](uint64_t h) { return h >> (64 - kFiltBits); };
     auto run = [&](auto f) { parallel_for(T, [&](int t) { f(t); }); };
     // keys (sorted variables + 1 as bytes), cells
     run([&](int t) {
@@ -1539,7 +1546,14 @@ static int64_t derive_plan(const fc_db *db, const int32_t *vars_flat, const int6
             key[(size_t)i] = kv;
             cells[(size_t)i] = c;
             kk[(size_t)i] = (uint8_t)k;
-            if (k >= 3) own[(size_t)t * T + (size_t)(mix64(kv) % (uint64_t)T)].push_back({kv, (int32_t)i});
+            if (k >= 3) {
+                const uint64_t h = mix64(kv);
+                own[(size_t)t * T + (size_t)(h % (uint64_t)T)].push_back({kv, (int32_t)i});
+                if (k <= 4) {
+                    const uint64_t b = filt_bit(h);
+                    filt[(size_t)(b >> 6)].fetch_or(1ull << (b & 63), std::memory_order_relaxed);
+                }
+            }
         }
     });
     if (bad) return 0;
@@ -1573,7 +1587,11 @@ static int64_t derive_plan(const fc_db *db, const int32_t *vars_flat, const int6
             for (int a = 0; a < k; ++a) v[a] = (uint8_t)(key[(size_t)i] >> (8 * (k - 1 - a)));
             const uint64_t mine = ((uint64_t)cells[(size_t)i] << 32) | (uint64_t)i;
             auto offer = [&](uint64_t sk) {
-                const int32_t r = find(sk);
+                const uint64_t h = mix64(sk);
+                const uint64_t bit = filt_bit(h);
+                if (!((filt[(size_t)(bit >> 6)].load(std::memory_order_relaxed) >> (bit & 63)) & 1))
+                    return;
+                const int32_t r = m0[(size_t)(h % (uint64_t)T)].get(sk, h >> 8);
                 if (r < 0) return;
                 std::atomic<uint64_t> &slot = best[(size_t)r];
                 uint64_t cur = slot.load(std::memory_order_relaxed);
