@@ -25,8 +25,9 @@
 //  * a lane expands its 32 bits of an item to 32 nibbles (16 bytes), the
 //    operand layout of the MFMA: bit 4k + t goes to nibble k of dword t.
 //    The 128 row items are shared by the 4 waves: each expands 2 of the 8
-//    row fragments into an LDS panel (double buffered, one barrier per
-//    step); the 64 column items of a wave stay in registers;
+//    row fragments into an LDS panel two steps ahead (four panels in
+//    rotation, one barrier per two steps); the 64 column items of a wave
+//    stay in registers, expanded one step ahead;
 //  * the words of the next 512 instances load during the current ones.
 #include <algorithm>
 #include <cmath>
@@ -87,28 +88,19 @@ __device__ __forceinline__ Words load_words(const uint64_t *const (&pa)[2],
     return x;
 }
 
-// Expansion of one step's operands: this wave's 2 row fragments into the
-// panel, its 4 column fragments into registers.
-template <int H>
-__device__ __forceinline__ void expand_step(const Words &x, const uint4 (&ma)[2],
-                                            const uint4 (&mb)[kGK], v4i (*panel)[64], int wave,
-                                            int lane, v4i (&b)[kGK]) {
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-        panel[2 * wave + i][lane] = expand32(bits_of<H>(x.a[i]) & bits_of<H>(ma[i]));
-#pragma unroll
-    for (int j = 0; j < kGK; ++j) b[j] = expand32(bits_of<H>(x.b[j]) & bits_of<H>(mb[j]));
-}
-
 // One step: the 8 x 4 MFMAs of the current operands (row fragments from
-// `cur_panel`, column fragments `b`) with the next step's expansions
-// (operands of step HN of the words `xn`) interleaved between the MFMA rows,
-// so a wave's VALU work overlaps its own matrix-core work; then the barrier
-// that publishes the next panel.
-template <int HN>
-__device__ __forceinline__ void gram_step(const Words &xn, const uint4 (&ma)[2],
+// `cur_panel`, column fragments `b`) with expansions interleaved between the
+// MFMA rows, so a wave's VALU work overlaps its own matrix-core work: this
+// wave's row fragments of the step two ahead (words `xr`, dword HR) into
+// `far_panel`, its column fragments of the next step (words `xc`, dword HC)
+// into `nb`.  Four panels rotate, so a barrier is needed after every
+// second step only (SYNC): the panel a step reads was written two steps
+// earlier, before the previous barrier, and the one it writes was last
+// read two steps earlier, also before it.
+template <int HR, int HC, bool SYNC>
+__device__ __forceinline__ void gram_step(const Words &xr, const Words &xc, const uint4 (&ma)[2],
                                           const uint4 (&mb)[kGK], v4i (*cur_panel)[64],
-                                          v4i (*next_panel)[64], int wave, int lane,
+                                          v4i (*far_panel)[64], int wave, int lane,
                                           bool active, const v4i (&b)[kGK], v4i (&nb)[kGK],
                                           v4f (&acc)[kGR][kGK]) {
     if (active) {
@@ -119,15 +111,19 @@ __device__ __forceinline__ void gram_step(const Words &xn, const uint4 (&ma)[2],
             for (int j = 0; j < kGK; ++j)
                 acc[i][j] = mfma_fp4(a, b[j], acc[i][j]);
             if (i < 2)
-                next_panel[2 * wave + i][lane] =
-                    expand32(bits_of<HN>(xn.a[i]) & bits_of<HN>(ma[i]));
+                far_panel[2 * wave + i][lane] =
+                    expand32(bits_of<HR>(xr.a[i]) & bits_of<HR>(ma[i]));
             else if (i < 2 + kGK)
-                nb[i - 2] = expand32(bits_of<HN>(xn.b[i - 2]) & bits_of<HN>(mb[i - 2]));
+                nb[i - 2] = expand32(bits_of<HC>(xc.b[i - 2]) & bits_of<HC>(mb[i - 2]));
         }
     } else {
-        expand_step<HN>(xn, ma, mb, next_panel, wave, lane, nb);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+            far_panel[2 * wave + i][lane] = expand32(bits_of<HR>(xr.a[i]) & bits_of<HR>(ma[i]));
+#pragma unroll
+        for (int j = 0; j < kGK; ++j) nb[j] = expand32(bits_of<HC>(xc.b[j]) & bits_of<HC>(mb[j]));
     }
-    __syncthreads();  // the next panel is complete; the current one is free
+    if (SYNC) __syncthreads();
 }
 
 __global__ __launch_bounds__(256, 2) void k_gram(const uint64_t *__restrict__ bits, int64_t words,
@@ -135,7 +131,7 @@ __global__ __launch_bounds__(256, 2) void k_gram(const uint64_t *__restrict__ bi
                                                  const int32_t *__restrict__ rowidx, int32_t nrb,
                                                  int32_t ncb, int32_t npairs, int32_t splits,
                                                  int32_t *__restrict__ C, int32_t ldc) {
-    __shared__ v4i panel[2][kGR][64];  // row fragments of two steps, lane-major
+    __shared__ v4i panel[4][kGR][64];  // row fragments of four steps, lane-major
     const int32_t p = (int32_t)(blockIdx.x % (uint32_t)npairs);
     const int32_t sp = (int32_t)(blockIdx.x / (uint32_t)npairs);
     // pair index -> (I, J): row block I meets the upper triangle from column
@@ -182,14 +178,21 @@ __global__ __launch_bounds__(256, 2) void k_gram(const uint64_t *__restrict__ bi
         const int64_t last = w1 - kGS;
         Words cur = load_words(pa, pb, w0);
         v4i b[kGK], nb[kGK];
-        expand_step<0>(cur, ma, mb, panel[0], wave, lane, b);
+        // the row fragments of steps 0 and 1, the column fragments of step 0
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            panel[0][2 * wave + i][lane] = expand32(bits_of<0>(cur.a[i]) & bits_of<0>(ma[i]));
+            panel[1][2 * wave + i][lane] = expand32(bits_of<1>(cur.a[i]) & bits_of<1>(ma[i]));
+        }
+#pragma unroll
+        for (int j = 0; j < kGK; ++j) b[j] = expand32(bits_of<0>(cur.b[j]) & bits_of<0>(mb[j]));
         __syncthreads();
         for (int64_t w = w0; w < w1; w += kGS) {
             const Words nxt = load_words(pa, pb, w + kGS < last ? w + kGS : last);
-            gram_step<1>(cur, ma, mb, panel[0], panel[1], wave, lane, active, b, nb, acc);
-            gram_step<2>(cur, ma, mb, panel[1], panel[0], wave, lane, active, nb, b, acc);
-            gram_step<3>(cur, ma, mb, panel[0], panel[1], wave, lane, active, b, nb, acc);
-            gram_step<0>(nxt, ma, mb, panel[1], panel[0], wave, lane, active, nb, b, acc);
+            gram_step<2, 1, false>(cur, cur, ma, mb, panel[0], panel[2], wave, lane, active, b, nb, acc);
+            gram_step<3, 2, true>(cur, cur, ma, mb, panel[1], panel[3], wave, lane, active, nb, b, acc);
+            gram_step<0, 3, false>(nxt, cur, ma, mb, panel[2], panel[0], wave, lane, active, b, nb, acc);
+            gram_step<1, 0, true>(nxt, nxt, ma, mb, panel[3], panel[1], wave, lane, active, nb, b, acc);
             cur = nxt;
         }
     }
