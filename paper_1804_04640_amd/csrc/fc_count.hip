@@ -1540,7 +1540,8 @@ static int64_t derive_plan(const fc_db *db, const int32_t *vars_flat, const int6
                 c *= db->arity[x];
                 if (c > INT32_MAX) c = INT32_MAX;
             }
-            std::sort(v, v + k);
+            for (int64_t a = 1; a < k; ++a)  // insertion sort of at most 8 bytes
+                for (int64_t b = a; b > 0 && v[b - 1] > v[b]; --b) std::swap(v[b - 1], v[b]);
             uint64_t kv = 0;
             for (int64_t a = 0; a < k; ++a) kv = (kv << 8) | v[a];
             key[(size_t)i] = kv;
