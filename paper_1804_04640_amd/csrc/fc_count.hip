@@ -1457,37 +1457,43 @@ inline uint64_t mix64(uint64_t z) {
 }
 
 // One partition of an open-addressing map from a variable-set key (never
-// 0) to a query index, keeping the entry that `better` prefers.
+// 0) to a query index, keeping the entry that `better` prefers.  Key and
+// value share a 16-byte slot, so a probe touches one cache line.
 struct SetMap {
-    std::vector<uint64_t> keys;
-    std::vector<int32_t> vals;
+    struct Slot {
+        uint64_t key;
+        int32_t val;
+        int32_t pad;
+    };
+    std::vector<Slot> slots;
     uint64_t mask = 0;
     void init(size_t entries) {
         size_t cap = 16;
         while (cap < 2 * entries) cap <<= 1;
-        keys.assign(cap, 0);
-        vals.assign(cap, -1);
+        slots.assign(cap, Slot{0, -1, 0});
         mask = cap - 1;
     }
     template <typename Better>
     void put(uint64_t key, uint64_t h, int32_t v, Better better) {
         for (uint64_t i = h & mask;; i = (i + 1) & mask) {
-            if (keys[i] == 0) {
-                keys[i] = key;
-                vals[i] = v;
+            Slot &e = slots[i];
+            if (e.key == 0) {
+                e.key = key;
+                e.val = v;
                 return;
             }
-            if (keys[i] == key) {
-                if (better(v, vals[i])) vals[i] = v;
+            if (e.key == key) {
+                if (better(v, e.val)) e.val = v;
                 return;
             }
         }
     }
     int32_t get(uint64_t key, uint64_t h) const {
-        if (keys.empty()) return -1;
+        if (slots.empty()) return -1;
         for (uint64_t i = h & mask;; i = (i + 1) & mask) {
-            if (keys[i] == key) return vals[i];
-            if (keys[i] == 0) return -1;
+            const Slot &e = slots[i];
+            if (e.key == key) return e.val;
+            if (e.key == 0) return -1;
         }
     }
 };
@@ -1723,7 +1729,7 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
     const bool gram_allowed = forced == FC_STRAT_AUTO && db->d_bits && db->m > 0;
     unsigned hw = std::thread::hardware_concurrency();
     int64_t T = std::min<int64_t>(std::max<unsigned>(1u, std::min(16u, hw ? hw : 1u)),
-                                  std::max<int64_t>(1, nq / 32768));
+                                  std::max<int64_t>(1, nq / 4096));  // workers persist: cheap
     std::vector<RangeStat> R((size_t)T);
     for (int64_t t = 0; t < T; ++t) {
         R[(size_t)t].lo = nq * t / T;
