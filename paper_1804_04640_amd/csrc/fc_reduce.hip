@@ -128,8 +128,11 @@ __global__ __launch_bounds__(256) void k_reduce(const QDesc *__restrict__ descs,
                                                 uint32_t reducers, float ess,
                                                 float *__restrict__ scores,
                                                 float *__restrict__ err) {
-    const int lane = threadIdx.x & 63;
-    const int64_t di = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    // R(z) of BDeu's small arguments, per wave: z = n + a_jk and z = n + a_j
+    // for n = 0..7, each computed once by one lane exactly as a cell would
+    __shared__ float rtab[4][2][8], mtab[4][2][8];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t di = (int64_t)blockIdx.x * 4 + wv;
     if (di >= nd) return;
     const QDesc &d = descs[di];
     const int32_t child = d.var[d.k - 1];
@@ -156,9 +159,21 @@ __global__ __launch_bounds__(256) void k_reduce(const QDesc *__restrict__ descs,
         D0 = -logf((float)r) + (lgammaf(1.0f + a1) - lgammaf(1.0f + a2));
     else
         D0 = lgammaf(a1) - G2;
+    if (want_bd && lane < 16) {
+        const float z = (float)(lane & 7) + ((lane < 8) ? a2 : a1);
+        float rm;
+        const float rz = stirling_rem(z, rm);
+        rtab[wv][lane >> 3][lane & 7] = rz;
+        mtab[wv][lane >> 3][lane & 7] = rm;
+    }
+    // the 64 lanes of a wave run in lockstep: the tables are complete here
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const float c3 = kHalfLn2Pi - G2;
     const float c3mag = kHalfLn2Pi + fabsf(G2);
     const float fm = (float)m;
+    const float inv_m = 1.0f / fm;
 
     Acc ll, bd, mi;
     for (int64_t j = lane; j < q; j += 64) {
@@ -171,24 +186,30 @@ __global__ __launch_bounds__(256) void k_reduce(const QDesc *__restrict__ descs,
             kc += v > 0;
         }
         if (nj == 0) continue;
-        float Z = 0.f, lnZ = 0.f;
+        float Z = 0.f, lnZ = 0.f, invZ = 0.f;
         if (want_bd) {
             Z = (float)nj + a1;
             lnZ = logf(Z);
+            invZ = 1.0f / Z;
             float t1 = -((float)(r - kc) * a2 + 0.5f * (float)(kc - 1)) * lnZ;
             bd.add(t1);
             bd.add((float)(r - kc) * a2);
             bd.add((float)(kc - 1) * c3, (float)(kc - 1) * c3mag);
             bd.add(D0, fabsf(D0) + 2.0f);
-            float rm;
-            float rZ = stirling_rem(Z, rm);
+            float rm, rZ;
+            if (nj < 8) {
+                rZ = rtab[wv][1][nj];
+                rm = mtab[wv][1][nj];
+            } else {
+                rZ = stirling_rem(Z, rm);
+            }
             bd.add(-rZ, rm);
         }
         for (int32_t k = 0; k < r; ++k) {
             const int64_t n = row[k];
             if (want_mi && nk[k] > 0) {
                 const int64_t den = nj * (int64_t)nk[k];
-                const float e = (float)den / fm;
+                const float e = (float)den * inv_m;
                 if (n == 0) {
                     mi.add(e);
                 } else {
@@ -205,10 +226,15 @@ __global__ __launch_bounds__(256) void k_reduce(const QDesc *__restrict__ descs,
             if (want_bd) {
                 const float zk = (float)n + a2;
                 const float dz = (float)(nj - n) + da;  // Z - z_k
-                const float lr = (dz < 0.5f * Z) ? log1pf(-dz / Z) : logf(zk / Z);
+                const float lr = (dz < 0.5f * Z) ? log1pf(-dz * invZ) : logf(zk * invZ);
                 bd.add(((float)n + (a2 - 0.5f)) * lr);
-                float rm;
-                float rk = stirling_rem(zk, rm);
+                float rm, rk;
+                if (n < 8) {
+                    rk = rtab[wv][0][n];
+                    rm = mtab[wv][0][n];
+                } else {
+                    rk = stirling_rem(zk, rm);
+                }
                 bd.add(rk, rm);
             }
         }
