@@ -633,18 +633,28 @@ __global__ void k_msd_clear(uint32_t *__restrict__ f, int64_t n4) {
 __global__ __launch_bounds__(kMsdThreads) void k_scan_sums(const uint8_t *__restrict__ f,
                                                            int64_t n,
                                                            uint32_t *__restrict__ bsum) {
-    __shared__ uint32_t part[kMsdThreads];
-    const int64_t a = (int64_t)blockIdx.x * kScanBlock;
+    // 16 flags (0 or 1 each) per thread in one 16-byte load: the flag array
+    // is zero up to a multiple of 16 bytes; a word's four flags sum in its
+    // top byte after a multiply by 0x01010101
+    static_assert(kScanBlock == kMsdThreads * 16, "one 16-byte load per thread");
+    __shared__ uint32_t part[kMsdThreads / 64];
+    const int64_t p = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * 16;
     uint32_t s = 0;
-    for (int64_t i = a + threadIdx.x; i < min(n, a + (int64_t)kScanBlock); i += kMsdThreads)
-        s += f[i];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = kMsdThreads / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < (unsigned)o) part[threadIdx.x] += part[threadIdx.x + o];
-        __syncthreads();
+    if (p < n) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(f + p);
+        s = ((v.x * 0x01010101u) >> 24) + ((v.y * 0x01010101u) >> 24) +
+            ((v.z * 0x01010101u) >> 24) + ((v.w * 0x01010101u) >> 24);
     }
-    if (threadIdx.x == 0) bsum[blockIdx.x] = part[0];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int w = 0; w < kMsdThreads / 64; ++w) t += part[w];
+        bsum[blockIdx.x] = t;
+    }
 }
 
 __global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *bsum, int64_t nb, MCtl *ctl) {
@@ -740,7 +750,7 @@ size_t carve_msd(char *base, int64_t nk, size_t kb, MsdScratch *S) {
     s.mid = (uint64_t *)take(sizeof(uint64_t) * (size_t)s.mid_cap);
     s.big_cap = nk / (kLeafKeys + 1) + 1;
     s.bigq = (uint64_t *)take(sizeof(uint64_t) * (size_t)s.big_cap);
-    s.flag = (uint8_t *)take((size_t)((nk + 3) / 4 * 4));
+    s.flag = (uint8_t *)take((size_t)((nk + 15) / 16 * 16));  // whole 16-byte loads
     s.rc = (uint32_t *)take(sizeof(uint32_t) * (size_t)nk);
     s.rk = take(kb * (size_t)nk);
     s.bsum = (uint32_t *)take(sizeof(uint32_t) * (size_t)s.nb);
@@ -789,7 +799,7 @@ int msd_sort_rle(const fc_db *db, K *keys, K *alt, int64_t nk, unsigned end_bit,
     K *rk = (K *)S.rk;
     hipLaunchKernelGGL(k_msd_init, dim3(1), dim3(256), 0, s, S.ctl, S.segs[0], S.counts[0],
                        top_given ? (const uint32_t *)S.top : nullptr, nk);
-    const int64_t n4 = (nk + 3) / 4;
+    const int64_t n4 = (nk + 15) / 16 * 4;  // flag words, to a multiple of 16 bytes
     hipLaunchKernelGGL(k_msd_clear, dim3((unsigned)std::min<int64_t>((n4 + 255) / 256, 8 * cus)),
                        dim3(256), 0, s, (uint32_t *)S.flag, n4);
     FC_HIP(hipGetLastError());
