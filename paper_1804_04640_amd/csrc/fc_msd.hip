@@ -180,16 +180,25 @@ __global__ __launch_bounds__(1024) void k_msd_tiles(MSeg *segs, MCtl *ctl, int n
 }
 
 // Moves every key of the level's segments to its bucket (order within a
-// bucket is free: the leaves sort it).  Workgroups stride over the tiles.
-template <typename K>
+// bucket is free: the leaves sort it).  Workgroups stride over the tiles;
+// a tile's keys are ranked per bucket in LDS and take one cursor atomic per
+// bucket.  STAGE: they are staged in LDS in bucket order, and each bucket's
+// keys leave as one contiguous run (neighbouring threads, neighbouring
+// addresses); this pays below the first level, where a tile's keys spread
+// over many buckets, and not at the first, where the top digit (mostly the
+// query) sends a tile's keys to a few.
+template <typename K, bool STAGE>
 __global__ __launch_bounds__(kMsdThreads) void k_msd_scatter(const K *__restrict__ in,
                                                              K *__restrict__ out,
                                                              const MSeg *__restrict__ segs,
                                                              const MCtl *__restrict__ ctl, int cur,
                                                              int lo, int width,
                                                              uint32_t *__restrict__ cursor) {
-    __shared__ uint32_t h[256], base[256];
+    __shared__ uint32_t h[256], base[256], tstart[256];
+    __shared__ uint32_t wsum[kMsdThreads / 64];
+    __shared__ K stage[STAGE ? kTileKeys : 1];
     constexpr int E = kTileKeys / kMsdThreads;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t nt = ctl->tiles[cur];
     const int32_t ns = ctl->nseg[cur];
     for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
@@ -210,13 +219,42 @@ __global__ __launch_bounds__(kMsdThreads) void k_msd_scatter(const K *__restrict
             }
         }
         __syncthreads();
+        // the tile's bucket starts (exclusive scan of h, one bucket per
+        // thread) and the buckets' places in the output
         const uint32_t c = h[threadIdx.x];
+        uint32_t incl = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t x = __shfl_up(incl, o);
+            if (lane >= o) incl += x;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        uint32_t before = 0;
+#pragma unroll
+        for (int w = 0; w < kMsdThreads / 64; ++w) before += w < wave ? wsum[w] : 0u;
+        tstart[threadIdx.x] = before + incl - c;
         base[threadIdx.x] = c ? atomicAdd(&cursor[(int64_t)s * 256 + threadIdx.x], c) : 0u;
         __syncthreads();
+        if (STAGE) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int64_t p = a + threadIdx.x + (int64_t)e * kMsdThreads;
-            if (p < b) out[base[digit_of((uint64_t)key[e], lo, width)] + rank[e]] = key[e];
+            for (int e = 0; e < E; ++e) {
+                const int64_t p = a + threadIdx.x + (int64_t)e * kMsdThreads;
+                if (p < b) stage[tstart[digit_of((uint64_t)key[e], lo, width)] + rank[e]] = key[e];
+            }
+            __syncthreads();
+            const int32_t n = (int32_t)(b - a);
+            for (int32_t j = threadIdx.x; j < n; j += kMsdThreads) {
+                const K k = stage[j];
+                const uint32_t d = digit_of((uint64_t)k, lo, width);
+                out[base[d] + ((uint32_t)j - tstart[d])] = k;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int64_t p = a + threadIdx.x + (int64_t)e * kMsdThreads;
+                if (p < b) out[base[digit_of((uint64_t)key[e], lo, width)] + rank[e]] = key[e];
+            }
         }
         __syncthreads();
     }
@@ -828,8 +866,12 @@ int msd_sort_rle(const fc_db *db, K *keys, K *alt, int64_t nk, unsigned end_bit,
                                S.counts[cur ^ 1], S.start, S.cursor, S.segs[cur ^ 1]);
             hipLaunchKernelGGL(k_msd_tiles, dim3(1), dim3(1024), 0, s, S.segs[cur ^ 1], S.ctl,
                                cur ^ 1);
-            hipLaunchKernelGGL(k_msd_scatter<K>, dim3((unsigned)gt), dim3(kMsdThreads), 0, s, in,
-                               out, S.segs[cur], S.ctl, cur, lo, width, S.cursor);
+            if (l == 0)
+                hipLaunchKernelGGL((k_msd_scatter<K, false>), dim3((unsigned)gt), dim3(kMsdThreads),
+                                   0, s, in, out, S.segs[cur], S.ctl, cur, lo, width, S.cursor);
+            else
+                hipLaunchKernelGGL((k_msd_scatter<K, true>), dim3((unsigned)gt), dim3(kMsdThreads),
+                                   0, s, in, out, S.segs[cur], S.ctl, cur, lo, width, S.cursor);
             hipLaunchKernelGGL(k_msd_tiny<K>,
                                dim3((unsigned)std::min<int64_t>((nc + kMsdThreads - 1) / kMsdThreads,
                                                                 8 * (int64_t)cus)),
