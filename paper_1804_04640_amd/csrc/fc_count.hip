@@ -459,6 +459,14 @@ __device__ __forceinline__ uint32_t pk_mad_u16(uint32_t a, uint32_t b, uint32_t 
     return __builtin_bit_cast(uint32_t, (u16x2)(x * y + z));
 }
 
+// Each 16-bit half shifted right by S (one packed shift): by 12 it leaves a
+// half's top nibble alone, with no mask.
+template <int S>
+__device__ __forceinline__ uint32_t pk_shr16(uint32_t a) {
+    const u16x2 x = __builtin_bit_cast(u16x2, a);
+    return __builtin_bit_cast(uint32_t, (u16x2)(x >> (unsigned short)S));
+}
+
 template <int K>
 __device__ __forceinline__ void hist16_body(const uint8_t *__restrict__ cols, int64_t pitch,
                                             const uint8_t *__restrict__ arity, const QDesc &q,
@@ -749,7 +757,7 @@ __device__ __forceinline__ void hist16n_body(const uint8_t *__restrict__ nib, in
                     a3 = pk_mad_u16(w8 & 0x00F000F0u, sq[t], a3);
                 } else {
                     a1 = pk_mad_u16((w >> 4) & 0x000F000Fu, sq[t], a1);
-                    a3 = pk_mad_u16((w >> 12) & 0x000F000Fu, sq[t], a3);
+                    a3 = pk_mad_u16(pk_shr16<12>(w), sq[t], a3);
                 }
             }
             atomicAdd(reinterpret_cast<uint32_t *>(base + (a0 & 0xFFFFu)), 1u);
