@@ -28,6 +28,7 @@
 #include <atomic>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -1511,6 +1512,21 @@ struct SetMap {
 // derived queries.  Needs at most 255 variables (a key packs the sorted
 // variables + 1 as bytes); any malformed query disables derivation, and
 // validation reports it.
+// The planner's working arrays, kept per host thread between calls so that
+// a steady stream of batches reuses their pages instead of faulting in new
+// ones on every call.
+struct DeriveScratch {
+    static constexpr int kFiltBits = 20;
+    std::vector<uint64_t> key;
+    std::vector<int64_t> cells;
+    std::vector<uint8_t> kk;
+    std::vector<std::vector<std::pair<uint64_t, int32_t>>> own;
+    std::vector<SetMap> m0;
+    std::unique_ptr<std::atomic<uint64_t>[]> filt{new std::atomic<uint64_t>[(size_t)1 << (kFiltBits - 6)]};
+    std::unique_ptr<std::atomic<uint64_t>[]> best;
+    size_t best_cap = 0;
+};
+
 static int64_t derive_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
                            int64_t nq, std::vector<int32_t> &src) {
     src.clear();
@@ -1518,24 +1534,38 @@ static int64_t derive_plan(const fc_db *db, const int32_t *vars_flat, const int6
     unsigned hw = std::thread::hardware_concurrency();
     const int T = (int)std::min<int64_t>(std::max<unsigned>(1u, std::min(16u, hw ? hw : 1u)),
                                          std::max<int64_t>(1, nq / 2048));
-    std::vector<uint64_t> key((size_t)nq, 0);
-    std::vector<int64_t> cells((size_t)nq, 0);
-    std::vector<uint8_t> kk((size_t)nq, 0);
+    static thread_local DeriveScratch W;
+    W.key.resize((size_t)nq);
+    W.cells.resize((size_t)nq);
+    W.kk.resize((size_t)nq);
+    if (W.best_cap < (size_t)nq) {
+        W.best.reset(new std::atomic<uint64_t>[(size_t)nq]);
+        W.best_cap = (size_t)nq;
+    }
+    uint64_t *key = W.key.data();
+    int64_t *cells = W.cells.data();
+    uint8_t *kk = W.kk.data();
+    std::atomic<uint64_t> *best = W.best.get();
     // per (range, owner partition): (own key, query) of queries of 3+ variables
-    std::vector<std::vector<std::pair<uint64_t, int32_t>>> own((size_t)T * T);
+    auto &own = W.own;
+    own.resize((size_t)T * T);
+    for (auto &v : own) v.clear();
     std::atomic<bool> bad(false);
     // a bit per hashed variable set of 3 or 4 variables present in the batch
     // (2^20 bits): most subsets of the larger queries are absent and are
     // turned away here without a probe of the map
-    constexpr int kFiltBits = 20;
-    std::vector<std::atomic<uint64_t>> filt((size_t)1 << (kFiltBits - 6));
-    for (auto &x : filt) x.store(0, std::memory_order_relaxed);
+    constexpr int kFiltBits = DeriveScratch::kFiltBits;
+    std::atomic<uint64_t> *filt = W.filt.get();
+    for (size_t i = 0; i < ((size_t)1 << (kFiltBits - 6)); ++i) filt[i].store(0, std::memory_order_relaxed);
     auto filt_bit = [](uint64_t h) { return h >> (64 - kFiltBits); };
+    // owner partition of a hashed key: its high half scaled to [0, T), no division
+    auto part_of = [T](uint64_t h) { return (size_t)(((h >> 32) * (uint64_t)T) >> 32); };
     auto run = [&](auto f) { parallel_for(T, [&](int t) { f(t); }); };
     // keys (sorted variables + 1 as bytes), cells
     run([&](int t) {
         const int64_t lo = nq * t / T, hi = nq * (t + 1) / T;
         for (int o = 0; o < T; ++o) own[(size_t)t * T + o].reserve((size_t)((hi - lo) / T + 16));
+        for (int64_t i = lo; i < hi; ++i) best[i].store(~0ull, std::memory_order_relaxed);
         for (int64_t i = lo; i < hi; ++i) {
             const int64_t k = var_off[i + 1] - var_off[i];
             if (k < 1 || k > FC_MAX_VARS) {
@@ -1563,7 +1593,7 @@ static int64_t derive_plan(const fc_db *db, const int32_t *vars_flat, const int6
             kk[(size_t)i] = (uint8_t)k;
             if (k >= 3) {
                 const uint64_t h = mix64(kv);
-                own[(size_t)t * T + (size_t)(h % (uint64_t)T)].push_back({kv, (int32_t)i});
+                own[(size_t)t * T + part_of(h)].push_back({kv, (int32_t)i});
                 if (k <= 4) {
                     const uint64_t b = filt_bit(h);
                     filt[(size_t)(b >> 6)].fetch_or(1ull << (b & 63), std::memory_order_relaxed);
@@ -1573,7 +1603,8 @@ static int64_t derive_plan(const fc_db *db, const int32_t *vars_flat, const int6
     });
     if (bad) return 0;
     // representatives: every variable set of 3+ variables to its lowest query
-    std::vector<SetMap> m0((size_t)T);
+    auto &m0 = W.m0;
+    m0.resize((size_t)T);
     run([&](int o) {
         size_t n0 = 0;
         for (int t = 0; t < T; ++t) n0 += own[(size_t)t * T + o].size();
@@ -1585,14 +1616,12 @@ static int64_t derive_plan(const fc_db *db, const int32_t *vars_flat, const int6
     });
     auto find = [&](uint64_t kv) {
         const uint64_t h = mix64(kv);
-        return m0[(size_t)(h % (uint64_t)T)].get(kv, h >> 8);
+        return m0[part_of(h)].get(kv, h >> 8);
     };
     // the smallest superset (fewest cells, then lowest index) of every
     // represented set of 3 or 4 variables: each query of 4+ variables looks
     // its sorted 3- and 4-variable subsets up and offers itself to those
     // that some query has
-    std::vector<std::atomic<uint64_t>> best((size_t)nq);
-    for (auto &x : best) x.store(~0ull, std::memory_order_relaxed);
     run([&](int t) {
         const int64_t lo = nq * t / T, hi = nq * (t + 1) / T;
         for (int64_t i = lo; i < hi; ++i) {
@@ -1606,7 +1635,7 @@ static int64_t derive_plan(const fc_db *db, const int32_t *vars_flat, const int6
                 const uint64_t bit = filt_bit(h);
                 if (!((filt[(size_t)(bit >> 6)].load(std::memory_order_relaxed) >> (bit & 63)) & 1))
                     return;
-                const int32_t r = m0[(size_t)(h % (uint64_t)T)].get(sk, h >> 8);
+                const int32_t r = m0[part_of(h)].get(sk, h >> 8);
                 if (r < 0) return;
                 std::atomic<uint64_t> &slot = best[(size_t)r];
                 uint64_t cur = slot.load(std::memory_order_relaxed);
