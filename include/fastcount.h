@@ -451,6 +451,13 @@ typedef struct fc_tuning {
                                   partition (columns read once, keys moved
                                   to their parts); 0: by key windows, each
                                   a scan of the columns.  Same tables.     */
+    int32_t row_sweep;         /* 1: the histogram workgroups resident on an
+                                  XCD start their row chunks where the
+                                  workgroups they replace ended, so they
+                                  read the same rows at the same time and
+                                  share them in the XCD's L2; 0: every
+                                  workgroup starts at its chunk's first row.
+                                  Same tables.                             */
 } fc_tuning;
 
 /*
@@ -471,8 +478,9 @@ int fc_db_set_tuning(fc_db *db, const fc_tuning *t);
 /*
  * Autotuner: times a representative batch (vars_flat/var_off as in
  * fc_count_batch) on the device with every candidate -- Bitmap against
- * histogram per (k, table-size bucket), then the row-chunk sizes -- and
- * installs the fastest choices in the handle.  Synchronises `stream`.
+ * histogram per (k, table-size bucket), the row-chunk sizes, then row
+ * sweeps on or off -- and installs the fastest choices in the handle.
+ * Synchronises `stream`.
  */
 int fc_autotune(fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
                 int64_t nq, void *stream);

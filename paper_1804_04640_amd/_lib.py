@@ -54,7 +54,8 @@ class fc_tuning(ctypes.Structure):
                 ("bitmap_words", ctypes.c_int32), ("persistent_max_queries", ctypes.c_int32),
                 ("bitmap_cells", (ctypes.c_uint8 * 6) * FC_MAX_VARS),
                 ("packed_columns", ctypes.c_int32), ("bitmap_order", ctypes.c_int32),
-                ("derive_tables", ctypes.c_int32), ("one_pass_partition", ctypes.c_int32)]
+                ("derive_tables", ctypes.c_int32), ("one_pass_partition", ctypes.c_int32),
+                ("row_sweep", ctypes.c_int32)]
 
     def to_dict(self):
         return {"chunk_rows": int(self.chunk_rows), "bitmap_chunk_rows": int(self.bitmap_chunk_rows),
@@ -64,7 +65,8 @@ class fc_tuning(ctypes.Structure):
                 "packed_columns": int(self.packed_columns),
                 "bitmap_order": int(self.bitmap_order),
                 "derive_tables": int(self.derive_tables),
-                "one_pass_partition": int(self.one_pass_partition)}
+                "one_pass_partition": int(self.one_pass_partition),
+                "row_sweep": int(self.row_sweep)}
 
     @classmethod
     def from_dict(cls, d):
@@ -80,6 +82,7 @@ class fc_tuning(ctypes.Structure):
         t.bitmap_order = int(d.get("bitmap_order", 1))
         t.derive_tables = int(d.get("derive_tables", 1))
         t.one_pass_partition = int(d.get("one_pass_partition", 1))
+        t.row_sweep = int(d.get("row_sweep", 1))
         return t
 
 

@@ -28,6 +28,7 @@
 #include <atomic>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -460,8 +461,20 @@ __device__ __forceinline__ uint32_t pk_mad_u16(uint32_t a, uint32_t b, uint32_t 
     return __builtin_bit_cast(uint32_t, (u16x2)(x * y + z));
 }
 
-// Each 16-bit half shifted right by S (one packed shift): by 12 it leaves a
-// half's top nibble alone, with no mask.
+// Row order inside a chunk (a synchronized sweep): the chunk's steps are
+// taken cyclically from step (seq * n / sweep) mod n, where seq is the
+// workgroup's place in its XCD's dispatch order (blocks are dealt to the
+// XCDs round-robin) and sweep the number of workgroups one XCD holds at a
+// time.  A workgroup then starts where the one whose slot it takes ended,
+// so the workgroups resident on an XCD read nearly the same rows of the
+// columns at any moment and share them in that XCD's L2, instead of each
+// reading a different part of the chunk.  The rows counted are the same in
+// any order; sweep = 0 starts every workgroup at step 0.
+__device__ __forceinline__ uint32_t sweep_start(int64_t seq, uint32_t n, int32_t sweep) {
+    return sweep > 0 && n > 1 ? (uint32_t)(((uint64_t)seq * n / (uint32_t)sweep) % n) : 0u;
+}
+
+// Each 16-bit half shifted right by S (one packed shift).
 template <int S>
 __device__ __forceinline__ uint32_t pk_shr16(uint32_t a) {
     const u16x2 x = __builtin_bit_cast(u16x2, a);
@@ -473,7 +486,8 @@ __device__ __forceinline__ void hist16_body(const uint8_t *__restrict__ cols, in
                                             const uint8_t *__restrict__ arity, const QDesc &q,
                                             int32_t c, int32_t chunks, int32_t lds_words,
                                             int32_t pad_rows, int32_t *__restrict__ tables,
-                                            uint32_t *lds) {
+                                            uint32_t *lds, int64_t seq,
+                                            int32_t sweep) {
     const int32_t cells = q.cells;
     uint32_t sb[K];
     Col colp[K];
@@ -504,7 +518,11 @@ __device__ __forceinline__ void hist16_body(const uint8_t *__restrict__ cols, in
     const uint32_t init = ((threadIdx.x & (uint32_t)(B - 1)) * 4u) * 0x00010001u;
     char *base = reinterpret_cast<char *>(lds);
 
-    for (uint32_t row = (uint32_t)r0 + threadIdx.x * 16u; row < (uint32_t)r1; row += kBlock * 16u) {
+    const uint32_t nstep = (uint32_t)((r1 - r0 + kBlock * 16 - 1) / (kBlock * 16));
+    uint32_t it = sweep_start(seq, nstep, sweep);
+    for (uint32_t i = 0; i < nstep; ++i, it = it + 1 == nstep ? 0u : it + 1) {
+        const uint32_t row = (uint32_t)r0 + it * (kBlock * 16u) + threadIdx.x * 16u;
+        if (row >= (uint32_t)r1) continue;  // the chunk's ragged last step
         uint4 v[K];
 #pragma unroll
         for (int t = 0; t < K; ++t) v[t] = load16(colp[t], row);
@@ -551,7 +569,8 @@ template <int K, int B>
 __device__ __forceinline__ void hist8_body(const uint8_t *__restrict__ cols, int64_t pitch,
                                            const uint8_t *__restrict__ arity, const QDesc &q,
                                            int32_t c, int32_t chunks, int32_t pad_rows,
-                                           int32_t *__restrict__ tables, uint32_t *lds) {
+                                           int32_t *__restrict__ tables, uint32_t *lds, int64_t seq,
+                                            int32_t sweep) {
     const int32_t cells = q.cells;
     uint32_t sb[K];
     Col colp[K];
@@ -573,7 +592,11 @@ __device__ __forceinline__ void hist8_body(const uint8_t *__restrict__ cols, int
     const uint32_t slot = B == 64 ? (threadIdx.x & 63u) * 4u : (threadIdx.x & 31u) * 8u;
     char *base = reinterpret_cast<char *>(lds);
 
-    for (uint32_t row = (uint32_t)r0 + threadIdx.x * 16u; row < (uint32_t)r1; row += kBlock * 16u) {
+    const uint32_t nstep = (uint32_t)((r1 - r0 + kBlock * 16 - 1) / (kBlock * 16));
+    uint32_t it = sweep_start(seq, nstep, sweep);
+    for (uint32_t i = 0; i < nstep; ++i, it = it + 1 == nstep ? 0u : it + 1) {
+        const uint32_t row = (uint32_t)r0 + it * (kBlock * 16u) + threadIdx.x * 16u;
+        if (row >= (uint32_t)r1) continue;  // the chunk's ragged last step
         uint4 v[K];
 #pragma unroll
         for (int t = 0; t < K; ++t) v[t] = load16(colp[t], row);
@@ -606,12 +629,13 @@ __global__ __launch_bounds__(kBlock) void k_hist8(const uint8_t *__restrict__ co
                                                   const uint8_t *__restrict__ arity,
                                                   const QDesc *__restrict__ descs, int32_t nd,
                                                   int32_t chunks, int32_t pad_rows,
-                                                  int32_t *__restrict__ tables) {
+                                                  int32_t *__restrict__ tables, int32_t sweep) {
     constexpr int B = CAP <= 64 ? 64 : 32;
     __shared__ __attribute__((aligned(16))) uint32_t lds[CAP * B];
     int32_t di, c;
     map_block(blockIdx.x, nd, chunks, di, c);
-    hist8_body<K, B>(cols, pitch, arity, descs[di], c, chunks, pad_rows, tables, lds);
+    hist8_body<K, B>(cols, pitch, arity, descs[di], c, chunks, pad_rows, tables, lds,
+                     (int64_t)blockIdx.x / kXcds, sweep);
 }
 
 template <int K>
@@ -621,25 +645,29 @@ __global__ __launch_bounds__(kBlock) void k_hist16(const uint8_t *__restrict__ c
                                                    const QDesc *__restrict__ descs, int32_t nd,
                                                    int32_t chunks, int32_t lds_words,
                                                    int32_t pad_rows,
-                                                   int32_t *__restrict__ tables) {
+                                                   int32_t *__restrict__ tables, int32_t sweep) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     int32_t di, c;
     map_block(blockIdx.x, nd, chunks, di, c);
-    hist16_body<K>(cols, pitch, arity, descs[di], c, chunks, lds_words, pad_rows, tables, lds);
+    hist16_body<K>(cols, pitch, arity, descs[di], c, chunks, lds_words, pad_rows, tables, lds,
+                   (int64_t)blockIdx.x / kXcds, sweep);
 }
 
 // The same two histograms over the 4-bit packed columns (all arities at most
 // 16): half the bytes per instance.  A packed word holds 8 instances, two
 // per byte (low nibble first); each thread reads 32 instances per column.
 //
-// Byte keys (tables of at most 64 cells): the even and the odd nibbles of a
-// word, masked into bytes, give two chains of packed multiply-adds, four
-// keys each.
+// Byte keys (tables of at most 256 cells): the odd nibbles of a word, masked
+// into bytes, give one chain of packed multiply-adds (four keys); the whole
+// word gives another, P, whose halves hold even key + 16 x odd key (every
+// key is below 256, so the difference P - 16 x odd is exact mod 2^16) and
+// the even keys come from one more multiply-add per word.
 template <int K, int B>
 __device__ __forceinline__ void hist8n_body(const uint8_t *__restrict__ nib, int64_t pitch,
                                             const uint8_t *__restrict__ arity, const QDesc &q,
                                             int32_t c, int32_t chunks, int32_t pad_rows,
-                                            int32_t *__restrict__ tables, uint32_t *lds) {
+                                            int32_t *__restrict__ tables, uint32_t *lds, int64_t seq,
+                                            int32_t sweep) {
     const int32_t cells = q.cells;
     uint32_t sb[K];
     Col colp[K];
@@ -660,20 +688,27 @@ __device__ __forceinline__ void hist8n_body(const uint8_t *__restrict__ nib, int
     const int64_t r1 = (int64_t)(c + 1) * tiles / chunks * kTileRows;
     const uint32_t slot = B == 64 ? (threadIdx.x & 63u) * 4u : (threadIdx.x & 31u) * 8u;
     char *base = reinterpret_cast<char *>(lds);
+    uint32_t kMinus16 = 0xFFF0FFF0u;  // -16 in both halves, kept one multiply-add
+    asm volatile("" : "+v"(kMinus16));
 
-    for (uint32_t row = (uint32_t)r0 + threadIdx.x * 32u; row < (uint32_t)r1; row += kBlock * 32u) {
+    const uint32_t nstep = (uint32_t)((r1 - r0 + kBlock * 32 - 1) / (kBlock * 32));
+    uint32_t it = sweep_start(seq, nstep, sweep);
+    for (uint32_t i = 0; i < nstep; ++i, it = it + 1 == nstep ? 0u : it + 1) {
+        const uint32_t row = (uint32_t)r0 + it * (kBlock * 32u) + threadIdx.x * 32u;
+        if (row >= (uint32_t)r1) continue;  // the chunk's ragged last step
         uint4 v[K];
 #pragma unroll
         for (int t = 0; t < K; ++t) v[t] = load16(colp[t], row >> 1);
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
-            uint32_t ke = 0, ko = 0;  // bytes: keys of the even / odd instances
+            uint32_t pw = 0, ko = 0;  // whole words / bytes: keys of the odd instances
 #pragma unroll
             for (int t = 0; t < K; ++t) {
                 const uint32_t w = d == 0 ? v[t].x : d == 1 ? v[t].y : d == 2 ? v[t].z : v[t].w;
-                ke = pk_mad_u16(w & 0x0F0F0F0Fu, sb[t], ke);
+                pw = pk_mad_u16(w, sb[t], pw);
                 ko = pk_mad_u16((w >> 4) & 0x0F0F0F0Fu, sb[t], ko);
             }
+            const uint32_t ke = pk_mad_u16(ko, kMinus16, pw);  // bytes: keys of the even instances
             atomicAdd(reinterpret_cast<uint32_t *>(base + lds_addr<B>(ke, slot, 0x0c0c0400u)), 1u);
             atomicAdd(reinterpret_cast<uint32_t *>(base + lds_addr<B>(ke, slot, 0x0c0c0500u)), 1u);
             atomicAdd(reinterpret_cast<uint32_t *>(base + lds_addr<B>(ke, slot, 0x0c0c0600u)), 1u);
@@ -695,30 +730,36 @@ __global__ __launch_bounds__(kBlock) void k_hist8n(const uint8_t *__restrict__ n
                                                    const uint8_t *__restrict__ arity,
                                                    const QDesc *__restrict__ descs, int32_t nd,
                                                    int32_t chunks, int32_t pad_rows,
-                                                   int32_t *__restrict__ tables) {
+                                                   int32_t *__restrict__ tables, int32_t sweep) {
     constexpr int B = CAP <= 64 ? 64 : 32;
     __shared__ __attribute__((aligned(16))) uint32_t lds[CAP * B];
     int32_t di, c;
     map_block(blockIdx.x, nd, chunks, di, c);
-    hist8n_body<K, B>(nib, pitch, arity, descs[di], c, chunks, pad_rows, tables, lds);
+    hist8n_body<K, B>(nib, pitch, arity, descs[di], c, chunks, pad_rows, tables, lds,
+                      (int64_t)blockIdx.x / kXcds, sweep);
 }
 
 // Address keys (lane columns of B words per cell): the key of two instances
-// (nibbles i and i + 4 of a word) forms in the 16-bit halves of a register.
-// WIDE (B >= 4): nibble positions 1 and 3 of a half are masked in place,
-// worth 16 times their state, and use strides pre-divided by 16, which is
-// exact because a cell is 4 B >= 16 bytes wide; positions 2 and 3 come from
-// the word shifted by 8.  Otherwise every position is shifted down first.
-template <int K, bool WIDE>
+// (nibbles j and j + 4 of a word) forms in the 16-bit halves of a register.
+// No nibble is masked out: with u_j the word's 16-bit halves each shifted
+// right by 4j, the halves of u_j - 16 u_(j+1) are exactly nibbles j and
+// j + 4 (and u_3 holds nibbles 3 and 7 alone), so the sums
+// P_j = init_j + sum_t u_j(t) * stride_t give every key as
+// P_j - 16 P_(j+1) (and P_3 itself) in one packed multiply-add per word:
+// 3 shifts and 4 multiply-adds per column per 8 instances.  The starting
+// values init_j are chosen so that each difference leaves the lane's word
+// offset.
+template <int K>
 __device__ __forceinline__ void hist16n_body(const uint8_t *__restrict__ nib, int64_t pitch,
                                              const uint8_t *__restrict__ arity, const QDesc &q,
                                              int32_t c, int32_t chunks, int32_t lds_words,
                                              int32_t pad_rows, int32_t *__restrict__ tables,
-                                             uint32_t *lds) {
+                                             uint32_t *lds, int64_t seq,
+                                            int32_t sweep) {
     const int32_t cells = q.cells;
     int32_t B = lds_words / cells;
     B = B >= 64 ? 64 : B >= 32 ? 32 : B >= 16 ? 16 : B >= 8 ? 8 : B >= 4 ? 4 : B >= 2 ? 2 : 1;
-    uint32_t sa[K], sq[K];
+    uint32_t sa[K];
     Col colp[K];
     {
         uint32_t s = 1;
@@ -726,8 +767,6 @@ __device__ __forceinline__ void hist16n_body(const uint8_t *__restrict__ nib, in
         for (int t = K - 1; t >= 0; --t) {
             const int32_t v = q.var[t];
             sa[t] = (s * 4u * (uint32_t)B) * 0x00010001u;  // byte stride of a state
-            sq[t] = WIDE ? (s * (uint32_t)B / 4u) * 0x00010001u  // the same for 16 x state
-                         : sa[t];
             s *= arity[v];
             colp[t] = make_col(nib + (int64_t)v * (pitch / 2), pitch / 2);
         }
@@ -737,30 +776,39 @@ __device__ __forceinline__ void hist16n_body(const uint8_t *__restrict__ nib, in
     const int64_t tiles = q.tiles;
     const int64_t r0 = (int64_t)c * tiles / chunks * kTileRows;
     const int64_t r1 = (int64_t)(c + 1) * tiles / chunks * kTileRows;
-    const uint32_t init = ((threadIdx.x & (uint32_t)(B - 1)) * 4u) * 0x00010001u;
+    // init_3 = o, init_j = o + 16 init_(j+1) (mod 2^16), o the lane's byte offset
+    const uint32_t o = (threadIdx.x & (uint32_t)(B - 1)) * 4u;
+    const uint32_t i3 = o * 0x00010001u, i2 = ((o * 17u) & 0xFFFFu) * 0x00010001u,
+                   i1 = ((o * 273u) & 0xFFFFu) * 0x00010001u,
+                   i0 = ((o * 4369u) & 0xFFFFu) * 0x00010001u;
+    // -16 in both halves, hidden from the optimiser so that each difference
+    // stays one multiply-add instead of a shift and a subtraction
+    uint32_t kMinus16 = 0xFFF0FFF0u;
+    asm volatile("" : "+v"(kMinus16));
     char *base = reinterpret_cast<char *>(lds);
 
-    for (uint32_t row = (uint32_t)r0 + threadIdx.x * 32u; row < (uint32_t)r1; row += kBlock * 32u) {
+    const uint32_t nstep = (uint32_t)((r1 - r0 + kBlock * 32 - 1) / (kBlock * 32));
+    uint32_t it = sweep_start(seq, nstep, sweep);
+    for (uint32_t i = 0; i < nstep; ++i, it = it + 1 == nstep ? 0u : it + 1) {
+        const uint32_t row = (uint32_t)r0 + it * (kBlock * 32u) + threadIdx.x * 32u;
+        if (row >= (uint32_t)r1) continue;  // the chunk's ragged last step
         uint4 v[K];
 #pragma unroll
         for (int t = 0; t < K; ++t) v[t] = load16(colp[t], row >> 1);
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
-            uint32_t a0 = init, a1 = init, a2 = init, a3 = init;  // instances (0,4) .. (3,7)
+            uint32_t p0 = i0, p1 = i1, p2 = i2, p3 = i3;
 #pragma unroll
             for (int t = 0; t < K; ++t) {
                 const uint32_t w = d == 0 ? v[t].x : d == 1 ? v[t].y : d == 2 ? v[t].z : v[t].w;
-                const uint32_t w8 = w >> 8;
-                a0 = pk_mad_u16(w & 0x000F000Fu, sa[t], a0);
-                a2 = pk_mad_u16(w8 & 0x000F000Fu, sa[t], a2);
-                if (WIDE) {
-                    a1 = pk_mad_u16(w & 0x00F000F0u, sq[t], a1);
-                    a3 = pk_mad_u16(w8 & 0x00F000F0u, sq[t], a3);
-                } else {
-                    a1 = pk_mad_u16((w >> 4) & 0x000F000Fu, sq[t], a1);
-                    a3 = pk_mad_u16(pk_shr16<12>(w), sq[t], a3);
-                }
+                p0 = pk_mad_u16(w, sa[t], p0);
+                p1 = pk_mad_u16(pk_shr16<4>(w), sa[t], p1);
+                p2 = pk_mad_u16(pk_shr16<8>(w), sa[t], p2);
+                p3 = pk_mad_u16(pk_shr16<12>(w), sa[t], p3);
             }
+            // instances (0,4) .. (3,7)
+            const uint32_t a0 = pk_mad_u16(p1, kMinus16, p0), a1 = pk_mad_u16(p2, kMinus16, p1),
+                           a2 = pk_mad_u16(p3, kMinus16, p2), a3 = p3;
             atomicAdd(reinterpret_cast<uint32_t *>(base + (a0 & 0xFFFFu)), 1u);
             atomicAdd(reinterpret_cast<uint32_t *>(base + (a1 & 0xFFFFu)), 1u);
             atomicAdd(reinterpret_cast<uint32_t *>(base + (a2 & 0xFFFFu)), 1u);
@@ -776,19 +824,19 @@ __device__ __forceinline__ void hist16n_body(const uint8_t *__restrict__ nib, in
                tables + q.table_off);
 }
 
-template <int K, bool WIDE>
+template <int K>
 __global__ __launch_bounds__(kBlock) void k_hist16n(const uint8_t *__restrict__ nib,
                                                     int64_t pitch,
                                                     const uint8_t *__restrict__ arity,
                                                     const QDesc *__restrict__ descs, int32_t nd,
                                                     int32_t chunks, int32_t lds_words,
                                                     int32_t pad_rows,
-                                                    int32_t *__restrict__ tables) {
+                                                    int32_t *__restrict__ tables, int32_t sweep) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     int32_t di, c;
     map_block(blockIdx.x, nd, chunks, di, c);
-    hist16n_body<K, WIDE>(nib, pitch, arity, descs[di], c, chunks, lds_words, pad_rows, tables,
-                          lds);
+    hist16n_body<K>(nib, pitch, arity, descs[di], c, chunks, lds_words, pad_rows, tables, lds,
+                    (int64_t)blockIdx.x / kXcds, sweep);
 }
 
 // Bitmap count (Alg. 1) of one descriptor over one chunk of 64-row words.
@@ -949,13 +997,13 @@ __device__ __forceinline__ void persistent_case(int type, const uint8_t *cols, c
                                                 int32_t *tables, uint32_t *lds) {
     switch (type) {
         case PK_HIST8:
-            hist8_body<K, 64>(cols, pitch, arity, q, c, chunks, pad, tables, lds);
+            hist8_body<K, 64>(cols, pitch, arity, q, c, chunks, pad, tables, lds, 0, 0);
             break;
         case PK_HIST8N:
-            hist8n_body<K, 64>(nib, pitch, arity, q, c, chunks, pad, tables, lds);
+            hist8n_body<K, 64>(nib, pitch, arity, q, c, chunks, pad, tables, lds, 0, 0);
             break;
         case PK_HIST16:
-            hist16_body<K>(cols, pitch, arity, q, c, chunks, lds_words, pad, tables, lds);
+            hist16_body<K>(cols, pitch, arity, q, c, chunks, lds_words, pad, tables, lds, 0, 0);
             break;
         case PK_HIST_S:
             hist_body<K, true>(cols, pitch, arity, q, c, chunks, lds_words, pad, tables, lds);
@@ -1213,7 +1261,6 @@ struct Launch {
     int K;
     bool small;
     int32_t hk;       // histogram kernel: HK_HIST8(N), HK_HIST16(N) or HK_GENERIC
-    bool wide;        // every table of the group has lane columns of >= 4 words
     int64_t first;    // first descriptor
     int32_t count;    // descriptors
     int32_t chunks;
@@ -1256,7 +1303,6 @@ static const int32_t kClassLds[] = {16 * 64 * 4, 64 * 64 * 4, 256 * 32 * 4, 1024
                                     4096 * 2 * 4, 16383 * 4,  kHistMaxCells * 4 + 4};
 constexpr int kHist8Classes = 3;
 constexpr int kHist16Classes = 6;
-constexpr int kHist16nWide = 4;     // classes with lane columns of at least 4 words
 enum { HK_GENERIC = 0, HK_HIST16 = 1, HK_HIST8 = 2, HK_HIST16N = 3, HK_HIST8N = 4 };
 
 static int hist_class(int64_t cells) {
@@ -1982,7 +2028,6 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
                            : nib && cls < kHist16Classes    ? HK_HIST16N
                            : cls < kHist16Classes           ? HK_HIST16
                                                             : HK_GENERIC;
-                    L.wide = cls < kHist16nWide;
                     // algorithmic bytes: k per (query, instance) whichever
                     // column store or strategy the launch reads
                     L.lds_bytes = st == S_BITMAP ? (int32_t)(maxc * kBlock * 4) : kClassLds[cls];
@@ -1996,8 +2041,8 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
                                  L.lds_bytes <= 16 * 64 * 4   ? 16
                                  : L.lds_bytes <= 64 * 64 * 4 ? 64
                                                               : 256);
-                    else if (L.hk == HK_HIST16N)  // <K, lane columns of >= 4 words>
-                        snprintf(L.name, sizeof L.name, "k_hist16n<%d,%d>", K, L.wide ? 1 : 0);
+                    else if (L.hk == HK_HIST16N)
+                        snprintf(L.name, sizeof L.name, "k_hist16n<%d>", K);
                     else if (L.hk == HK_HIST16)
                         snprintf(L.name, sizeof L.name, "k_hist16<%d>", K);
                     else
@@ -2038,41 +2083,68 @@ static int build_plan(const fc_db *db, const int32_t *vars_flat, const int64_t *
 }
 
 // ------------------------------------------------------------------ launch
+// Workgroups of kernel f (dyn bytes of dynamic LDS) one XCD holds at a time:
+// the sweep argument of the histogram kernels (0 with row_sweep off).
+static int32_t sweep_of(const fc_db *db, const void *f, int32_t dyn) {
+    if (!db->tune.row_sweep) return 0;
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int32_t>, int32_t> per_cu;
+    int32_t nb = 0;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = per_cu.find({f, dyn});
+        if (it != per_cu.end()) {
+            nb = it->second;
+        } else {
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kBlock, (size_t)dyn) !=
+                hipSuccess) {
+                (void)hipGetLastError();
+                nb = 0;
+            }
+            per_cu[{f, dyn}] = nb;
+        }
+    }
+    return nb > 0 ? (int32_t)((int64_t)nb * db->cu_count / kXcds) : 0;
+}
+
 template <int K>
 static hipError_t launch_hist_k(const fc_db *db, const Launch &L, const QDesc *d,
                                 int32_t *tables, hipStream_t s) {
     const int64_t blocks = (int64_t)L.count * L.chunks;
     const int32_t pad = (int32_t)(db->m_pad - db->m);
+    const dim3 grid((unsigned)blocks), block(kBlock);
     if (L.hk == HK_HIST8N && L.lds_bytes <= 16 * 64 * 4)
-        hipLaunchKernelGGL((k_hist8n<K, 16>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                           db->d_nib, db->pitch, db->d_arity, d, L.count, L.chunks, pad, tables);
+        hipLaunchKernelGGL((k_hist8n<K, 16>), grid, block, 0, s, db->d_nib, db->pitch,
+                           db->d_arity, d, L.count, L.chunks, pad, tables,
+                           sweep_of(db, (const void *)k_hist8n<K, 16>, 0));
     else if (L.hk == HK_HIST8N && L.lds_bytes <= 64 * 64 * 4)
-        hipLaunchKernelGGL((k_hist8n<K, 64>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                           db->d_nib, db->pitch, db->d_arity, d, L.count, L.chunks, pad, tables);
+        hipLaunchKernelGGL((k_hist8n<K, 64>), grid, block, 0, s, db->d_nib, db->pitch,
+                           db->d_arity, d, L.count, L.chunks, pad, tables,
+                           sweep_of(db, (const void *)k_hist8n<K, 64>, 0));
     else if (L.hk == HK_HIST8N)
-        hipLaunchKernelGGL((k_hist8n<K, 256>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                           db->d_nib, db->pitch, db->d_arity, d, L.count, L.chunks, pad, tables);
-    else if (L.hk == HK_HIST16N && L.wide)
-        hipLaunchKernelGGL((k_hist16n<K, true>), dim3((unsigned)blocks), dim3(kBlock), L.lds_bytes,
-                           s, db->d_nib, db->pitch, db->d_arity, d, L.count, L.chunks,
-                           L.lds_bytes / 4, pad, tables);
+        hipLaunchKernelGGL((k_hist8n<K, 256>), grid, block, 0, s, db->d_nib, db->pitch,
+                           db->d_arity, d, L.count, L.chunks, pad, tables,
+                           sweep_of(db, (const void *)k_hist8n<K, 256>, 0));
     else if (L.hk == HK_HIST16N)
-        hipLaunchKernelGGL((k_hist16n<K, false>), dim3((unsigned)blocks), dim3(kBlock),
-                           L.lds_bytes, s, db->d_nib, db->pitch, db->d_arity, d, L.count, L.chunks,
-                           L.lds_bytes / 4, pad, tables);
+        hipLaunchKernelGGL((k_hist16n<K>), grid, block, L.lds_bytes, s, db->d_nib, db->pitch,
+                           db->d_arity, d, L.count, L.chunks, L.lds_bytes / 4, pad, tables,
+                           sweep_of(db, (const void *)k_hist16n<K>, L.lds_bytes));
     else if (L.hk == HK_HIST8 && L.lds_bytes <= 16 * 64 * 4)
-        hipLaunchKernelGGL((k_hist8<K, 16>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                           db->d_cols, db->pitch, db->d_arity, d, L.count, L.chunks, pad, tables);
+        hipLaunchKernelGGL((k_hist8<K, 16>), grid, block, 0, s, db->d_cols, db->pitch,
+                           db->d_arity, d, L.count, L.chunks, pad, tables,
+                           sweep_of(db, (const void *)k_hist8<K, 16>, 0));
     else if (L.hk == HK_HIST8 && L.lds_bytes <= 64 * 64 * 4)
-        hipLaunchKernelGGL((k_hist8<K, 64>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                           db->d_cols, db->pitch, db->d_arity, d, L.count, L.chunks, pad, tables);
+        hipLaunchKernelGGL((k_hist8<K, 64>), grid, block, 0, s, db->d_cols, db->pitch,
+                           db->d_arity, d, L.count, L.chunks, pad, tables,
+                           sweep_of(db, (const void *)k_hist8<K, 64>, 0));
     else if (L.hk == HK_HIST8)
-        hipLaunchKernelGGL((k_hist8<K, 256>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                           db->d_cols, db->pitch, db->d_arity, d, L.count, L.chunks, pad, tables);
+        hipLaunchKernelGGL((k_hist8<K, 256>), grid, block, 0, s, db->d_cols, db->pitch,
+                           db->d_arity, d, L.count, L.chunks, pad, tables,
+                           sweep_of(db, (const void *)k_hist8<K, 256>, 0));
     else if (L.hk == HK_HIST16)
-        hipLaunchKernelGGL((k_hist16<K>), dim3((unsigned)blocks), dim3(kBlock), L.lds_bytes, s,
-                           db->d_cols, db->pitch, db->d_arity, d, L.count, L.chunks,
-                           L.lds_bytes / 4, pad, tables);
+        hipLaunchKernelGGL((k_hist16<K>), grid, block, L.lds_bytes, s, db->d_cols, db->pitch,
+                           db->d_arity, d, L.count, L.chunks, L.lds_bytes / 4, pad, tables,
+                           sweep_of(db, (const void *)k_hist16<K>, L.lds_bytes));
     else if (L.small)
         hipLaunchKernelGGL((k_hist<K, true>), dim3((unsigned)blocks), dim3(kBlock), L.lds_bytes,
                            s, db->d_cols, db->pitch, db->d_arity, d, L.count, L.chunks,
@@ -2136,9 +2208,7 @@ static void set_attrs_k() {
                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
     (void)hipFuncSetAttribute((const void *)k_hist16<K>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
-    (void)hipFuncSetAttribute((const void *)k_hist16n<K, true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
-    (void)hipFuncSetAttribute((const void *)k_hist16n<K, false>,
+    (void)hipFuncSetAttribute((const void *)k_hist16n<K>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
     (void)hipFuncSetAttribute((const void *)k_bitmap<K, 1>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
@@ -2819,6 +2889,7 @@ extern "C" int fc_db_get_tuning(const fc_db *db, fc_tuning *t) {
     t->bitmap_order = db->tune.bitmap_order;
     t->derive_tables = db->tune.derive;
     t->one_pass_partition = db->tune.one_pass;
+    t->row_sweep = db->tune.row_sweep;
     return FC_OK;
 }
 
@@ -2833,9 +2904,11 @@ extern "C" int fc_db_set_tuning(fc_db *db, const fc_tuning *t) {
         (t->packed_columns != 0 && t->packed_columns != 1) ||
         (t->bitmap_order != 0 && t->bitmap_order != 1) ||
         (t->derive_tables != 0 && t->derive_tables != 1) ||
-        (t->one_pass_partition != 0 && t->one_pass_partition != 1)) {
+        (t->one_pass_partition != 0 && t->one_pass_partition != 1) ||
+        (t->row_sweep != 0 && t->row_sweep != 1)) {
         set_error("fc_db_set_tuning: chunk rows must be >= %lld, bitmap_words 1, 2 or 4, "
-                  "packed_columns, bitmap_order, derive_tables and one_pass_partition 0 or 1",
+                  "packed_columns, bitmap_order, derive_tables, one_pass_partition and "
+                  "row_sweep 0 or 1",
                   (long long)kTileRows);
         return FC_ERR_INVALID;
     }
@@ -2848,6 +2921,7 @@ extern "C" int fc_db_set_tuning(fc_db *db, const fc_tuning *t) {
     db->tune.bitmap_order = t->bitmap_order;
     db->tune.derive = t->derive_tables;
     db->tune.one_pass = t->one_pass_partition;
+    db->tune.row_sweep = t->row_sweep;
     return FC_OK;
 }
 
@@ -3070,6 +3144,16 @@ extern "C" int fc_autotune(fc_db *db, const int32_t *vars_flat, const int64_t *v
             if ((rc = tune_persistent())) return rc;
             if ((rc = sweep_chunks(0))) return rc;
         }
+    }
+    // 6. Synchronized row sweeps against every workgroup starting at its
+    //    chunk's first row.
+    {
+        const int cur = db->tune.row_sweep;
+        float ms_cur = 0.f, ms_alt = 0.f;
+        if ((rc = time_batch(db, flat, off, FC_STRAT_AUTO, tables, s, 5, ms_cur))) return rc;
+        db->tune.row_sweep = 1 - cur;
+        if ((rc = time_batch(db, flat, off, FC_STRAT_AUTO, tables, s, 5, ms_alt))) return rc;
+        db->tune.row_sweep = ms_alt < 0.97f * ms_cur ? 1 - cur : cur;
     }
     return FC_OK;
 }

@@ -47,6 +47,7 @@ struct Tuning {
     int bitmap_order = 1;               // 1: bitmap trees walk variables by ascending entropy
     int derive = 1;                     // 1: automatic plans sum tables out of supersets
     int one_pass = 1;                   // 1: one-pass partition for tables beyond LDS
+    int row_sweep = 1;                  // 1: histogram workgroups sweep their chunks in step
     // bitmap_cells[k-1][b]: bitmap for k variables and <= 2^(b+2) cells
     uint8_t bitmap_cells[FC_MAX_VARS][6] = {};
     Tuning() {
