@@ -113,6 +113,37 @@ def test_partition_one_pass_slices_and_ragged_parts():
         np.testing.assert_array_equal(t2.cpu().numpy(), T[:toff[6]])
 
 
+def test_row_sweep_rotated_starts_and_ragged_steps():
+    """Histogram workgroups start their row chunks at rotated steps (row
+    sweeps).  m = 100,003 with 16,384-row chunks gives chunks of 3 or 4
+    tiles, so the packed kernels' steps of two tiles end raggedly inside a
+    chunk; 600 queries over every LDS class give each XCD enough
+    workgroups that the starts wrap.  Tables equal the oracle with sweeps
+    on and off, and the flag accepts only 0 and 1."""
+    rng = np.random.default_rng(23)
+    m = 100_003
+    ar = np.array([2, 3, 4, 5, 6, 7, 8, 9, 3, 4, 5, 2], np.uint8)
+    D = np.stack([rng.integers(0, a, size=m) for a in ar]).astype(np.uint8)
+    qs = [rng.choice(len(ar), size=int(rng.integers(2, 7)), replace=False).astype(np.int32)
+          for _ in range(600)]
+    refs = [orc.count(D, ar, q) for q in qs]
+    print("row sweeps: m=%d queries=%d" % (m, len(qs)), flush=True)
+    with Database(D, ar) as db:
+        for sweep in (1, 0):
+            t = db.tuning()
+            t.update(row_sweep=sweep, chunk_rows=16384, derive_tables=0)
+            db.set_tuning(t)
+            tables, toff = db.count_batch(qs, strategy="hist")
+            T = tables.cpu().numpy()
+            for i, q in enumerate(qs):
+                np.testing.assert_array_equal(T[toff[i]:toff[i + 1]], refs[i],
+                                              err_msg="row_sweep=%d query %s" % (sweep, q))
+        t = db.tuning()
+        t["row_sweep"] = 2
+        with pytest.raises(_lib.FastcountError):
+            db.set_tuning(t)
+
+
 def test_partition_beyond_the_part_table_uses_key_windows():
     """62.7M cells (7 variables of arity 13) exceed the one-pass partition's
     2^25 cells: the key windows count it, equal to the oracle."""
