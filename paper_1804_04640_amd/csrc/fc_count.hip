@@ -486,8 +486,7 @@ __device__ __forceinline__ void hist16_body(const uint8_t *__restrict__ cols, in
                                             const uint8_t *__restrict__ arity, const QDesc &q,
                                             int32_t c, int32_t chunks, int32_t lds_words,
                                             int32_t pad_rows, int32_t *__restrict__ tables,
-                                            uint32_t *lds, int64_t seq,
-                                            int32_t sweep) {
+                                            uint32_t *lds, int64_t seq, int32_t sweep) {
     const int32_t cells = q.cells;
     uint32_t sb[K];
     Col colp[K];
@@ -569,8 +568,8 @@ template <int K, int B>
 __device__ __forceinline__ void hist8_body(const uint8_t *__restrict__ cols, int64_t pitch,
                                            const uint8_t *__restrict__ arity, const QDesc &q,
                                            int32_t c, int32_t chunks, int32_t pad_rows,
-                                           int32_t *__restrict__ tables, uint32_t *lds, int64_t seq,
-                                            int32_t sweep) {
+                                           int32_t *__restrict__ tables, uint32_t *lds,
+                                           int64_t seq, int32_t sweep) {
     const int32_t cells = q.cells;
     uint32_t sb[K];
     Col colp[K];
@@ -666,8 +665,8 @@ template <int K, int B>
 __device__ __forceinline__ void hist8n_body(const uint8_t *__restrict__ nib, int64_t pitch,
                                             const uint8_t *__restrict__ arity, const QDesc &q,
                                             int32_t c, int32_t chunks, int32_t pad_rows,
-                                            int32_t *__restrict__ tables, uint32_t *lds, int64_t seq,
-                                            int32_t sweep) {
+                                            int32_t *__restrict__ tables, uint32_t *lds,
+                                            int64_t seq, int32_t sweep) {
     const int32_t cells = q.cells;
     uint32_t sb[K];
     Col colp[K];
@@ -754,8 +753,7 @@ __device__ __forceinline__ void hist16n_body(const uint8_t *__restrict__ nib, in
                                              const uint8_t *__restrict__ arity, const QDesc &q,
                                              int32_t c, int32_t chunks, int32_t lds_words,
                                              int32_t pad_rows, int32_t *__restrict__ tables,
-                                             uint32_t *lds, int64_t seq,
-                                            int32_t sweep) {
+                                             uint32_t *lds, int64_t seq, int32_t sweep) {
     const int32_t cells = q.cells;
     int32_t B = lds_words / cells;
     B = B >= 64 ? 64 : B >= 32 ? 32 : B >= 16 ? 16 : B >= 8 ? 8 : B >= 4 ? 4 : B >= 2 ? 2 : 1;
