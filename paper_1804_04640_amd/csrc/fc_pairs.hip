@@ -9,10 +9,11 @@
 // which holds because one workgroup covers at most 2^24 instances.  The
 // item bit-vectors of state 1 are expanded to one nibble per instance in
 // registers, never materialised.
-//  * a workgroup of 4 waves owns a 128 x 256 block of items (the blocks
+//  * a workgroup of 4 waves owns a 128 x 128 block of items (the blocks
 //    that reach the upper triangle; the matrix is symmetric) over one range
-//    of instances (split K); each wave holds a 128 x 64 part as an 8 x 4 grid
-//    of 16x16x128 scaled-MFMA accumulators (e2m1 operands, unit scales);
+//    of instances (split K); each wave holds a 128 x 32 part as an 8 x 2 grid
+//    of 16x16x128 scaled-MFMA accumulators (e2m1 operands, unit scales),
+//    which leaves registers for four resident workgroups per CU;
 //    partial blocks are converted to int32 and summed into the output with
 //    int32 atomics;
 //  * the instances are taken 512 at a time (8 words of every item): a lane
@@ -26,7 +27,7 @@
 //    operand layout of the MFMA: bit 4k + t goes to nibble k of dword t.
 //    The 128 row items are shared by the 4 waves: each expands 2 of the 8
 //    row fragments into an LDS panel two steps ahead (four panels in
-//    rotation, one barrier per two steps); the 64 column items of a wave
+//    rotation, one barrier per two steps); the 32 column items of a wave
 //    stay in registers, expanded one step ahead;
 //  * the words of the next 512 instances load during the current ones.
 #include <algorithm>
@@ -44,9 +45,9 @@ typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int kGT = 128;  // row items per block
-constexpr int kGC = 256;  // column items per block (64 per wave)
+constexpr int kGK = 2;         // column fragments per wave
+constexpr int kGC = 4 * kGK * 16;  // column items per block (kGK * 16 per wave)
 constexpr int kGR = kGT / 16;  // row fragments
-constexpr int kGK = 4;         // column fragments per wave
 constexpr int kGS = 8;         // words per load step
 
 // 32 instance bits -> 32 e2m1 values of 0 or 1.0 (0x2): bit 4k + t of b
@@ -135,17 +136,17 @@ __global__ __launch_bounds__(256, 2) void k_gram(const uint64_t *__restrict__ bi
     const int32_t p = (int32_t)(blockIdx.x % (uint32_t)npairs);
     const int32_t sp = (int32_t)(blockIdx.x / (uint32_t)npairs);
     // pair index -> (I, J): row block I meets the upper triangle from column
-    // block I / 2 on
+    // block I * kGT / kGC on
     int32_t I = 0, rem = p;
-    while (rem >= ncb - I / 2) {
-        rem -= ncb - I / 2;
+    while (rem >= ncb - I * kGT / kGC) {
+        rem -= ncb - I * kGT / kGC;
         ++I;
     }
-    const int32_t J = I / 2 + rem;
+    const int32_t J = I * kGT / kGC + rem;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane >> 4, col = lane & 15;
-    const int32_t col0 = J * kGC + wave * 64;  // this wave's first column item
+    const int32_t col0 = J * kGC + wave * kGK * 16;  // this wave's first column item
     // a wave whose columns all lie left of the block's first row adds nothing
-    const bool active = col0 + 63 >= I * kGT;
+    const bool active = col0 + kGK * 16 - 1 >= I * kGT;
     // this lane's words 2g, 2g + 1 of every 8; padding items read row 0, masked
     const uint64_t *pa[2], *pb[kGK];
     uint4 ma[2], mb[kGK];
@@ -275,11 +276,20 @@ hipError_t launch_gram(const fc_db *db, const int32_t *rowidx, int32_t np, int32
     if (db->m == 0 || np == 0) return hipSuccess;
     const int32_t ncb = np / kGC, nrb = np / kGT;
     int32_t npairs = 0;  // (row block, column block) pairs reaching the upper triangle
-    for (int32_t I = 0; I < nrb; ++I) npairs += ncb - I / 2;
+    for (int32_t I = 0; I < nrb; ++I) npairs += ncb - I * kGT / kGC;
     const int64_t tiles = db->words / (kTileRows / 64);
-    // two workgroups per CU are resident: as many splits as fill them once,
-    // whole 64-word tiles each
-    int64_t splits = 2 * (int64_t)db->cu_count / npairs;
+    // as many splits as fill the resident workgroups once, whole 64-word
+    // tiles each
+    static const int per_cu = [] {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)k_gram, 256, 0) !=
+                hipSuccess || nb < 1) {
+            (void)hipGetLastError();
+            nb = 2;
+        }
+        return nb;
+    }();
+    int64_t splits = (int64_t)per_cu * db->cu_count / npairs;
     splits = std::min<int64_t>(splits, tiles);
     // at most 4096 tiles (2^24 instances) per workgroup keeps the fp32 sums exact
     splits = std::max<int64_t>(splits, (tiles + 4095) / 4096);
