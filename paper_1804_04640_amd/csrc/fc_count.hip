@@ -1638,15 +1638,15 @@ static int64_t derive_plan(const fc_db *db, const int32_t *vars_flat, const int6
             if (k >= 3) {
                 const uint64_t h = mix64(kv);
                 own[(size_t)t * T + part_of(h)].push_back({kv, (int32_t)i});
-                if (k <= 4) {
-                    const uint64_t b = filt_bit(h);
-                    filt[(size_t)(b >> 6)].fetch_or(1ull << (b & 63), std::memory_order_relaxed);
-                }
             }
         }
     });
     if (bad) return 0;
-    // representatives: every variable set of 3+ variables to its lowest query
+    // representatives: every variable set of 3+ variables to its lowest
+    // query; the filter bits of the sets of 3 or 4 variables are set here,
+    // by the partition's owner (a partition's keys share the hash's high
+    // bits, so its filter words are a range of their own: few contended
+    // cache lines)
     auto &m0 = W.m0;
     m0.resize((size_t)T);
     run([&](int o) {
@@ -1654,9 +1654,15 @@ static int64_t derive_plan(const fc_db *db, const int32_t *vars_flat, const int6
         for (int t = 0; t < T; ++t) n0 += own[(size_t)t * T + o].size();
         m0[(size_t)o].init(n0);
         for (int t = 0; t < T; ++t)
-            for (auto &e : own[(size_t)t * T + o])
-                m0[(size_t)o].put(e.first, mix64(e.first) >> 8, e.second,
+            for (auto &e : own[(size_t)t * T + o]) {
+                const uint64_t h = mix64(e.first);
+                m0[(size_t)o].put(e.first, h >> 8, e.second,
                                   [](int32_t a, int32_t b) { return a < b; });
+                if (e.first < (1ull << 32)) {  // 3 or 4 variables, a byte each
+                    const uint64_t b = filt_bit(h);
+                    filt[(size_t)(b >> 6)].fetch_or(1ull << (b & 63), std::memory_order_relaxed);
+                }
+            }
     });
     auto find = [&](uint64_t kv) {
         const uint64_t h = mix64(kv);
@@ -1665,35 +1671,53 @@ static int64_t derive_plan(const fc_db *db, const int32_t *vars_flat, const int6
     // the smallest superset (fewest cells, then lowest index) of every
     // represented set of 3 or 4 variables: each query of 4+ variables looks
     // its sorted 3- and 4-variable subsets up and offers itself to those
-    // that some query has
+    // that some query has.  A query's subsets that pass the filter are
+    // staged with their map slots prefetched, then probed, so the probes'
+    // memory latencies overlap.
     run([&](int t) {
         const int64_t lo = nq * t / T, hi = nq * (t + 1) / T;
+        uint64_t skb[126], hb[126];  // C(8,3) + C(8,4) subsets at most
+        int32_t rb[126];
         for (int64_t i = lo; i < hi; ++i) {
             const int k = kk[(size_t)i];
             if (k < 4) continue;
             uint8_t v[FC_MAX_VARS];
             for (int a = 0; a < k; ++a) v[a] = (uint8_t)(key[(size_t)i] >> (8 * (k - 1 - a)));
             const uint64_t mine = ((uint64_t)cells[(size_t)i] << 32) | (uint64_t)i;
-            auto offer = [&](uint64_t sk) {
+            int ns = 0;
+            auto stage = [&](uint64_t sk) {
                 const uint64_t h = mix64(sk);
                 const uint64_t bit = filt_bit(h);
                 if (!((filt[(size_t)(bit >> 6)].load(std::memory_order_relaxed) >> (bit & 63)) & 1))
                     return;
-                const int32_t r = m0[part_of(h)].get(sk, h >> 8);
-                if (r < 0) return;
-                std::atomic<uint64_t> &slot = best[(size_t)r];
-                uint64_t cur = slot.load(std::memory_order_relaxed);
-                while (mine < cur && !slot.compare_exchange_weak(cur, mine, std::memory_order_relaxed)) {
-                }
+                const SetMap &mp = m0[part_of(h)];
+                __builtin_prefetch(&mp.slots[(h >> 8) & mp.mask]);
+                skb[ns] = sk;
+                hb[ns] = h;
+                ++ns;
             };
             for (int a = 0; a < k; ++a)
                 for (int b = a + 1; b < k; ++b)
                     for (int d = b + 1; d < k; ++d) {
                         const uint64_t s3 = ((uint64_t)v[a] << 16) | ((uint64_t)v[b] << 8) | v[d];
-                        offer(s3);
+                        stage(s3);
                         if (k < 5) continue;
-                        for (int e = d + 1; e < k; ++e) offer((s3 << 8) | v[e]);
+                        for (int e = d + 1; e < k; ++e) stage((s3 << 8) | v[e]);
                     }
+            int nr = 0;
+            for (int j = 0; j < ns; ++j) {
+                const int32_t r = m0[part_of(hb[j])].get(skb[j], hb[j] >> 8);
+                if (r < 0) continue;
+                __builtin_prefetch(&best[(size_t)r]);
+                rb[nr++] = r;
+            }
+            for (int j = 0; j < nr; ++j) {
+                std::atomic<uint64_t> &slot = best[(size_t)rb[j]];
+                uint64_t cur = slot.load(std::memory_order_relaxed);
+                while (mine < cur &&
+                       !slot.compare_exchange_weak(cur, mine, std::memory_order_relaxed)) {
+                }
+            }
         }
     });
     src.assign((size_t)nq, -1);
