@@ -1564,6 +1564,7 @@ struct DeriveScratch {
     std::vector<uint64_t> key;
     std::vector<int64_t> cells;
     std::vector<uint8_t> kk;
+    std::vector<int32_t> rep;
     std::vector<std::vector<std::pair<uint64_t, int32_t>>> own;
     std::vector<SetMap> m0;
     std::unique_ptr<std::atomic<uint64_t>[]> filt{new std::atomic<uint64_t>[(size_t)1 << (kFiltBits - 6)]};
@@ -1582,6 +1583,7 @@ static int64_t derive_plan(const fc_db *db, const int32_t *vars_flat, const int6
     W.key.resize((size_t)nq);
     W.cells.resize((size_t)nq);
     W.kk.resize((size_t)nq);
+    W.rep.resize((size_t)nq);
     if (W.best_cap < (size_t)nq) {
         W.best.reset(new std::atomic<uint64_t>[(size_t)nq]);
         W.best_cap = (size_t)nq;
@@ -1589,6 +1591,7 @@ static int64_t derive_plan(const fc_db *db, const int32_t *vars_flat, const int6
     uint64_t *key = W.key.data();
     int64_t *cells = W.cells.data();
     uint8_t *kk = W.kk.data();
+    int32_t *rep = W.rep.data();  // query of 3+ variables -> its representative
     std::atomic<uint64_t> *best = W.best.get();
     // per (range, owner partition): (own key, query) of queries of 3+ variables
     auto &own = W.own;
@@ -1664,10 +1667,13 @@ static int64_t derive_plan(const fc_db *db, const int32_t *vars_flat, const int6
                 }
             }
     });
-    auto find = [&](uint64_t kv) {
-        const uint64_t h = mix64(kv);
-        return m0[part_of(h)].get(kv, h >> 8);
-    };
+    // every query of 3+ variables to its representative, looked up by the
+    // partition's owner while that map is in its thread's cache
+    run([&](int o) {
+        for (int t = 0; t < T; ++t)
+            for (auto &e : own[(size_t)t * T + o])
+                rep[(size_t)e.second] = m0[(size_t)o].get(e.first, mix64(e.first) >> 8);
+    });
     // the smallest superset (fewest cells, then lowest index) of every
     // represented set of 3 or 4 variables: each query of 4+ variables looks
     // its sorted 3- and 4-variable subsets up and offers itself to those
@@ -1738,8 +1744,7 @@ static int64_t derive_plan(const fc_db *db, const int32_t *vars_flat, const int6
             if (kk[(size_t)i] < 3 || cells[(size_t)i] > kMargMaxCells) continue;
             int32_t ch[FC_MAX_VARS + 1];
             int L = 0;
-            const int32_t r0 = find(key[(size_t)i]);
-            ch[L++] = r0 >= 0 ? r0 : (int32_t)i;
+            ch[L++] = rep[(size_t)i];
             while (L < FC_MAX_VARS + 1) {
                 const int32_t r = ch[L - 1];
                 const int kr = kk[(size_t)r];
@@ -1747,8 +1752,7 @@ static int64_t derive_plan(const fc_db *db, const int32_t *vars_flat, const int6
                                                          : ~0ull;
                 if (bu == ~0ull) break;
                 const int32_t up = (int32_t)(bu & 0xFFFFFFFFull);
-                const int32_t ru = find(key[(size_t)up]);
-                ch[L++] = ru >= 0 ? ru : up;
+                ch[L++] = rep[(size_t)up];
             }
             bool counted[FC_MAX_VARS + 1];
             counted[L - 1] = true;
