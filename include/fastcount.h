@@ -480,7 +480,10 @@ int fc_db_set_tuning(fc_db *db, const fc_tuning *t);
  * fc_count_batch) on the device with every candidate -- Bitmap against
  * histogram per (k, table-size bucket), the row-chunk sizes, then row
  * sweeps on or off -- and installs the fastest choices in the handle.
- * Synchronises `stream`.
+ * Choices that change only device work are compared by the summed
+ * event-timed durations of the batch's kernel launches, the persistent
+ * threshold and the strategy mix by wall time per batch.  Synchronises
+ * `stream`.
  */
 int fc_autotune(fc_db *db, const int32_t *vars_flat, const int64_t *var_off,
                 int64_t nq, void *stream);

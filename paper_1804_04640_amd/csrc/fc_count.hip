@@ -2956,13 +2956,27 @@ namespace fc {
 // Time per batch under the current tuning: one warm-up call, then `reps`
 // calls back to back between two events, so the host's planning of a call
 // overlaps the device work of the one before it.
+// With device = true, the time is instead the summed event-timed duration
+// of the batch's kernel launches: the measure for choices that only change
+// device work (column store, chunk sizes, row order, per-shape strategy),
+// which on a batch bound by host planning the wall time would hide.
 static int time_batch(fc_db *db, const std::vector<int32_t> &flat,
                       const std::vector<int64_t> &off, uint32_t flags, int32_t *tables,
-                      hipStream_t s, int reps, float &ms_out) {
+                      hipStream_t s, int reps, float &ms_out, bool device = false) {
     const int64_t nq = (int64_t)off.size() - 1;
     int rc = fc_count_batch(db, flat.data(), off.data(), nq, tables, nullptr, flags, s);
     if (rc) return rc;
     FC_HIP(hipStreamSynchronize(s));
+    if (device) {
+        double dev = 0.0;
+        device_time_begin(&dev);
+        for (int r = 0; r < reps && rc == FC_OK; ++r)
+            rc = fc_count_batch(db, flat.data(), off.data(), nq, tables, nullptr, flags, s);
+        device_time_end();
+        if (rc) return rc;
+        ms_out = (float)(dev / reps);
+        return FC_OK;
+    }
     hipEvent_t a, b;
     FC_HIP(hipEventCreate(&a));
     if (hipEventCreate(&b) != hipSuccess) {
@@ -3047,7 +3061,7 @@ extern "C" int fc_autotune(fc_db *db, const int32_t *vars_flat, const int64_t *v
         for (int64_t c : cand) {
             if (which == 0) db->tune.chunk_rows = c; else db->tune.bitmap_chunk_rows = c;
             float ms = 0.f;
-            r = time_batch(db, sf, so, FC_STRAT_AUTO, tables, s, 5, ms);
+            r = time_batch(db, sf, so, FC_STRAT_AUTO, tables, s, 5, ms, true);
             if (r) return r;
             if (c == cur) cur_ms = ms;
             if (ms < best_ms) {
@@ -3085,9 +3099,9 @@ extern "C" int fc_autotune(fc_db *db, const int32_t *vars_flat, const int64_t *v
     if (db->d_nib) {
         const int cur = db->tune.packed_columns;
         float ms_cur = 0.f, ms_alt = 0.f;
-        if ((rc = time_batch(db, flat, off, FC_STRAT_AUTO, tables, s, 5, ms_cur))) return rc;
+        if ((rc = time_batch(db, flat, off, FC_STRAT_AUTO, tables, s, 5, ms_cur, true))) return rc;
         db->tune.packed_columns = 1 - cur;
-        if ((rc = time_batch(db, flat, off, FC_STRAT_AUTO, tables, s, 5, ms_alt))) return rc;
+        if ((rc = time_batch(db, flat, off, FC_STRAT_AUTO, tables, s, 5, ms_alt, true))) return rc;
         db->tune.packed_columns = ms_alt < 0.97f * ms_cur ? 1 - cur : cur;
     }
     if ((rc = sweep_chunks(0))) return rc;
@@ -3122,9 +3136,9 @@ extern "C" int fc_autotune(fc_db *db, const int32_t *vars_flat, const int64_t *v
                 }
                 if (need > total) continue;  // the scratch table is sized for the sample
                 float tb = 0.f, th = 0.f;
-                if ((rc = time_batch(db, f, o, FC_STRAT_BITMAP, tables, s, 5, tb)))
+                if ((rc = time_batch(db, f, o, FC_STRAT_BITMAP, tables, s, 5, tb, true)))
                     return rc;
-                if ((rc = time_batch(db, f, o, FC_STRAT_HIST, tables, s, 5, th)))
+                if ((rc = time_batch(db, f, o, FC_STRAT_HIST, tables, s, 5, th, true)))
                     return rc;
                 // switch away from the current choice only on a clear win
                 const bool cur_bitmap = db->tune.bitmap_cells[k - 1][bkt] != 0;
@@ -3143,7 +3157,7 @@ extern "C" int fc_autotune(fc_db *db, const int32_t *vars_flat, const int64_t *v
         for (int wv : {1, 2, 4}) {
             db->tune.bitmap_words = wv;
             float ms = 0.f;
-            if ((rc = time_batch(db, flat, off, FC_STRAT_AUTO, tables, s, 5, ms)))
+            if ((rc = time_batch(db, flat, off, FC_STRAT_AUTO, tables, s, 5, ms, true)))
                 return rc;
             if (wv == curw) cur_ms = ms;
             if (ms < best_ms) {
@@ -3176,9 +3190,9 @@ extern "C" int fc_autotune(fc_db *db, const int32_t *vars_flat, const int64_t *v
     {
         const int cur = db->tune.row_sweep;
         float ms_cur = 0.f, ms_alt = 0.f;
-        if ((rc = time_batch(db, flat, off, FC_STRAT_AUTO, tables, s, 5, ms_cur))) return rc;
+        if ((rc = time_batch(db, flat, off, FC_STRAT_AUTO, tables, s, 5, ms_cur, true))) return rc;
         db->tune.row_sweep = 1 - cur;
-        if ((rc = time_batch(db, flat, off, FC_STRAT_AUTO, tables, s, 5, ms_alt))) return rc;
+        if ((rc = time_batch(db, flat, off, FC_STRAT_AUTO, tables, s, 5, ms_alt, true))) return rc;
         db->tune.row_sweep = ms_alt < 0.97f * ms_cur ? 1 - cur : cur;
     }
     return FC_OK;

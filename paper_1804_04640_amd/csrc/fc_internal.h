@@ -154,6 +154,11 @@ void workspace_release(fc_db *db, Workspace *w, hipStream_t s);
 // Launch profiling: RAII bracket of one launch with events on its stream.
 bool profiling_on();
 void set_capturing(bool on);  // this thread is recording a graph: no event brackets
+// Device time of this thread's bracketed launches: between begin and end,
+// every launch the thread brackets adds its event-timed duration (ms) to
+// *sink; end waits for them.  Independent of the per-kernel aggregates.
+void device_time_begin(double *sink);
+void device_time_end();
 struct ProfScope {
     int slot = -1;
     ProfScope(const char *name, hipStream_t s, double alg_bytes, double alg_ops);

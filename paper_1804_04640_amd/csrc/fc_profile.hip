@@ -14,6 +14,8 @@ struct Pending {
     hipEvent_t a = nullptr, b = nullptr;
     double bytes = 0, ops = 0;
     bool closed = false;
+    bool agg = false;        // counted in the per-kernel aggregates
+    double *sink = nullptr;  // device-time sum of the thread that launched it
 };
 struct Agg {
     int64_t launches = 0;
@@ -45,11 +47,14 @@ void drain() {
         if (!p.a || !p.b || !p.closed) continue;
         float ms = 0.f;
         if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
-            Agg &g = g_agg[p.name];
-            g.launches += 1;
-            g.ms += ms;
-            g.bytes += p.bytes;
-            g.ops += p.ops;
+            if (p.agg) {
+                Agg &g = g_agg[p.name];
+                g.launches += 1;
+                g.ms += ms;
+                g.bytes += p.bytes;
+                g.ops += p.ops;
+            }
+            if (p.sink) *p.sink += ms;
         } else {
             (void)hipGetLastError();
         }
@@ -61,13 +66,23 @@ void drain() {
 }  // namespace
 
 static thread_local bool t_capturing = false;
+static thread_local double *t_sink = nullptr;
 
 bool profiling_on() { return g_on.load(std::memory_order_relaxed); }
 
 void set_capturing(bool on) { t_capturing = on; }
 
+void device_time_begin(double *sink) { t_sink = sink; }
+
+void device_time_end() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    drain();
+    t_sink = nullptr;
+}
+
 ProfScope::ProfScope(const char *name, hipStream_t s, double alg_bytes, double alg_ops) {
-    if (!profiling_on() || t_capturing) return;
+    const bool agg = profiling_on();
+    if ((!agg && !t_sink) || t_capturing) return;
     std::lock_guard<std::mutex> lk(g_mu);
     if (g_pending.size() > 4096) drain();
     Pending p;
@@ -76,6 +91,8 @@ ProfScope::ProfScope(const char *name, hipStream_t s, double alg_bytes, double a
     p.b = get_event();
     p.bytes = alg_bytes;
     p.ops = alg_ops;
+    p.agg = agg;
+    p.sink = t_sink;
     if (p.a) (void)hipEventRecord(p.a, s);
     g_pending.push_back(p);
     slot = (int)g_pending.size() - 1;
