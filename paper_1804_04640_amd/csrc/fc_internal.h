@@ -171,7 +171,7 @@ int count_reduce_device(fc_db *db, const int32_t *vars_flat, const int64_t *var_
                         uint32_t reducers, double ess, float *scores, hipStream_t s);
 
 // Gram of bit-vector rows (fc_pairs.hip): C[i][j] = Count(row i AND row j)
-// for every i <= j of the np = rowidx entries (np a multiple of 256; -1 is
+// for every i <= j of the np = rowidx entries (np a multiple of 128; -1 is
 // an all-zero padding row), over all instances, on the matrix cores.  C
 // (np x np int32, leading dimension ldc) must be zero on entry; entries
 // below the diagonal are unspecified.  name/alg_bytes/alg_ops label the

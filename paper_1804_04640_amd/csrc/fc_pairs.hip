@@ -89,7 +89,7 @@ __device__ __forceinline__ Words load_words(const uint64_t *const (&pa)[2],
     return x;
 }
 
-// One step: the 8 x 4 MFMAs of the current operands (row fragments from
+// One step: the 8 x kGK MFMAs of the current operands (row fragments from
 // `cur_panel`, column fragments `b`) with expansions interleaved between the
 // MFMA rows, so a wave's VALU work overlaps its own matrix-core work: this
 // wave's row fragments of the step two ahead (words `xr`, dword HR) into
